@@ -1,0 +1,506 @@
+/*
+ * FP64 CPU oracle of the coupled lattice Boltzmann model of aqueous-humour dynamics
+ * (Qin, Meng, Yang, Zhang & Wen, "Aqueous humor dynamics in human eyes: a lattice
+ * Boltzmann study", arXiv:2102.12663).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously-correct statement of
+ * what one time step computes.  It is used by the tests, by the smoke check and by the
+ * benchmark's CPU-baseline leg, never by the product path.  It shares no code, header or
+ * constant table with the HIP library.
+ *
+ * Form: push.  Each step (1) collides every active node, then (2) streams every
+ * post-collision population to its downstream neighbour or, at a link into a non-active
+ * node, applies that link's boundary rule, then (3) swaps the buffers.  Every step is
+ * taken in the paper's order and notation:
+ *
+ *   flow     f_i(x+e_i, t+1) = f_i - (f_i - f_i^eq)/tau + F_i            (eq. 6)
+ *            f_i^eq = lambda_i p + S_i(u), lambda_{1-4}=lambda, lambda_{5-8}=gamma (eq. 7)
+ *            S_i(u) = w_i [3 e_i.u + 9/2 (e_i.u)^2 - 3/2 |u|^2]            (eq. 8)
+ *            u = sum_i e_i f_i,  p = c^2/(4 sigma) [sum_{i>=1} f_i + S_0(u)] (eq. 9)
+ *   thermal  T_i(x+e_i, t+1) = T_i - (T_i - T_i^eq)/tau_T                 (eq. 11)
+ *            T_i^eq = w^T_i T [1 + e_i.u / c_sT^2]                        (eq. 12, D2Q5)
+ *            T = sum_i T_i                                                 (eq. 13)
+ *   force    F = g beta (T - T0) (sin phi, cos phi), i.e. -g beta (T-T0) with gravity
+ *            g = |g| (-sin phi, -cos phi)                                 (eq. 15-16)
+ *            F_i = 1/2 e_i.F on the four axis links, 0 on diagonals       (eq. 17)
+ *   Darcy    in POROUS nodes the drag F_D = -(nu/K) u_D, with the mid-step
+ *            velocity u_D = (u + F_b/2) / (1 + nu/(2K)), enters as
+ *            3 w_i e_i.F_D on every link                                  (eq. 4)
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *   - sigma = 5/12, lambda = 1/3, gamma = 1/12: the unique choice with lambda_i = 3 w_i,
+ *     satisfying the constraints printed under eq. 7.
+ *   - The state is held as deviations h_i = f_i - lambda_i p_ref (i = 1..8) and
+ *     g_i = T_i - w^T_i T_ref (i = 0..4).  This is an exact affine change of variables
+ *     (sum_{i>=1} lambda_i = 4 sigma, sum_i e_i lambda_i = 0), so eq. 6-13 keep their form:
+ *     u = sum e_i h_i, p - p_ref = c^2/(4 sigma)[sum h_i + S_0(u)],
+ *     h_i^eq = lambda_i (p - p_ref) + S_i(u).  It keeps the small pressure signal from
+ *     cancelling against p_ref = 1/3.
+ *   - f_0 is not carried: it enters neither u nor p (eq. 9 sums i >= 1 and e_0 = 0).
+ *   - Thermal lattice D2Q5 with rest weight w0 and w^T_{1-4} = (1-w0)/4, c_sT^2 =
+ *     (1-w0)/2; w0 = 0 is the paper's D2Q4 exactly (eq. 11-14).
+ *   - Gravity at an angle: alpha_i = 1 on all four axis links (reduces to eq. 17 when
+ *     gravity is along y).
+ *   - Boundaries are link-wise: half-way bounce-back at SOLID, moving-wall bounce-back
+ *     at INLET (wall velocity u_in), anti-bounce-back pressure at OUTLET (p_out, the
+ *     O(u^2) term dropped).  Thermal: anti-bounce-back Dirichlet at CORNEA, IRIS and
+ *     INLET (T_cornea, T_iris, T_inlet), adiabatic bounce-back at BOX and OUTLET.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, so rounding follows
+ * the written order).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "aq_oracle.h"
+
+/* ---------------------------------------------------------------- lattice (section 2.3) */
+/* D2Q9 velocities: e_0 rest, e_1..e_4 axis, e_5..e_8 diagonal; e_2 and e_4 are the
+ * y (gravity) axis of eq. 17. */
+static const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const int opposite[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+/* eq. 8 weights */
+static double w_flow(int i) { return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0); }
+
+/* eq. 7 constants: lambda + gamma = sigma, lambda + 2 gamma = 1/2 */
+static const double sigma_ = 5.0 / 12.0;
+static double lambda_i(int i) { return i <= 4 ? 1.0 / 3.0 : 1.0 / 12.0; }
+
+static double w_heat(const or_params* P, int i) { return i == 0 ? P->w0 : (1.0 - P->w0) / 4.0; }
+
+/* eq. 8: S_i(u), c = 1 */
+static double S(int i, double ux, double uy)
+{
+    double eu = ex[i] * ux + ey[i] * uy;
+    double uu = ux * ux + uy * uy;
+    return w_flow(i) * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+}
+
+/* ---------------------------------------------------------------- state */
+struct or_state {
+    or_params P;
+    int nx, ny;
+    size_t n;
+    uint8_t* cls;
+    uint8_t* wall;
+    double* h;      /* [8][n] flow deviations, pre-collision, slot q-1 holds direction q */
+    double* g;      /* [5][n] thermal deviations, pre-collision */
+    double* hs;     /* post-collision / next buffers */
+    double* gs;
+    double* hn;
+    double* gn;
+    double* u_prev_x;
+    double* u_prev_y;
+    double* T_prev;
+    int n_walls;
+    int32_t* wall_node;
+    int32_t* wall_id;
+    double* wall_nx;
+    double* wall_ny;
+    double q_out_last, q_in_last;
+    double gx_hat, gy_hat;   /* (sin phi, cos phi): direction of the buoyant force for T > T0 */
+    int64_t step;
+    or_observables obs;
+};
+
+#define H(s, q, k) (s)->h[(size_t)((q) - 1) * (s)->n + (k)]
+#define G(s, q, k) (s)->g[(size_t)(q) * (s)->n + (k)]
+
+static int is_active(const or_state* s, size_t k) { return s->cls[k] == OR_FLUID || s->cls[k] == OR_POROUS; }
+
+/* Neighbour of node (x, y) along (dx, dy); -1 if it leaves a non-periodic lattice. */
+static long neighbour(const or_state* s, int x, int y, int dx, int dy)
+{
+    int xx = x + dx, yy = y + dy;
+    if (s->P.periodic_x) xx = (xx + s->nx) % s->nx;
+    if (s->P.periodic_y) yy = (yy + s->ny) % s->ny;
+    if (xx < 0 || xx >= s->nx || yy < 0 || yy >= s->ny) return -1;
+    return (long)yy * s->nx + xx;
+}
+
+/* ---------------------------------------------------------------- moments (eq. 9, 13) */
+typedef struct { double dp, ux, uy, T; } moments;
+
+static moments moments_of(const or_state* s, const double* h8, const double* g5)
+{
+    moments m;
+    double sum = 0.0, ux = 0.0, uy = 0.0, T = 0.0;
+    for (int i = 1; i <= 8; i++) {
+        sum += h8[i - 1];
+        ux += ex[i] * h8[i - 1];
+        uy += ey[i] * h8[i - 1];
+    }
+    m.ux = ux;
+    m.uy = uy;
+    /* p - p_ref = c^2/(4 sigma) [sum_{i>=1} h_i + S_0(u)] */
+    m.dp = (1.0 / (4.0 * sigma_)) * (sum + S(0, ux, uy));
+    for (int i = 0; i <= 4; i++) T += g5[i];
+    m.T = s->P.T_ref + T;
+    return m;
+}
+
+static void gather(const or_state* s, size_t k, double* h8, double* g5)
+{
+    for (int i = 1; i <= 8; i++) h8[i - 1] = H(s, i, k);
+    for (int i = 0; i <= 4; i++) g5[i] = G(s, i, k);
+}
+
+/* ---------------------------------------------------------------- collision (eq. 6-17) */
+static double nu_of(const or_params* P) { return (2.0 * P->tau_f - 1.0) / 6.0; }   /* eq. 10 */
+
+static void collide_node(const or_state* s, int porous, const double* h8, const double* g5,
+                         double* h8s, double* g5s)
+{
+    const or_params* P = &s->P;
+    moments m = moments_of(s, h8, g5);
+
+    /* eq. 15-16: buoyancy with the constant part absorbed into p */
+    double Bx = P->gbeta * (m.T - P->T0) * s->gx_hat;
+    double By = P->gbeta * (m.T - P->T0) * s->gy_hat;
+    double Dx = 0.0, Dy = 0.0;
+    if (porous) {
+        /* eq. 4 as a body force: Darcy drag on the mid-step velocity
+         * u_D = u + (F_b + F_D)/2 with F_D = -(nu/K) u_D, solved for u_D */
+        double nuK = nu_of(P) / P->K;
+        double uDx = (m.ux + 0.5 * Bx) / (1.0 + 0.5 * nuK);
+        double uDy = (m.uy + 0.5 * By) / (1.0 + 0.5 * nuK);
+        Dx = -nuK * uDx;
+        Dy = -nuK * uDy;
+    }
+
+    double omega = 1.0 / P->tau_f;
+    for (int i = 1; i <= 8; i++) {
+        double heq = lambda_i(i) * m.dp + S(i, m.ux, m.uy);                 /* eq. 7 */
+        /* eq. 17: buoyancy on the axis links only */
+        double Fi = (i <= 4) ? 0.5 * (ex[i] * Bx + ey[i] * By) : 0.0;
+        /* Darcy drag on all links with weights 3 w_i, which matches the linear term of
+         * eq. 8 (zero mass, momentum F_D, zero second moment, third moment F_D/3); the
+         * axis-only form is unstable once nu/K exceeds about 4 */
+        Fi += 3.0 * w_flow(i) * (ex[i] * Dx + ey[i] * Dy);
+        h8s[i - 1] = h8[i - 1] - omega * (h8[i - 1] - heq) + Fi;           /* eq. 6 */
+    }
+
+    double omegaT = 1.0 / P->tau_t;
+    double cs2T = (1.0 - P->w0) / 2.0;
+    for (int i = 0; i <= 4; i++) {
+        double eu = ex[i] * m.ux + ey[i] * m.uy;
+        double geq = w_heat(P, i) * ((m.T - P->T_ref) + m.T * eu / cs2T);  /* eq. 12 */
+        g5s[i] = g5[i] - omegaT * (g5[i] - geq);                            /* eq. 11 */
+    }
+}
+
+/* ---------------------------------------------------------------- boundaries */
+static double wall_temperature(const or_state* s, int wall)
+{
+    return wall == OR_WALL_CORNEA ? s->P.T_cornea : s->P.T_iris;
+}
+
+/* One full time step. */
+static void step_once(or_state* s)
+{
+    const or_params* P = &s->P;
+    size_t n = s->n;
+
+    /* (1) collide every active node into hs/gs */
+#pragma omp parallel for schedule(static)
+    for (size_t k = 0; k < n; k++) {
+        if (!is_active(s, k)) continue;
+        double h8[8], g5[5], h8s[8], g5s[5];
+        gather(s, k, h8, g5);
+        collide_node(s, s->cls[k] == OR_POROUS, h8, g5, h8s, g5s);
+        for (int i = 1; i <= 8; i++) s->hs[(size_t)(i - 1) * n + k] = h8s[i - 1];
+        for (int i = 0; i <= 4; i++) s->gs[(size_t)i * n + k] = g5s[i];
+    }
+
+    /* (2) stream: poison the targets so an unwritten slot shows as NaN */
+    for (size_t k = 0; k < 8 * n; k++) s->hn[k] = NAN;
+    for (size_t k = 0; k < 5 * n; k++) s->gn[k] = NAN;
+
+    double q_out = 0.0, q_in = 0.0;
+    /* every (target node, direction) slot has exactly one writer, so rows are independent */
+#pragma omp parallel for schedule(static) reduction(+ : q_out, q_in)
+    for (int y = 0; y < s->ny; y++) {
+        for (int x = 0; x < s->nx; x++) {
+            size_t k = (size_t)y * s->nx + x;
+            if (!is_active(s, k)) continue;
+            for (int i = 1; i <= 8; i++) {
+                double hout = s->hs[(size_t)(i - 1) * n + k];
+                long kk = neighbour(s, x, y, ex[i], ey[i]);
+                int c = kk < 0 ? OR_SOLID : s->cls[kk];
+                int ib = opposite[i];
+                double* back = &s->hn[(size_t)(ib - 1) * n + k];
+                if (c == OR_FLUID || c == OR_POROUS) {
+                    s->hn[(size_t)(i - 1) * n + kk] = hout;
+                } else if (c == OR_SOLID) {
+                    *back = hout;                                       /* half-way bounce-back */
+                } else if (c == OR_INLET) {
+                    double eu = ex[i] * P->u_in_x + ey[i] * P->u_in_y;
+                    *back = hout - 6.0 * w_flow(i) * eu;                /* moving wall u_in */
+                    q_in += *back - hout;
+                } else { /* OR_OUTLET */
+                    *back = -hout + 2.0 * lambda_i(i) * (P->p_out - P->p_ref); /* pressure ABB */
+                    q_out += hout - *back;
+                }
+            }
+            for (int i = 1; i <= 4; i++) {
+                double gout = s->gs[(size_t)i * n + k];
+                long kk = neighbour(s, x, y, ex[i], ey[i]);
+                int c = kk < 0 ? OR_SOLID : s->cls[kk];
+                int wall = kk < 0 ? OR_WALL_BOX : s->wall[kk];
+                int ib = opposite[i];
+                double* back = &s->gn[(size_t)ib * n + k];
+                if (c == OR_FLUID || c == OR_POROUS) {
+                    s->gn[(size_t)i * n + kk] = gout;
+                } else if ((c == OR_SOLID && wall != OR_WALL_BOX) || c == OR_INLET) {
+                    double Tw = (c == OR_INLET) ? P->T_inlet : wall_temperature(s, wall);
+                    *back = -gout + 2.0 * w_heat(P, i) * (Tw - P->T_ref);   /* Dirichlet ABB */
+                } else {
+                    *back = gout;                                           /* adiabatic */
+                }
+            }
+            s->gn[k] = s->gs[k];   /* rest population stays */
+        }
+    }
+    s->q_out_last = q_out;
+    s->q_in_last = q_in;
+
+    /* (3) swap */
+    double* t = s->h; s->h = s->hn; s->hn = t;
+    t = s->g; s->g = s->gn; s->gn = t;
+    s->step++;
+}
+
+/* ---------------------------------------------------------------- observables */
+static void observe(or_state* s)
+{
+    const or_params* P = &s->P;
+    double sum_dp = 0.0, cnt = 0.0, du2 = 0.0, u2 = 0.0, dT2 = 0.0, T2 = 0.0;
+    double mf = 0.0, mt = 0.0, umax = 0.0;
+    int64_t bad = 0;
+    for (size_t k = 0; k < s->n; k++) {
+        if (!is_active(s, k)) continue;
+        double h8[8], g5[5];
+        gather(s, k, h8, g5);
+        moments m = moments_of(s, h8, g5);
+        if (!isfinite(m.dp) || !isfinite(m.ux) || !isfinite(m.uy) || !isfinite(m.T)) bad++;
+        if (s->cls[k] == OR_FLUID) { sum_dp += m.dp; cnt += 1.0; }
+        double dx = m.ux - s->u_prev_x[k], dy = m.uy - s->u_prev_y[k];
+        du2 += dx * dx + dy * dy;
+        u2 += m.ux * m.ux + m.uy * m.uy;
+        double dT = m.T - s->T_prev[k];
+        dT2 += dT * dT;
+        T2 += (m.T - P->T_ref) * (m.T - P->T_ref);
+        double um = sqrt(m.ux * m.ux + m.uy * m.uy);
+        if (um > umax) umax = um;
+        for (int i = 0; i < 8; i++) mf += h8[i];
+        for (int i = 0; i < 5; i++) mt += g5[i];
+        s->u_prev_x[k] = m.ux;
+        s->u_prev_y[k] = m.uy;
+        s->T_prev[k] = m.T;
+    }
+
+    /* wall shear stress from the non-equilibrium stress, sigma = -(1 - 1/(2 tau)) Pi^neq */
+    double ws[3] = {0, 0, 0}, wm[3] = {0, 0, 0}, wc[3] = {0, 0, 0};
+    for (int w = 0; w < s->n_walls; w++) {
+        size_t k = (size_t)s->wall_node[w];
+        double h8[8], g5[5];
+        gather(s, k, h8, g5);
+        moments m = moments_of(s, h8, g5);
+        double pxx = 0.0, pxy = 0.0, pyy = 0.0;
+        for (int i = 1; i <= 8; i++) {
+            double neq = h8[i - 1] - (lambda_i(i) * m.dp + S(i, m.ux, m.uy));
+            pxx += ex[i] * ex[i] * neq;
+            pxy += ex[i] * ey[i] * neq;
+            pyy += ey[i] * ey[i] * neq;
+        }
+        double f = -(1.0 - 0.5 / P->tau_f);
+        double sxx = f * pxx, sxy = f * pxy, syy = f * pyy;
+        double nx_ = s->wall_nx[w], ny_ = s->wall_ny[w];
+        double tx = sxx * nx_ + sxy * ny_, ty = sxy * nx_ + syy * ny_;
+        double tn = tx * nx_ + ty * ny_;
+        double tau_w = sqrt((tx - tn * nx_) * (tx - tn * nx_) + (ty - tn * ny_) * (ty - tn * ny_));
+        int id = s->wall_id[w];
+        if (id < 1 || id > 2) continue;
+        ws[id] += tau_w;
+        wc[id] += 1.0;
+        if (tau_w > wm[id]) wm[id] = tau_w;
+    }
+
+    double D = (double)P->check_interval;
+    or_observables* o = &s->obs;
+    o->step = s->step;
+    o->p_mean_fluid = P->p_ref + (cnt > 0 ? sum_dp / cnt : 0.0);
+    o->iop_gauge = o->p_mean_fluid - P->p_out;
+    o->q_in = s->q_in_last;
+    o->q_out = s->q_out_last;
+    o->wss_cornea_mean = wc[1] > 0 ? ws[1] / wc[1] : 0.0;
+    o->wss_cornea_max = wm[1];
+    o->wss_iris_mean = wc[2] > 0 ? ws[2] / wc[2] : 0.0;
+    o->wss_iris_max = wm[2];
+    o->resid_u = u2 > 0 ? sqrt(du2) / (D * sqrt(u2)) : sqrt(du2) / D;
+    o->resid_T = T2 > 0 ? sqrt(dT2) / (D * sqrt(T2)) : sqrt(dT2) / D;
+    o->u_max = umax;
+    o->mass_flow = mf;
+    o->mass_thermal = mt;
+    o->n_nonfinite = bad;
+}
+
+static void set_prev_from_state(or_state* s)
+{
+    for (size_t k = 0; k < s->n; k++) {
+        if (!is_active(s, k)) { s->u_prev_x[k] = s->u_prev_y[k] = s->T_prev[k] = 0.0; continue; }
+        double h8[8], g5[5];
+        gather(s, k, h8, g5);
+        moments m = moments_of(s, h8, g5);
+        s->u_prev_x[k] = m.ux;
+        s->u_prev_y[k] = m.uy;
+        s->T_prev[k] = m.T;
+    }
+}
+
+/* ---------------------------------------------------------------- API */
+or_state* or_create(const or_params* P, const uint8_t* mask, int n_walls, const int32_t* wall_node,
+                    const int32_t* wall_id, const double* wall_nx, const double* wall_ny)
+{
+    if (P->nx < 3 || P->ny < 3 || P->tau_f <= 0.5 || P->tau_t <= 0.5 || P->check_interval < 1) return NULL;
+    or_state* s = (or_state*)calloc(1, sizeof(or_state));
+    s->P = *P;
+    s->gx_hat = sin(P->gravity_angle);
+    s->gy_hat = cos(P->gravity_angle);
+    s->nx = P->nx;
+    s->ny = P->ny;
+    s->n = (size_t)P->nx * P->ny;
+    size_t n = s->n;
+    s->cls = (uint8_t*)malloc(n);
+    s->wall = (uint8_t*)malloc(n);
+    for (size_t k = 0; k < n; k++) {
+        s->cls[k] = mask[k] & 7;
+        s->wall[k] = (mask[k] >> 3) & 3;
+    }
+    s->h = (double*)malloc(8 * n * sizeof(double));
+    s->hs = (double*)malloc(8 * n * sizeof(double));
+    s->hn = (double*)malloc(8 * n * sizeof(double));
+    s->g = (double*)malloc(5 * n * sizeof(double));
+    s->gs = (double*)malloc(5 * n * sizeof(double));
+    s->gn = (double*)malloc(5 * n * sizeof(double));
+    s->u_prev_x = (double*)calloc(n, sizeof(double));
+    s->u_prev_y = (double*)calloc(n, sizeof(double));
+    s->T_prev = (double*)calloc(n, sizeof(double));
+    s->n_walls = n_walls;
+    s->wall_node = (int32_t*)malloc((n_walls + 1) * sizeof(int32_t));
+    s->wall_id = (int32_t*)malloc((n_walls + 1) * sizeof(int32_t));
+    s->wall_nx = (double*)malloc((n_walls + 1) * sizeof(double));
+    s->wall_ny = (double*)malloc((n_walls + 1) * sizeof(double));
+    for (int w = 0; w < n_walls; w++) {
+        s->wall_node[w] = wall_node[w];
+        s->wall_id[w] = wall_id[w];
+        s->wall_nx[w] = wall_nx[w];
+        s->wall_ny[w] = wall_ny[w];
+    }
+
+    /* initial state: equilibrium at (p_init, u = 0, T_init), eq. 7 and eq. 12 */
+    for (size_t k = 0; k < n; k++) {
+        int act = is_active(s, k);
+        for (int i = 1; i <= 8; i++)
+            H(s, i, k) = act ? lambda_i(i) * (P->p_init - P->p_ref) + S(i, 0.0, 0.0) : NAN;
+        for (int i = 0; i <= 4; i++)
+            G(s, i, k) = act ? w_heat(P, i) * (P->T_init - P->T_ref) : NAN;
+    }
+    set_prev_from_state(s);
+    memset(&s->obs, 0, sizeof(s->obs));
+    return s;
+}
+
+void or_destroy(or_state* s)
+{
+    if (!s) return;
+    free(s->cls); free(s->wall);
+    free(s->h); free(s->hs); free(s->hn);
+    free(s->g); free(s->gs); free(s->gn);
+    free(s->u_prev_x); free(s->u_prev_y); free(s->T_prev);
+    free(s->wall_node); free(s->wall_id); free(s->wall_nx); free(s->wall_ny);
+    free(s);
+}
+
+void or_step(or_state* s, int64_t nsteps)
+{
+    for (int64_t t = 0; t < nsteps; t++) {
+        step_once(s);
+        if (s->step % s->P.check_interval == 0) observe(s);
+    }
+}
+
+int64_t or_step_count(const or_state* s) { return s->step; }
+
+void or_observables_get(const or_state* s, or_observables* out) { *out = s->obs; }
+
+/* Macroscopic fields of the current (pre-collision) state; NaN at non-active nodes. */
+void or_fields(const or_state* s, double* dp, double* ux, double* uy, double* T)
+{
+    for (size_t k = 0; k < s->n; k++) {
+        if (!is_active(s, k)) { dp[k] = ux[k] = uy[k] = T[k] = NAN; continue; }
+        double h8[8], g5[5];
+        gather(s, k, h8, g5);
+        moments m = moments_of(s, h8, g5);
+        dp[k] = m.dp;
+        ux[k] = m.ux;
+        uy[k] = m.uy;
+        T[k] = m.T;
+    }
+}
+
+void or_get_populations(const or_state* s, double* h, double* g)
+{
+    memcpy(h, s->h, 8 * s->n * sizeof(double));
+    memcpy(g, s->g, 5 * s->n * sizeof(double));
+}
+
+/* Replace the pre-collision state; values at non-active nodes are ignored (kept NaN). */
+void or_set_populations(or_state* s, const double* h, const double* g)
+{
+    for (size_t k = 0; k < s->n; k++) {
+        int act = is_active(s, k);
+        for (int q = 0; q < 8; q++) s->h[(size_t)q * s->n + k] = act ? h[(size_t)q * s->n + k] : NAN;
+        for (int q = 0; q < 5; q++) s->g[(size_t)q * s->n + k] = act ? g[(size_t)q * s->n + k] : NAN;
+    }
+    set_prev_from_state(s);
+}
+
+/* Single-node collision on caller-given populations (for unit checks). */
+void or_collide_node(const or_params* P, int porous, const double* h8, const double* g5,
+                     double* h8s, double* g5s)
+{
+    or_state s;
+    memset(&s, 0, sizeof(s));
+    s.P = *P;
+    s.gx_hat = sin(P->gravity_angle);
+    s.gy_hat = cos(P->gravity_angle);
+    collide_node(&s, porous, h8, g5, h8s, g5s);
+}
+
+/* Equilibrium populations (deviation form) for given (p, u, T). */
+void or_equilibrium(const or_params* P, double p, double ux, double uy, double T, double* h8, double* g5)
+{
+    double cs2T = (1.0 - P->w0) / 2.0;
+    for (int i = 1; i <= 8; i++) h8[i - 1] = lambda_i(i) * (p - P->p_ref) + S(i, ux, uy);
+    for (int i = 0; i <= 4; i++) {
+        double eu = ex[i] * ux + ey[i] * uy;
+        g5[i] = w_heat(P, i) * ((T - P->T_ref) + T * eu / cs2T);
+    }
+}
+
+void or_moments(const or_params* P, const double* h8, const double* g5, double* out4)
+{
+    or_state s;
+    memset(&s, 0, sizeof(s));
+    s.P = *P;
+    moments m = moments_of(&s, h8, g5);
+    out4[0] = m.dp;
+    out4[1] = m.ux;
+    out4[2] = m.uy;
+    out4[3] = m.T;
+}

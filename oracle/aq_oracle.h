@@ -1,0 +1,43 @@
+/* Oracle of the coupled lattice Boltzmann model: types and entry points.
+ * TEST INFRASTRUCTURE ONLY (tests, smoke check, CPU-baseline timing). */
+#ifndef AQ_ORACLE_H
+#define AQ_ORACLE_H
+#include <stdint.h>
+
+enum { OR_SOLID = 0, OR_FLUID = 1, OR_POROUS = 2, OR_INLET = 3, OR_OUTLET = 4 };
+enum { OR_WALL_BOX = 0, OR_WALL_CORNEA = 1, OR_WALL_IRIS = 2 };
+
+typedef struct {
+    int32_t nx, ny, periodic_x, periodic_y, check_interval, pad_;
+    double tau_f, tau_t, w0;
+    double u_in_x, u_in_y;
+    double p_ref, p_out, p_init;
+    double T_ref, T_init, T0;
+    double T_cornea, T_iris, T_inlet;
+    double gbeta, gravity_angle, K;
+} or_params;
+
+typedef struct {
+    int64_t step;
+    double iop_gauge, p_mean_fluid, q_in, q_out;
+    double wss_cornea_mean, wss_cornea_max, wss_iris_mean, wss_iris_max;
+    double resid_u, resid_T, u_max, mass_flow, mass_thermal;
+    int64_t n_nonfinite;
+} or_observables;
+
+typedef struct or_state or_state;
+
+or_state* or_create(const or_params* P, const uint8_t* mask, int n_walls, const int32_t* wall_node,
+                    const int32_t* wall_id, const double* wall_nx, const double* wall_ny);
+void or_destroy(or_state* s);
+void or_step(or_state* s, int64_t nsteps);
+int64_t or_step_count(const or_state* s);
+void or_observables_get(const or_state* s, or_observables* out);
+void or_fields(const or_state* s, double* dp, double* ux, double* uy, double* T);
+void or_get_populations(const or_state* s, double* h, double* g);
+void or_set_populations(or_state* s, const double* h, const double* g);
+void or_collide_node(const or_params* P, int porous, const double* h8, const double* g5,
+                     double* h8s, double* g5s);
+void or_equilibrium(const or_params* P, double p, double ux, double uy, double T, double* h8, double* g5);
+void or_moments(const or_params* P, const double* h8, const double* g5, double* out4);
+#endif
