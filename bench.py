@@ -1,0 +1,169 @@
+"""Benchmark of the fused collide-and-stream hot path on one MI355X.
+
+Workload: the 2048x1024 synthetic eye section (parameter-sweep draw, seed 0), FP64
+populations.  One benchmark step = one check interval: 99 plain time steps replayed
+from a HIP graph plus the reducing time step (IOP, fluxes, wall shear stress, residuals),
+i.e. every part of the per-step method.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f64|f32|f16s]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (flow+thermal) & HBM-roofline %; batched solves/s + p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+STORAGES = {"f64": 0, "f32": 1, "f16s": 2}
+DTYPE = {"f64": "f64", "f32": "f32", "f16s": "f16 storage / f32 compute"}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("aq_kernels.hip", "aq_device.h"):
+        with open(os.path.join(ROOT, "paper_2102_12663_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage, workload_key):
+    """HBM bytes per launch of the plain step kernel from the committed rocprofv3 PMC
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    e = d.get(f"{workload_key}/{storage}")
+    if not e or e.get("kernel_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(p, mask, walls, budget_s=12.0):
+    """The oracle, as it stands, on the host cores: time a bounded number of steps of the
+    same workload and convert to active MLUPS."""
+    import aqinputs as A
+    import oracle as O
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = O.Oracle(p, mask, walls)
+    o.step(1)                       # first-touch
+    t0 = time.perf_counter()
+    o.step(4)
+    dt = (time.perf_counter() - t0) / 4
+    n = max(2, int(budget_s / max(dt, 1e-6)))
+    t0 = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t0
+    act = int(A.active(mask).sum())
+    return {"value": act * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n} time steps of the same 2048x1024 lattice ({act} active nodes), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100, help="timed check intervals (100 time steps each)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--storage", default="f64", choices=sorted(STORAGES))
+    ap.add_argument("--nx", type=int, default=2048)
+    ap.add_argument("--ny", type=int, default=1024)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--tile", default="64x4")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extra-storages", action="store_true", help="also time f32 and f16s")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
+              "decomposition is design-only", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import aqinputs as A
+    import paper_2102_12663_amd as aq
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    tx, ty = (int(v) for v in args.tile.split("x"))
+
+    def run(storage_name, steps, warmup):
+        p, mask, walls, geo = A.sweep_instance(args.seed, args.nx, args.ny,
+                                               storage=STORAGES[storage_name])
+        s = aq.Solver(p, mask, walls)
+        s.set_tile(tx, ty)
+        info = s.info()
+        D = info["check_interval"]
+        if warmup:
+            s.run_intervals_timed(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        total_ms, plain_ms = s.run_intervals_timed(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ob = s.observe()
+        s.close()
+        act = info["active_nodes"]
+        mlups = act * steps * D / wall / 1e6
+        plain_launch_ms = plain_ms / (steps * (D - 1))
+        return dict(p=p, mask=mask, walls=walls, geo=geo, info=info, wall=wall, total_ms=total_ms,
+                    plain_launch_ms=plain_launch_ms, mlups=mlups, obs=ob, D=D)
+
+    r = run(args.storage, args.steps, args.warmup)
+    info, D = r["info"], r["D"]
+    act = info["active_nodes"]
+    bpu = info["bytes_per_node_update"]
+    achieved = bpu * act / (r["plain_launch_ms"] * 1e-3) / 1e9
+    workload_key = f"eye{args.nx}x{args.ny}s{args.seed}"
+    traffic = measured_traffic(args.storage, workload_key)
+    out = {
+        "metric": METRIC,
+        "value": round(r["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["wall"] * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.storage],
+        "data": "synthetic",
+        "config": {"workload": f"synthetic eye section {args.nx}x{args.ny} (sweep draw seed {args.seed}: "
+                               f"alpha {r['geo'].alpha_deg:.2f} deg, u_in {r['p'].u_in_y:.3e}), "
+                               f"{args.storage} populations, one step = {D} time steps incl. the reducing step",
+                   "nx": args.nx, "ny": args.ny, "active_nodes": act, "lattice_nodes": info["lattice_nodes"],
+                   "time_steps_per_step": D, "tile": f"{info['tile_x']}x{info['tile_y']}",
+                   "storage": args.storage, "parallelism": "single GPU"},
+        "lattice_mlups": round(info["lattice_nodes"] * args.steps * D / r["wall"] / 1e6, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": f"step_kernel<{STORAGES[args.storage]}, false>",
+                     "kernel_ms": round(r["plain_launch_ms"], 5),
+                     "bytes_per_active_node": bpu},
+        "observables": {k: r["obs"][k] for k in ("step", "iop_gauge", "q_in", "q_out", "resid_u", "u_max")},
+    }
+    if args.extra_storages:
+        extra = {}
+        for st in ("f32", "f16s"):
+            if st == args.storage:
+                continue
+            e = run(st, args.steps, args.warmup)
+            a2 = e["info"]["bytes_per_node_update"] * act / (e["plain_launch_ms"] * 1e-3) / 1e9
+            extra[st] = {"mlups": round(e["mlups"], 1), "kernel_ms": round(e["plain_launch_ms"], 5),
+                         "achieved_GBs": round(a2, 1), "frac": round(a2 / HBM_PEAK_GBS, 4)}
+        out["other_storages"] = extra
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(r["p"], r["mask"], r["walls"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,229 @@
+/*
+ * aqlbm: MI355X (gfx950) library for the coupled lattice Boltzmann model of
+ * aqueous-humour dynamics of Qin, Meng, Yang, Zhang & Wen (arXiv:2102.12663).
+ *
+ * One time step is one fused pull-stream / collide kernel over the active nodes of a 2D
+ * lattice:
+ *   - flow: incompressible D2Q9 BGK (section 2.3, eq. 6-10) with the buoyancy force of
+ *     eq. 15-17 and a Darcy drag (eq. 4) in POROUS nodes;
+ *   - heat: a D2Q5 convection-diffusion BGK (eq. 11-14; rest weight w0 = 0 is the
+ *     paper's D2Q4);
+ *   - link-wise boundaries: bounce-back walls (cornea, iris/lens floor, outer box), a
+ *     moving-wall secretion inlet, an anti-bounce-back pressure outlet, and
+ *     anti-bounce-back Dirichlet temperatures;
+ *   - every `check_interval` steps the same kernel also reduces the IOP (mean pressure of
+ *     the chamber, sections 2.2.4 and 3.1), the outflow rate (Fig. 2), the cornea and iris
+ *     wall shear stress (section 3.6) and the convergence residuals.
+ *
+ * Conventions
+ *   - Lattice units, delta_x = delta_t = c = 1.  Node (x, y) is element y*nx + x of every
+ *     host array (row-major, x fastest).
+ *   - Status codes: AQ_OK (0) or a negative AQ_E* value.  Out-parameters are written only
+ *     on AQ_OK.  aq_last_error() returns a message for the calling thread's last failure.
+ *   - Ownership: the caller owns every host array and keeps it only for the duration of
+ *     the call (the library copies what it needs).  The library owns the solver and, for
+ *     aq_create, its device memory.  With aq_create_ext the caller owns the device arena
+ *     and the HIP stream; both must outlive the solver.
+ *   - Threading: a solver handle may be used by one thread at a time.  Calls on distinct
+ *     handles are independent.
+ *   - Asynchrony: aq_step only enqueues work on the solver's stream.  aq_observe,
+ *     aq_read_field, aq_run_to_steady, aq_save and aq_write_populations synchronise it.
+ */
+#ifndef AQLBM_H
+#define AQLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    AQ_OK = 0,
+    AQ_EINVAL = -1,        /* invalid argument, parameter or mask */
+    AQ_ENOMEM = -2,        /* device or host allocation failed, or arena too small */
+    AQ_EDEVICE = -3,       /* HIP runtime error */
+    AQ_EDIVERGED = -4,     /* a non-finite moment was seen at a check step (latched) */
+    AQ_ENOTCONVERGED = -5, /* aq_run_to_steady reached max_steps */
+    AQ_EBUSY = -6,         /* no free slot or memory (serving admission) */
+    AQ_ESTATE = -7         /* call not valid in the solver's current state */
+};
+
+/* Storage precision of the populations.  F64: stored and computed in double.  F32:
+ * stored and computed in float.  F16S: stored as binary16 of (deviation * 2^s) with a
+ * per-solver power-of-two scale, computed in float.  Reductions are always double. */
+enum { AQ_F64 = 0, AQ_F32 = 1, AQ_F16S = 2 };
+
+/* Fields for aq_read_field. */
+enum {
+    AQ_FIELD_P = 0,        /* absolute pressure p (eq. 9) */
+    AQ_FIELD_UX = 1,       /* velocity x (eq. 9) */
+    AQ_FIELD_UY = 2,       /* velocity y */
+    AQ_FIELD_T = 3,        /* temperature (eq. 13) */
+    AQ_FIELD_POP_FLOW = 4, /* pre-collision flow population q = 1..8, deviation form */
+    AQ_FIELD_POP_HEAT = 5  /* pre-collision thermal population q = 0..4, deviation form */
+};
+
+/* Mask byte (input): bits 0-2 node class, bits 3-4 wall id of a SOLID node. */
+enum { AQ_SOLID = 0, AQ_FLUID = 1, AQ_POROUS = 2, AQ_INLET = 3, AQ_OUTLET = 4 };
+enum { AQ_WALL_BOX = 0, AQ_WALL_CORNEA = 1, AQ_WALL_IRIS = 2 };
+
+/*
+ * Solver parameters (lattice units).  struct_size must be sizeof(aq_params).
+ *
+ *   tau_f, tau_t      flow / thermal relaxation times, > 1/2 (eq. 6, eq. 11);
+ *                     viscosity (2 tau_f - 1)/6 (eq. 10), diffusivity
+ *                     (1 - w0)(2 tau_t - 1)/4 (eq. 14 at w0 = 0)
+ *   w0                thermal rest weight in [0, 1); the axis weights are (1 - w0)/4
+ *   u_in_x, u_in_y    velocity of the secretion inlet (moving-wall bounce-back)
+ *   p_ref             pressure about which flow populations are stored:
+ *                     h_i = f_i - lambda_i p_ref (lambda_{1-4} = 1/3, lambda_{5-8} = 1/12,
+ *                     the reading sigma = 5/12 of the constraints under eq. 7)
+ *   p_out             absolute pressure at OUTLET nodes (anti-bounce-back)
+ *   p_init, T_init    initial equilibrium state, at rest
+ *   T_ref             temperature about which thermal populations are stored:
+ *                     g_i = T_i - w^T_i T_ref
+ *   T0                Boussinesq reference temperature (eq. 5)
+ *   T_cornea, T_iris  wall temperatures of CORNEA and IRIS solids; T_inlet of INLET cells
+ *   gbeta             g*beta; buoyant force g*beta*(T - T0)*(sin phi, cos phi) (eq. 16-17)
+ *   gravity_angle     phi in radians; 0 means gravity along -y
+ *   K                 Darcy permeability of POROUS nodes (eq. 4), > 0
+ *   storage           AQ_F64, AQ_F32 or AQ_F16S
+ *   check_interval    steps between reductions; even, >= 2
+ *   fp16_exp_flow, fp16_exp_thermal
+ *                     F16S scale exponents s (values stored as deviation * 2^s);
+ *                     -1 picks them from the parameters
+ */
+typedef struct aq_params {
+    uint32_t struct_size;
+    int32_t nx, ny;
+    int32_t storage;
+    int32_t check_interval;
+    int32_t fp16_exp_flow, fp16_exp_thermal;
+    int32_t reserved0;
+    double tau_f, tau_t, w0;
+    double u_in_x, u_in_y;
+    double p_ref, p_out, p_init;
+    double T_ref, T_init, T0;
+    double T_cornea, T_iris, T_inlet;
+    double gbeta, gravity_angle, K;
+} aq_params;
+
+/* Wall-shear-stress node: an active FLUID node next to a CORNEA or IRIS solid, with the
+ * unit normal (n_x, n_y) pointing into the fluid.  Lists must be sorted by node. */
+typedef struct aq_wall_node {
+    int32_t node;   /* y*nx + x */
+    int32_t wall;   /* AQ_WALL_CORNEA or AQ_WALL_IRIS */
+    double n_x, n_y;
+} aq_wall_node;
+
+/*
+ * Observables of one check step, all in lattice units and computed from that step's
+ * pre-collision moments:
+ *   iop_gauge       mean pressure over FLUID nodes minus p_out (IOP; sections 2.2.4, 3.1)
+ *   p_mean_fluid    mean absolute pressure over FLUID nodes
+ *   q_in, q_out     flow mass entering through INLET links / leaving through OUTLET links
+ *                   during the step (outflow rate of Fig. 2)
+ *   wss_*           mean and maximum wall shear stress over the CORNEA and IRIS wall
+ *                   nodes, |t - (t.n) n| with t = sigma n and
+ *                   sigma = -(1 - 1/(2 tau_f)) sum_i e_i e_i (h_i - h_i^eq) (section 3.6)
+ *   resid_u         ||u - u_prev|| / (check_interval ||u||) over active nodes (or the
+ *                   absolute form when ||u|| = 0); resid_T the same with T - T_ref
+ *   u_max           max |u|; mass_flow = sum h, mass_thermal = sum g over active nodes
+ *   n_nonfinite     number of active nodes with a non-finite moment
+ */
+typedef struct aq_observables {
+    int64_t step;
+    double iop_gauge, p_mean_fluid, q_in, q_out;
+    double wss_cornea_mean, wss_cornea_max, wss_iris_mean, wss_iris_max;
+    double resid_u, resid_T, u_max, mass_flow, mass_thermal;
+    int64_t n_nonfinite;
+} aq_observables;
+
+/* Read-only facts about a solver. */
+typedef struct aq_info {
+    int64_t active_nodes, fluid_nodes, lattice_nodes;
+    int32_t nx, ny, pitch, storage;
+    int32_t tile_x, tile_y, n_tiles, check_interval;
+    int32_t fp16_exp_flow, fp16_exp_thermal;
+    int64_t step;
+    size_t device_bytes;
+    double bytes_per_node_update;   /* algorithmic HBM bytes per active-node update */
+} aq_info;
+
+typedef struct aq_solver aq_solver;
+
+const char* aq_version(void);
+const char* aq_last_error(void);
+
+/* Device bytes aq_create_ext needs for these parameters and mask (admission check). */
+int aq_required_bytes(const aq_params* params, const uint8_t* mask, size_t* bytes);
+
+/* Create a solver.  mask: ny*nx bytes; walls: n_walls entries (may be NULL if 0).  The
+ * state starts as the equilibrium of (p_init, u = 0, T_init).  Errors: AQ_EINVAL for
+ * tau <= 1/2, nx or ny < 4, an active node on the outer frame, unknown storage, an odd or
+ * < 2 check_interval, K <= 0, or an invalid wall list; AQ_ENOMEM; AQ_EDEVICE. */
+int aq_create(const aq_params* params, const uint8_t* mask, const aq_wall_node* walls,
+              int32_t n_walls, aq_solver** out);
+
+/* As aq_create, with device memory carved from the caller's arena (256-byte aligned,
+ * arena_bytes >= aq_required_bytes) and work enqueued on the caller's HIP stream
+ * (hipStream_t, may be NULL for the default stream). */
+int aq_create_ext(const aq_params* params, const uint8_t* mask, const aq_wall_node* walls,
+                  int32_t n_walls, void* device_arena, size_t arena_bytes, void* hip_stream,
+                  aq_solver** out);
+
+int aq_destroy(aq_solver* s);
+
+/* Enqueue nsteps time steps (eq. 6 and eq. 11 with their boundaries).  Steps whose global
+ * index is a multiple of check_interval also run the reductions.  Whole check intervals
+ * replay a captured HIP graph. */
+int aq_step(aq_solver* s, int64_t nsteps);
+
+/* Step until max(resid_u, resid_T) < tol at a check step, or max_steps.  Writes the last
+ * check step's observables.  Returns AQ_ENOTCONVERGED at the step cap and AQ_EDIVERGED on
+ * a non-finite state. */
+int aq_run_to_steady(aq_solver* s, double tol, int64_t max_steps, aq_observables* out);
+
+/* Observables of the most recent check step (step = 0 and zeros before the first). */
+int aq_observe(aq_solver* s, aq_observables* out);
+
+/* Copy a field of the current state to host (count must be nx*ny): p, u_x, u_y, T in
+ * absolute lattice units, or pre-collision population q in deviation form.  NaN at
+ * non-active nodes. */
+int aq_read_field(aq_solver* s, int32_t field, int32_t q, double* host, size_t count);
+
+/* Replace the pre-collision state by flow[8][ny][nx] (q = 1..8) and heat[5][ny][nx]
+ * (q = 0..4), deviation form; values at non-active nodes are ignored.  Also resets the
+ * residual reference to this state's moments.  count must be nx*ny. */
+int aq_write_populations(aq_solver* s, const double* flow, const double* heat, size_t count);
+
+/* Checkpoint: the stored populations (in storage precision), the residual reference and
+ * the step counter.  aq_load requires a solver created with the same parameters and mask;
+ * a resumed run is bitwise identical to an uninterrupted one. */
+int aq_save(aq_solver* s, const char* path);
+int aq_load(aq_solver* s, const char* path);
+
+int aq_get_info(aq_solver* s, aq_info* out);
+
+/* Choose the tile shape (tile_x a multiple of 64 up to 256, tile_y with
+ * tile_x * tile_y in [64, 1024]).  Rebuilds the tile list and graphs. */
+int aq_set_tile(aq_solver* s, int32_t tile_x, int32_t tile_y);
+
+/* Time n_launch back-to-back launches of the plain (non-reducing) step kernel with HIP
+ * events on the solver's stream; *ms_per_launch receives the average.  The state
+ * advances by n_launch steps (n_launch must be even). */
+int aq_time_step_kernel(aq_solver* s, int32_t n_launch, double* ms_per_launch);
+
+/* Whole-interval graph replays with HIP events around the non-reducing part of each
+ * interval: runs n_intervals * check_interval steps (the current step must be a multiple
+ * of check_interval) and returns the total elapsed milliseconds and the milliseconds
+ * spent in the check_interval - 1 plain launches of every interval. */
+int aq_run_intervals_timed(aq_solver* s, int32_t n_intervals, double* total_ms,
+                           double* plain_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AQLBM_H */

@@ -1,0 +1,255 @@
+"""MI355X (gfx950) implementation of the coupled lattice Boltzmann model of aqueous-humour
+dynamics of arXiv:2102.12663 (section 2.3): fused pull-stream/collide HIP kernels behind
+the C-ABI of include/aqlbm.h.
+
+This module only marshals arguments: every step of the method runs in the HIP library
+`libaqlbm.so`.  PyTorch supplies the device arena and the HIP stream.  If the library is
+missing, constructing a solver raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaqlbm.so")
+
+AQ_OK, AQ_EINVAL, AQ_ENOMEM, AQ_EDEVICE, AQ_EDIVERGED, AQ_ENOTCONVERGED, AQ_EBUSY, AQ_ESTATE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+F64, F32, F16S = 0, 1, 2
+FIELDS = {"p": 0, "ux": 1, "uy": 2, "T": 3, "pop_flow": 4, "pop_heat": 5}
+
+# every symbol include/aqlbm.h declares
+EXPORTS = ("aq_version", "aq_last_error", "aq_required_bytes", "aq_create", "aq_create_ext",
+           "aq_destroy", "aq_step", "aq_run_to_steady", "aq_observe", "aq_read_field",
+           "aq_write_populations", "aq_save", "aq_load", "aq_get_info", "aq_set_tile",
+           "aq_time_step_kernel", "aq_run_intervals_timed")
+
+
+class AqParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("storage", C.c_int32), ("check_interval", C.c_int32),
+                ("fp16_exp_flow", C.c_int32), ("fp16_exp_thermal", C.c_int32),
+                ("reserved0", C.c_int32)] + [(n, C.c_double) for n in (
+                    "tau_f", "tau_t", "w0", "u_in_x", "u_in_y", "p_ref", "p_out", "p_init",
+                    "T_ref", "T_init", "T0", "T_cornea", "T_iris", "T_inlet", "gbeta",
+                    "gravity_angle", "K")]
+
+
+class AqWallNode(C.Structure):
+    _fields_ = [("node", C.c_int32), ("wall", C.c_int32), ("n_x", C.c_double), ("n_y", C.c_double)]
+
+
+class AqObservables(C.Structure):
+    _fields_ = [("step", C.c_int64)] + [(n, C.c_double) for n in (
+        "iop_gauge", "p_mean_fluid", "q_in", "q_out", "wss_cornea_mean", "wss_cornea_max",
+        "wss_iris_mean", "wss_iris_max", "resid_u", "resid_T", "u_max", "mass_flow",
+        "mass_thermal")] + [("n_nonfinite", C.c_int64)]
+
+    def asdict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class AqInfo(C.Structure):
+    _fields_ = [("active_nodes", C.c_int64), ("fluid_nodes", C.c_int64), ("lattice_nodes", C.c_int64),
+                ("nx", C.c_int32), ("ny", C.c_int32), ("pitch", C.c_int32), ("storage", C.c_int32),
+                ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("n_tiles", C.c_int32),
+                ("check_interval", C.c_int32), ("fp16_exp_flow", C.c_int32),
+                ("fp16_exp_thermal", C.c_int32), ("step", C.c_int64), ("device_bytes", C.c_size_t),
+                ("bytes_per_node_update", C.c_double)]
+
+    def asdict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class AqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"aqlbm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libaqlbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is not built; run __graft_entry__.build()")
+    L = C.CDLL(path)
+    vp, sz, i32, i64, dp = C.c_void_p, C.c_size_t, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    L.aq_version.restype = C.c_char_p
+    L.aq_last_error.restype = C.c_char_p
+    L.aq_required_bytes.argtypes = [C.POINTER(AqParams), vp, C.POINTER(sz)]
+    L.aq_create.argtypes = [C.POINTER(AqParams), vp, vp, i32, C.POINTER(vp)]
+    L.aq_create_ext.argtypes = [C.POINTER(AqParams), vp, vp, i32, vp, sz, vp, C.POINTER(vp)]
+    L.aq_destroy.argtypes = [vp]
+    L.aq_step.argtypes = [vp, i64]
+    L.aq_run_to_steady.argtypes = [vp, C.c_double, i64, C.POINTER(AqObservables)]
+    L.aq_observe.argtypes = [vp, C.POINTER(AqObservables)]
+    L.aq_read_field.argtypes = [vp, i32, i32, dp, sz]
+    L.aq_write_populations.argtypes = [vp, dp, dp, sz]
+    L.aq_save.argtypes = [vp, C.c_char_p]
+    L.aq_load.argtypes = [vp, C.c_char_p]
+    L.aq_get_info.argtypes = [vp, C.POINTER(AqInfo)]
+    L.aq_set_tile.argtypes = [vp, i32, i32]
+    L.aq_time_step_kernel.argtypes = [vp, i32, dp]
+    L.aq_run_intervals_timed.argtypes = [vp, i32, dp, dp]
+    for name in EXPORTS:
+        if name not in ("aq_version", "aq_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != AQ_OK:
+        raise AqError(rc, _lib.aq_last_error().decode())
+    return rc
+
+
+def make_params(p) -> AqParams:
+    """From an aqinputs.Params-like object or dict (periodic lattices are not supported
+    by the HIP path)."""
+    d = p if isinstance(p, dict) else p.asdict()
+    if d.get("periodic_x") or d.get("periodic_y"):
+        raise ValueError("the HIP path has no periodic boundaries")
+    ap = AqParams()
+    ap.struct_size = C.sizeof(AqParams)
+    for name, _ in AqParams._fields_:
+        if name in ("struct_size", "reserved0"):
+            continue
+        setattr(ap, name, d[name])
+    return ap
+
+
+def _walls(walls):
+    if walls is None or len(walls) == 0:
+        return None, 0, None
+    arr = (AqWallNode * len(walls))()
+    for i, w in enumerate(walls):
+        arr[i].node, arr[i].wall, arr[i].n_x, arr[i].n_y = int(w["node"]), int(w["wall"]), float(w["nx"]), float(w["ny"])
+    return C.cast(arr, C.c_void_p), len(walls), arr
+
+
+class Solver:
+    """One lattice on the GPU.  Device memory is a torch uint8 arena, work runs on a
+    torch stream (default priority) owned by this object."""
+
+    def __init__(self, params, mask, walls=None, device="cuda:0", stream=None):
+        import torch
+        L = load_library()
+        self.params = params
+        self._p = make_params(params)
+        self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        self.ny, self.nx = self.mask.shape
+        if (self.nx, self.ny) != (self._p.nx, self._p.ny):
+            raise ValueError("mask shape does not match nx, ny")
+        nbytes = C.c_size_t()
+        _check(L.aq_required_bytes(C.byref(self._p), self.mask.ctypes.data, C.byref(nbytes)))
+        self.device = torch.device(device)
+        self._arena = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        base = self._arena.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        wptr, nw, self._warr = _walls(walls)
+        h = C.c_void_p()
+        torch.cuda.synchronize(self.device)
+        _check(L.aq_create_ext(C.byref(self._p), self.mask.ctypes.data, wptr, nw, C.c_void_p(aligned),
+                               nbytes.value, C.c_void_p(self._stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.aq_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # --- stepping
+    def step(self, n: int):
+        _check(_lib.aq_step(self._h, int(n)))
+        return self
+
+    def run_to_steady(self, tol: float, max_steps: int):
+        o = AqObservables()
+        rc = _lib.aq_run_to_steady(self._h, float(tol), int(max_steps), C.byref(o))
+        if rc not in (AQ_OK, AQ_ENOTCONVERGED):
+            _check(rc)
+        return rc == AQ_OK, o.asdict()
+
+    def synchronize(self):
+        self._stream.synchronize()
+
+    # --- outputs
+    def observe(self) -> dict:
+        o = AqObservables()
+        _check(_lib.aq_observe(self._h, C.byref(o)))
+        return o.asdict()
+
+    def info(self) -> dict:
+        i = AqInfo()
+        _check(_lib.aq_get_info(self._h, C.byref(i)))
+        return i.asdict()
+
+    def read_field(self, name: str, q: int = 0) -> np.ndarray:
+        out = np.empty(self.nx * self.ny)
+        _check(_lib.aq_read_field(self._h, FIELDS[name], int(q),
+                                  out.ctypes.data_as(C.POINTER(C.c_double)), out.size))
+        return out.reshape(self.ny, self.nx)
+
+    def fields(self):
+        """(p - p_ref, u_x, u_y, T) like the oracle's fields()."""
+        p = self.read_field("p") - self._p.p_ref
+        return [p, self.read_field("ux"), self.read_field("uy"), self.read_field("T")]
+
+    def populations(self):
+        h = np.stack([self.read_field("pop_flow", q) for q in range(1, 9)])
+        g = np.stack([self.read_field("pop_heat", q) for q in range(0, 5)])
+        return h, g
+
+    def write_populations(self, h, g):
+        h = np.ascontiguousarray(h, np.float64).reshape(-1)
+        g = np.ascontiguousarray(g, np.float64).reshape(-1)
+        n = self.nx * self.ny
+        assert h.size == 8 * n and g.size == 5 * n
+        _check(_lib.aq_write_populations(self._h, h.ctypes.data_as(C.POINTER(C.c_double)),
+                                         g.ctypes.data_as(C.POINTER(C.c_double)), n))
+
+    # --- tuning and timing
+    def set_tile(self, tx: int, ty: int):
+        _check(_lib.aq_set_tile(self._h, int(tx), int(ty)))
+
+    def time_step_kernel(self, n_launch: int) -> float:
+        ms = C.c_double()
+        _check(_lib.aq_time_step_kernel(self._h, int(n_launch), C.byref(ms)))
+        return ms.value
+
+    def run_intervals_timed(self, n: int):
+        tot, plain = C.c_double(), C.c_double()
+        _check(_lib.aq_run_intervals_timed(self._h, int(n), C.byref(tot), C.byref(plain)))
+        return tot.value, plain.value
+
+    def save(self, path: str):
+        _check(_lib.aq_save(self._h, path.encode()))
+
+    def load(self, path: str):
+        _check(_lib.aq_load(self._h, path.encode()))
+
+
+def version() -> str:
+    return load_library().aq_version().decode()

@@ -1,0 +1,74 @@
+// Shared declarations between the HIP kernels and the host side of the aqlbm library.
+// Internal to the library; the public interface is include/aqlbm.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aq {
+
+// Device-side node-type byte.  Bits 0-4 are the input mask byte (class, wall id); the
+// library adds the two flags below.
+enum : uint8_t {
+    CLS_MASK = 7,
+    SOLID = 0, FLUID = 1, POROUS = 2, INLET = 3, OUTLET = 4,
+    WALL_SHIFT = 3, WALL_BOX = 0, WALL_CORNEA = 1, WALL_IRIS = 2,
+    F_WSS = 1 << 5,       // active node listed in the wall-shear-stress set
+    F_BOUNDARY = 1 << 6,  // active node with at least one non-active neighbour
+};
+
+// Raw per-check-step sums written by the reducing kernel (double).
+enum {
+    R_DP_FLUID = 0, R_QOUT, R_QIN, R_WSS_C_SUM, R_WSS_C_MAX, R_WSS_I_SUM, R_WSS_I_MAX,
+    R_DU2, R_U2, R_DT2, R_T2, R_MASS_F, R_MASS_T, R_UMAX, R_NONFINITE, NRED
+};
+
+constexpr int NPOP = 13;    // 8 flow (q = 1..8) + 5 thermal (q = 0..4)
+constexpr int OBS_RING = 64;
+
+// Kernel arguments, passed by value.  Physical constants are double and converted to the
+// compute precision inside the kernel.
+struct StepArgs {
+    const void* src;          // 13 population arrays, qs elements apart
+    void* dst;
+    long long qs;             // elements between population arrays
+    const uint8_t* type;      // [ny][pitch]
+    const int* tiles;         // active tile indices (ty * tiles_x + tx)
+    int n_tiles, tiles_x, tile_x, tile_y;
+    int pitch, nx, ny, xcd_remap;
+
+    double omega_f, omega_t;  // 1/tau_f, 1/tau_t
+    double w0T, wT, inv_cs2T; // thermal weights (rest, axis) and 1/c_sT^2
+    double nuK, drag_den;     // nu/K and 1/(1 + nu/(2K))
+    double bx, by;            // g*beta*(sin phi, cos phi)
+    double dT0;               // T_ref - T0
+    double T_ref;
+    double uin_x, uin_y;      // inlet wall velocity
+    double dp_out;            // p_out - p_ref
+    double tw_cornea, tw_iris, tw_inlet;   // T_w - T_ref
+    double sf, inv_sf, st, inv_st;         // F16S scales (flow, thermal)
+
+    // reductions (check steps only)
+    double* partials;         // [gridDim][NRED]
+    unsigned int* counter;    // blocks done; reset by the last block
+    double* obs;              // [OBS_RING][NRED]
+    unsigned int* obs_count;  // check steps reduced so far
+    double* uprev;            // 3 arrays (u_x, u_y, T) of qs doubles
+    const int* wall_node;     // sorted node indices (y * pitch + x)
+    const int* wall_id;
+    const double* wall_n;     // interleaved (n_x, n_y)
+    int n_walls;
+};
+
+// Host-side launchers (defined in aq_kernels.hip).
+hipError_t launch_step(int mode, bool reduce, const StepArgs& a, hipStream_t s);
+// Write into a.dst the buffer whose pull gives the pre-collision populations `pops`
+// (dense [13][ny][nx] doubles), or, if pops is null, the rest equilibrium with
+// p - p_ref = dp0 and T - T_ref = th0.
+hipError_t launch_scatter(int mode, const StepArgs& a, const double* pops, double dp0, double th0,
+                          hipStream_t s);
+// Pull a.src and write one field (0 p, 1 u_x, 2 u_y, 3 T, 4 flow population q, 5 thermal
+// population q) to out[ny][nx]; field 6 stores the moments as the residual reference.
+hipError_t launch_unpack(int mode, const StepArgs& a, int field, int q, double p_ref, double* out,
+                         hipStream_t s);
+
+}  // namespace aq

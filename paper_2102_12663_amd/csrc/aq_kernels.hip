@@ -1,0 +1,585 @@
+// HIP kernels (gfx950) for one time step of the coupled lattice Boltzmann model of
+// arXiv:2102.12663, section 2.3.
+//
+// One launch = one time step over the active tiles.  Each thread owns one node and
+//   1. pulls its 8 flow and 5 thermal post-collision populations from the upstream
+//      neighbours (buffer src), or from its own opposite slot through the link's boundary
+//      rule when the upstream node is not active (half-way bounce-back, moving-wall inlet,
+//      anti-bounce-back pressure outlet, anti-bounce-back / adiabatic thermal walls);
+//   2. takes the moments u = sum e_i h_i, p - p_ref = 3/5 (sum h_i + S_0(u))      (eq. 9)
+//      and T = T_ref + sum g_i                                                  (eq. 13);
+//   3. forms the buoyant force g beta (T - T0)(sin phi, cos phi) (eq. 15-16) and, in
+//      porous nodes, the Darcy drag -(nu/K) u_D on the mid-step velocity          (eq. 4);
+//   4. relaxes both distributions toward their equilibria (eq. 6-8, eq. 11-12) and adds
+//      the force term (eq. 17 for buoyancy on the axis links; weights 3 w_i for the drag);
+//   5. stores the 13 post-collision values to dst at its own index (SoA, coalesced).
+// Every stored value is read exactly once in the next step, so HBM traffic per active
+// node is one read and one write of each live population plus the type byte.
+//
+// On check steps the same kernel also reduces the IOP, outlet/inlet fluxes, wall shear
+// stress, residuals, masses and max |u| in double: wavefront shuffles, one partial per
+// block, one atomic ticket per block, and the last block sums the partials in a fixed
+// order (deterministic).
+#include "aq_device.h"
+
+#include <math.h>
+
+namespace aq {
+
+// D2Q9 link directions (e_2, e_4 are the gravity axis of eq. 17) and opposites.
+__device__ constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+// Storage precision: how a population is stored and in which type it is computed.
+template <int MODE> struct Traits;
+template <> struct Traits<0> {   // AQ_F64
+    using S = double;
+    using R = double;
+    __device__ static R ld(const S* p, R) { return *p; }
+    __device__ static void st(S* p, R v, R) { *p = v; }
+};
+template <> struct Traits<1> {   // AQ_F32
+    using S = float;
+    using R = float;
+    __device__ static R ld(const S* p, R) { return *p; }
+    __device__ static void st(S* p, R v, R) { *p = v; }
+};
+template <> struct Traits<2> {   // AQ_F16S: binary16 of (deviation * 2^s)
+    using S = _Float16;
+    using R = float;
+    __device__ static R ld(const S* p, R inv) { return (R)(*p) * inv; }
+    __device__ static void st(S* p, R v, R sc) { *p = (S)(v * sc); }
+};
+
+template <typename R> struct Node {
+    R h[9];   // h[1..8] flow (h[0] unused)
+    R g[5];   // g[0..4] thermal
+    R qin, qout;
+};
+
+// Weight of link i in eq. 8 and lambda_i of eq. 7 (lambda_i = 3 w_i).
+template <typename R> __device__ __forceinline__ R wflow(int i) { return i <= 4 ? R(1.0 / 9.0) : R(1.0 / 36.0); }
+template <typename R> __device__ __forceinline__ R lam(int i) { return i <= 4 ? R(1.0 / 3.0) : R(1.0 / 12.0); }
+
+__device__ __forceinline__ bool is_active(uint8_t t)
+{
+    uint8_t c = t & CLS_MASK;
+    return c == FLUID || c == POROUS;
+}
+
+// ------------------------------------------------------------------------------ pull
+template <int MODE, int I>
+__device__ __forceinline__ void pull_flow(const StepArgs& a, const typename Traits<MODE>::S* src, int k,
+                                          bool boundary, Node<typename Traits<MODE>::R>& n)
+{
+    using T = Traits<MODE>;
+    using R = typename T::R;
+    const R inv = R(a.inv_sf);
+    const int ks = k - EY[I] * a.pitch - EX[I];
+    const typename T::S* ps = src + (long long)(I - 1) * a.qs;
+    if (!boundary) {
+        n.h[I] = T::ld(ps + ks, inv);
+        return;
+    }
+    const uint8_t c = a.type[ks] & CLS_MASK;
+    if (c == FLUID || c == POROUS) {
+        n.h[I] = T::ld(ps + ks, inv);
+        return;
+    }
+    const R v = T::ld(src + (long long)(OPP[I] - 1) * a.qs + k, inv);
+    if (c == SOLID) {
+        n.h[I] = v;                                        // half-way bounce-back
+    } else if (c == INLET) {
+        const R corr = R(6.0) * wflow<R>(I) * (R(EX[I]) * R(a.uin_x) + R(EY[I]) * R(a.uin_y));
+        n.h[I] = v + corr;                                 // moving wall at u_in
+        n.qin += corr;
+    } else {
+        const R out = -v + R(2.0) * lam<R>(I) * R(a.dp_out); // pressure anti-bounce-back
+        n.qout += v - out;
+        n.h[I] = out;
+    }
+}
+
+template <int MODE, int I>
+__device__ __forceinline__ void pull_heat(const StepArgs& a, const typename Traits<MODE>::S* src, int k,
+                                          bool boundary, Node<typename Traits<MODE>::R>& n)
+{
+    using T = Traits<MODE>;
+    using R = typename T::R;
+    const R inv = R(a.inv_st);
+    const typename T::S* base = src + 8LL * a.qs;
+    const int ks = k - EY[I] * a.pitch - EX[I];
+    if (!boundary) {
+        n.g[I] = T::ld(base + (long long)I * a.qs + ks, inv);
+        return;
+    }
+    const uint8_t t = a.type[ks];
+    const uint8_t c = t & CLS_MASK;
+    if (c == FLUID || c == POROUS) {
+        n.g[I] = T::ld(base + (long long)I * a.qs + ks, inv);
+        return;
+    }
+    const R v = T::ld(base + (long long)OPP[I] * a.qs + k, inv);
+    const uint8_t wall = (t >> WALL_SHIFT) & 3;
+    if (c == INLET || (c == SOLID && wall != WALL_BOX)) {
+        const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
+        n.g[I] = -v + R(2.0) * R(a.wT) * R(tw);          // Dirichlet anti-bounce-back
+    } else {
+        n.g[I] = v;                                        // adiabatic bounce-back
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void pull_all(const StepArgs& a, const typename Traits<MODE>::S* src, int k,
+                                         bool boundary, Node<typename Traits<MODE>::R>& n)
+{
+    using R = typename Traits<MODE>::R;
+    n.qin = R(0);
+    n.qout = R(0);
+    pull_flow<MODE, 1>(a, src, k, boundary, n);
+    pull_flow<MODE, 2>(a, src, k, boundary, n);
+    pull_flow<MODE, 3>(a, src, k, boundary, n);
+    pull_flow<MODE, 4>(a, src, k, boundary, n);
+    pull_flow<MODE, 5>(a, src, k, boundary, n);
+    pull_flow<MODE, 6>(a, src, k, boundary, n);
+    pull_flow<MODE, 7>(a, src, k, boundary, n);
+    pull_flow<MODE, 8>(a, src, k, boundary, n);
+    n.g[0] = Traits<MODE>::ld(src + 8LL * a.qs + k, R(a.inv_st));
+    pull_heat<MODE, 1>(a, src, k, boundary, n);
+    pull_heat<MODE, 2>(a, src, k, boundary, n);
+    pull_heat<MODE, 3>(a, src, k, boundary, n);
+    pull_heat<MODE, 4>(a, src, k, boundary, n);
+}
+
+// ------------------------------------------------------------------------------ moments
+template <typename R> struct Moments {
+    R sum, ux, uy, uu, dp, th;   // th = T - T_ref
+};
+
+template <typename R>
+__device__ __forceinline__ Moments<R> moments(const Node<R>& n)
+{
+    Moments<R> m;
+    const R* h = n.h;
+    m.sum = ((h[1] + h[2]) + (h[3] + h[4])) + ((h[5] + h[6]) + (h[7] + h[8]));
+    m.ux = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
+    m.uy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
+    m.uu = m.ux * m.ux + m.uy * m.uy;
+    // p - p_ref = c^2/(4 sigma) [sum h_i + S_0(u)], S_0 = -(2/3)|u|^2, sigma = 5/12
+    m.dp = R(0.6) * (m.sum - R(2.0 / 3.0) * m.uu);
+    m.th = (n.g[0] + n.g[1]) + (n.g[2] + n.g[3]) + n.g[4];
+    return m;
+}
+
+// ------------------------------------------------------------------------------ collide
+template <typename R>
+__device__ __forceinline__ void collide(const StepArgs& a, bool porous, const Node<R>& n,
+                                        const Moments<R>& m, R* hs, R* gs)
+{
+    const R om = R(a.omega_f), omc = R(1) - om;
+    // buoyancy, eq. 15-16
+    const R tm = m.th + R(a.dT0);              // T - T0
+    const R Bx = R(a.bx) * tm, By = R(a.by) * tm;
+    R Dx = R(0), Dy = R(0);
+    if (porous) {                              // Darcy drag on the mid-step velocity, eq. 4
+        const R dd = R(a.drag_den), nk = R(a.nuK);
+        Dx = -nk * ((m.ux + R(0.5) * Bx) * dd);
+        Dy = -nk * ((m.uy + R(0.5) * By) * dd);
+    }
+    const R ux = m.ux, uy = m.uy;
+    const R u15 = R(1.5) * m.uu;
+    const R w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+    const R l1 = R(1.0 / 3.0) * m.dp, l5 = R(1.0 / 12.0) * m.dp;
+    const R d3 = R(1.0 / 3.0), d12 = R(1.0 / 12.0);
+    // eq. 7-8 equilibria, eq. 6 relaxation, eq. 17 / drag force terms
+    {
+        const R eu = ux;
+        const R heq = l1 + w1 * (R(3) * eu + R(4.5) * eu * eu - u15);
+        hs[1] = omc * n.h[1] + om * heq + (R(0.5) * Bx + d3 * Dx);
+    }
+    {
+        const R eu = uy;
+        const R heq = l1 + w1 * (R(3) * eu + R(4.5) * eu * eu - u15);
+        hs[2] = omc * n.h[2] + om * heq + (R(0.5) * By + d3 * Dy);
+    }
+    {
+        const R eu = -ux;
+        const R heq = l1 + w1 * (R(3) * eu + R(4.5) * eu * eu - u15);
+        hs[3] = omc * n.h[3] + om * heq - (R(0.5) * Bx + d3 * Dx);
+    }
+    {
+        const R eu = -uy;
+        const R heq = l1 + w1 * (R(3) * eu + R(4.5) * eu * eu - u15);
+        hs[4] = omc * n.h[4] + om * heq - (R(0.5) * By + d3 * Dy);
+    }
+    {
+        const R eu = ux + uy;
+        const R heq = l5 + w5 * (R(3) * eu + R(4.5) * eu * eu - u15);
+        hs[5] = omc * n.h[5] + om * heq + d12 * (Dx + Dy);
+    }
+    {
+        const R eu = uy - ux;
+        const R heq = l5 + w5 * (R(3) * eu + R(4.5) * eu * eu - u15);
+        hs[6] = omc * n.h[6] + om * heq + d12 * (Dy - Dx);
+    }
+    {
+        const R eu = -ux - uy;
+        const R heq = l5 + w5 * (R(3) * eu + R(4.5) * eu * eu - u15);
+        hs[7] = omc * n.h[7] + om * heq - d12 * (Dx + Dy);
+    }
+    {
+        const R eu = ux - uy;
+        const R heq = l5 + w5 * (R(3) * eu + R(4.5) * eu * eu - u15);
+        hs[8] = omc * n.h[8] + om * heq + d12 * (Dx - Dy);
+    }
+    // eq. 11-12: thermal relaxation toward w_i [(T - T_ref) + T e_i.u / c_sT^2]
+    const R omT = R(a.omega_t), omTc = R(1) - omT;
+    const R T = R(a.T_ref) + m.th;
+    const R wT = R(a.wT), k2 = R(a.inv_cs2T) * T;
+    gs[0] = omTc * n.g[0] + omT * (R(a.w0T) * m.th);
+    gs[1] = omTc * n.g[1] + omT * (wT * (m.th + k2 * ux));
+    gs[2] = omTc * n.g[2] + omT * (wT * (m.th + k2 * uy));
+    gs[3] = omTc * n.g[3] + omT * (wT * (m.th - k2 * ux));
+    gs[4] = omTc * n.g[4] + omT * (wT * (m.th - k2 * uy));
+}
+
+template <int MODE>
+__device__ __forceinline__ void store_all(const StepArgs& a, typename Traits<MODE>::S* dst, int k,
+                                          const typename Traits<MODE>::R* hs,
+                                          const typename Traits<MODE>::R* gs)
+{
+    using T = Traits<MODE>;
+    using R = typename T::R;
+    const R sf = R(a.sf), st = R(a.st);
+#pragma unroll
+    for (int i = 1; i <= 8; i++) T::st(dst + (long long)(i - 1) * a.qs + k, hs[i], sf);
+#pragma unroll
+    for (int i = 0; i <= 4; i++) T::st(dst + (8LL + i) * a.qs + k, gs[i], st);
+}
+
+// ------------------------------------------------------------------------------ reduction
+__device__ __forceinline__ bool red_is_max(int j) { return j == R_WSS_C_MAX || j == R_WSS_I_MAX || j == R_UMAX; }
+
+__device__ __forceinline__ double load_coherent(const double* p)
+{
+    unsigned long long v = __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)v);
+}
+
+__device__ void block_reduce_publish(double* r, const StepArgs& a)
+{
+    __shared__ double sm[16][NRED];
+    __shared__ int last;
+#pragma unroll
+    for (int j = 0; j < NRED; j++) {
+        double v = r[j];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            double o = __shfl_xor(v, off, 64);
+            v = red_is_max(j) ? fmax(v, o) : v + o;
+        }
+        r[j] = v;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if (lane == 0)
+        for (int j = 0; j < NRED; j++) sm[w][j] = r[j];
+    __syncthreads();
+    if (threadIdx.x < NRED) {
+        const int j = threadIdx.x;
+        double acc = sm[0][j];
+        for (int q = 1; q < nw; q++) acc = red_is_max(j) ? fmax(acc, sm[q][j]) : acc + sm[q][j];
+        a.partials[(long long)blockIdx.x * NRED + j] = acc;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = (atomicAdd(a.counter, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // last block: fixed-order sum of all partials
+    const int nb = gridDim.x;
+    for (int j = 0; j < NRED; j++) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+            double v = load_coherent(a.partials + (long long)b * NRED + j);
+            acc = red_is_max(j) ? fmax(acc, v) : acc + v;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            double o = __shfl_xor(acc, off, 64);
+            acc = red_is_max(j) ? fmax(acc, o) : acc + o;
+        }
+        if (lane == 0) sm[w][j] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int c = *a.obs_count;
+        double* o = a.obs + (long long)(c % OBS_RING) * NRED;
+        for (int j = 0; j < NRED; j++) {
+            double acc = sm[0][j];
+            for (int q = 1; q < nw; q++) acc = red_is_max(j) ? fmax(acc, sm[q][j]) : acc + sm[q][j];
+            o[j] = acc;
+        }
+        *a.obs_count = c + 1;
+        *a.counter = 0;
+    }
+}
+
+// Wall-shear stress |t - (t.n) n| with t = sigma n, sigma = -(1 - omega/2) Pi^neq.
+template <typename R>
+__device__ __forceinline__ double wall_stress(const StepArgs& a, const Node<R>& n, const Moments<R>& m,
+                                              double nxw, double nyw)
+{
+    double pxx = 0, pxy = 0, pyy = 0;
+    const double ux = m.ux, uy = m.uy, uu = m.uu, dp = m.dp;
+#pragma unroll
+    for (int i = 1; i <= 8; i++) {
+        const double ex = EX[i], ey = EY[i];
+        const double eu = ex * ux + ey * uy;
+        const double w = i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0;
+        const double l = i <= 4 ? 1.0 / 3.0 : 1.0 / 12.0;
+        const double neq = (double)n.h[i] - (l * dp + w * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+        pxx += ex * ex * neq;
+        pxy += ex * ey * neq;
+        pyy += ey * ey * neq;
+    }
+    const double f = -(1.0 - 0.5 * a.omega_f);
+    const double tx = f * (pxx * nxw + pxy * nyw), ty = f * (pxy * nxw + pyy * nyw);
+    const double tn = tx * nxw + ty * nyw;
+    const double sx = tx - tn * nxw, sy = ty - tn * nyw;
+    return sqrt(sx * sx + sy * sy);
+}
+
+__device__ __forceinline__ int find_wall(const StepArgs& a, int k)
+{
+    int lo = 0, hi = a.n_walls - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int v = a.wall_node[mid];
+        if (v == k) return mid;
+        if (v < k) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+// ------------------------------------------------------------------------------ step
+__device__ __forceinline__ int tile_of_block(const StepArgs& a)
+{
+    const int G = gridDim.x, b = blockIdx.x;
+    if (!a.xcd_remap || G < 8) return b;
+    // consecutive tiles to the same XCD (blocks are dealt round-robin over 8 XCDs), so
+    // neighbouring tiles share that XCD's L2
+    const int xcd = b & 7, seq = b >> 3, q = G >> 3, r = G & 7;
+    return xcd * q + min(xcd, r) + seq;
+}
+
+template <int MODE, bool REDUCE>
+__global__ __launch_bounds__(256) void step_kernel(StepArgs a)
+{
+    using T = Traits<MODE>;
+    using R = typename T::R;
+    const int tile = a.tiles[tile_of_block(a)];
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int lx = threadIdx.x % a.tile_x, ly = threadIdx.x / a.tile_x;
+    const int x = tx * a.tile_x + lx, y = ty * a.tile_y + ly;
+    const bool inb = x < a.nx && y < a.ny;
+    const int k = y * a.pitch + x;
+    const uint8_t t = inb ? a.type[k] : (uint8_t)0;
+    const bool act = is_active(t);
+    if (!REDUCE && !act) return;
+
+    const typename T::S* src = (const typename T::S*)a.src;
+    typename T::S* dst = (typename T::S*)a.dst;
+    double r[NRED];
+    if (REDUCE) {
+#pragma unroll
+        for (int j = 0; j < NRED; j++) r[j] = 0.0;
+    }
+    if (act) {
+        Node<R> n;
+        pull_all<MODE>(a, src, k, (t & F_BOUNDARY) != 0, n);
+        const Moments<R> m = moments(n);
+        R hs[9], gs[5];
+        collide(a, (t & CLS_MASK) == POROUS, n, m, hs, gs);
+        store_all<MODE>(a, dst, k, hs, gs);
+        if (REDUCE) {
+            const double ux = m.ux, uy = m.uy, th = m.th, dp = m.dp;
+            const double Tabs = a.T_ref + th;
+            if ((t & CLS_MASK) == FLUID) r[R_DP_FLUID] = dp;
+            r[R_QOUT] = n.qout;
+            r[R_QIN] = n.qin;
+            if (t & F_WSS) {
+                const int wi = find_wall(a, k);
+                if (wi >= 0) {
+                    const double tw = wall_stress(a, n, m, a.wall_n[2 * wi], a.wall_n[2 * wi + 1]);
+                    if (a.wall_id[wi] == WALL_CORNEA) { r[R_WSS_C_SUM] = tw; r[R_WSS_C_MAX] = tw; }
+                    else { r[R_WSS_I_SUM] = tw; r[R_WSS_I_MAX] = tw; }
+                }
+            }
+            double* up = a.uprev;
+            const double pux = up[k], puy = up[a.qs + k], pT = up[2 * a.qs + k];
+            r[R_DU2] = (ux - pux) * (ux - pux) + (uy - puy) * (uy - puy);
+            r[R_U2] = ux * ux + uy * uy;
+            r[R_DT2] = (Tabs - pT) * (Tabs - pT);
+            r[R_T2] = th * th;
+            up[k] = ux;
+            up[a.qs + k] = uy;
+            up[2 * a.qs + k] = Tabs;
+            r[R_MASS_F] = m.sum;
+            r[R_MASS_T] = th;
+            r[R_UMAX] = sqrt(ux * ux + uy * uy);
+            r[R_NONFINITE] = (isfinite(dp) && isfinite(ux) && isfinite(uy) && isfinite(th)) ? 0.0 : 1.0;
+        }
+    }
+    if (REDUCE) block_reduce_publish(r, a);
+}
+
+// ------------------------------------------------------------------------------ scatter / unpack
+// The state after step N is kept as two buffers: `cur` holds the post-collision
+// populations of step N, and `prev` (the buffer step N read) pulls back to the
+// pre-collision populations F^N of step N.  To set the state to a given F (the initial
+// equilibrium, or caller-given populations) this kernel writes into `dst` the unique
+// pre-image X with pull(X) = F: every slot of X is read by exactly one link of the pull,
+// so each F_i(x) is placed either at the upstream node's slot or, for a boundary link,
+// at the node's own opposite slot with the link rule inverted.  A regular step kernel
+// from X then produces cur = collide(F).
+template <int MODE>
+__global__ __launch_bounds__(256) void scatter_kernel(StepArgs a, const double* pops, double dp0, double th0)
+{
+    using T = Traits<MODE>;
+    using R = typename T::R;
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= a.nx || y >= a.ny) return;
+    const int k = y * a.pitch + x;
+    const uint8_t t = a.type[k];
+    if (!is_active(t)) return;
+    typename T::S* X = (typename T::S*)a.dst;
+    const long long n2 = (long long)a.nx * a.ny, d = (long long)y * a.nx + x;
+    const R sf = R(a.sf), st = R(a.st);
+    // flow, q = 1..8
+    for (int i = 1; i <= 8; i++) {
+        const R f = pops ? R(pops[(i - 1) * n2 + d]) : lam<R>(i) * R(dp0);   // eq. 7 at u = 0
+        const int ks = k - EY[i] * a.pitch - EX[i];
+        const uint8_t c = a.type[ks] & CLS_MASK;
+        if (c == FLUID || c == POROUS) {
+            T::st(X + (long long)(i - 1) * a.qs + ks, f, sf);
+        } else {
+            R v;
+            if (c == SOLID) v = f;
+            else if (c == INLET) v = f - R(6.0) * wflow<R>(i) * (R(EX[i]) * R(a.uin_x) + R(EY[i]) * R(a.uin_y));
+            else v = R(2.0) * lam<R>(i) * R(a.dp_out) - f;
+            T::st(X + (long long)(OPP[i] - 1) * a.qs + k, v, sf);
+        }
+    }
+    // thermal, q = 0..4
+    const R g0 = pops ? R(pops[8 * n2 + d]) : R(a.w0T) * R(th0);              // eq. 12 at u = 0
+    T::st(X + 8LL * a.qs + k, g0, st);
+    for (int i = 1; i <= 4; i++) {
+        const R f = pops ? R(pops[(8 + i) * n2 + d]) : R(a.wT) * R(th0);
+        const int ks = k - EY[i] * a.pitch - EX[i];
+        const uint8_t tn = a.type[ks];
+        const uint8_t c = tn & CLS_MASK;
+        if (c == FLUID || c == POROUS) {
+            T::st(X + (8LL + i) * a.qs + ks, f, st);
+        } else {
+            const uint8_t wall = (tn >> WALL_SHIFT) & 3;
+            R v;
+            if (c == INLET || (c == SOLID && wall != WALL_BOX)) {
+                const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
+                v = R(2.0) * R(a.wT) * R(tw) - f;
+            } else {
+                v = f;
+            }
+            T::st(X + (8LL + OPP[i]) * a.qs + k, v, st);
+        }
+    }
+}
+
+// Fields of the current state: pull `src` (the `prev` buffer) to the pre-collision
+// populations of the current step and take their moments; NaN at non-active nodes.
+// Output is dense [ny][nx].  field 6 instead resets the residual reference (u, T).
+template <int MODE>
+__global__ __launch_bounds__(256) void unpack_kernel(StepArgs a, int field, int q, double p_ref, double* out)
+{
+    using T = Traits<MODE>;
+    using R = typename T::R;
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= a.nx || y >= a.ny) return;
+    const int k = y * a.pitch + x;
+    const long long d = (long long)y * a.nx + x;
+    const uint8_t t = a.type[k];
+    if (!is_active(t)) {
+        if (field != 6) out[d] = __builtin_nan("");
+        return;
+    }
+    Node<R> n;
+    pull_all<MODE>(a, (const typename T::S*)a.src, k, (t & F_BOUNDARY) != 0, n);
+    const Moments<R> m = moments(n);
+    if (field == 6) {
+        a.uprev[k] = m.ux;
+        a.uprev[a.qs + k] = m.uy;
+        a.uprev[2 * a.qs + k] = a.T_ref + (double)m.th;
+        return;
+    }
+    double v;
+    switch (field) {
+    case 0: v = p_ref + (double)m.dp; break;
+    case 1: v = m.ux; break;
+    case 2: v = m.uy; break;
+    case 3: v = a.T_ref + (double)m.th; break;
+    case 4: v = n.h[q < 1 ? 1 : (q > 8 ? 8 : q)]; break;
+    default: v = n.g[q < 0 ? 0 : (q > 4 ? 4 : q)]; break;
+    }
+    out[d] = v;
+}
+
+// ------------------------------------------------------------------------------ launchers
+template <int MODE>
+static hipError_t launch_step_t(bool reduce, const StepArgs& a, hipStream_t s)
+{
+    const dim3 grid(a.n_tiles), block(a.tile_x * a.tile_y);
+    if (a.n_tiles == 0) return hipSuccess;
+    if (reduce) hipLaunchKernelGGL((step_kernel<MODE, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((step_kernel<MODE, false>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(int mode, bool reduce, const StepArgs& a, hipStream_t s)
+{
+    switch (mode) {
+    case 0: return launch_step_t<0>(reduce, a, s);
+    case 1: return launch_step_t<1>(reduce, a, s);
+    case 2: return launch_step_t<2>(reduce, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+static dim3 lattice_grid(const StepArgs& a) { return dim3((a.nx + 63) / 64, (a.ny + 3) / 4); }
+
+hipError_t launch_scatter(int mode, const StepArgs& a, const double* pops, double dp0, double th0,
+                          hipStream_t s)
+{
+    switch (mode) {
+    case 0: hipLaunchKernelGGL(scatter_kernel<0>, lattice_grid(a), dim3(256), 0, s, a, pops, dp0, th0); break;
+    case 1: hipLaunchKernelGGL(scatter_kernel<1>, lattice_grid(a), dim3(256), 0, s, a, pops, dp0, th0); break;
+    case 2: hipLaunchKernelGGL(scatter_kernel<2>, lattice_grid(a), dim3(256), 0, s, a, pops, dp0, th0); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(int mode, const StepArgs& a, int field, int q, double p_ref, double* out,
+                         hipStream_t s)
+{
+    switch (mode) {
+    case 0: hipLaunchKernelGGL(unpack_kernel<0>, lattice_grid(a), dim3(256), 0, s, a, field, q, p_ref, out); break;
+    case 1: hipLaunchKernelGGL(unpack_kernel<1>, lattice_grid(a), dim3(256), 0, s, a, field, q, p_ref, out); break;
+    case 2: hipLaunchKernelGGL(unpack_kernel<2>, lattice_grid(a), dim3(256), 0, s, a, field, q, p_ref, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace aq

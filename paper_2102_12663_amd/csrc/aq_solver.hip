@@ -1,0 +1,801 @@
+// Host side of the aqlbm C-ABI (include/aqlbm.h): solver creation, device layout,
+// tile lists, HIP-graph chunks, observables and checkpoints.  No kernels live here.
+#include "aq_device.h"
+
+#include "../../include/aqlbm.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace aq;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(AQ_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t storage_size(int mode) { return mode == AQ_F64 ? 8 : (mode == AQ_F32 ? 4 : 2); }
+
+struct Layout {
+    int pitch;
+    long long qs;
+    size_t off_a, off_b, off_type, off_uprev, off_tiles, off_partials, off_counters, off_obs,
+        off_walls, off_scratch, total;
+    int max_tiles;
+};
+
+Layout make_layout(const aq_params& P, int n_walls)
+{
+    Layout L;
+    L.pitch = (int)align_up((size_t)P.nx, 64);
+    // population arrays sit 64*11 elements past a multiple of 64, so the 13 streams of a
+    // node do not start on the same DRAM channel
+    L.qs = (long long)align_up((size_t)P.ny * L.pitch, 64) + 64 * 11;
+    const size_t es = storage_size(P.storage);
+    const size_t pop_bytes = align_up((size_t)NPOP * L.qs * es, 256);
+    L.max_tiles = (int)(((P.nx + 63) / 64) * (size_t)P.ny);   // smallest tile is 64x1
+    size_t o = 0;
+    L.off_a = o; o += pop_bytes;
+    L.off_b = o; o += pop_bytes;
+    L.off_type = o; o += align_up((size_t)L.qs, 256);
+    L.off_uprev = o; o += align_up(3 * (size_t)L.qs * 8, 256);
+    L.off_tiles = o; o += align_up((size_t)L.max_tiles * 4, 256);
+    L.off_partials = o; o += align_up((size_t)L.max_tiles * NRED * 8, 256);
+    L.off_counters = o; o += 256;
+    L.off_obs = o; o += align_up((size_t)OBS_RING * NRED * 8, 256);
+    L.off_walls = o; o += align_up((size_t)std::max(n_walls, 1) * (4 + 4 + 16), 256);
+    L.off_scratch = o; o += align_up((size_t)P.nx * P.ny * 8, 256);
+    L.total = o;
+    return L;
+}
+
+double bytes_per_update(int mode) { return 2.0 * NPOP * storage_size(mode) + 1.0; }
+
+}  // namespace
+
+struct aq_solver {
+    aq_params P;
+    Layout L;
+    int mode;
+    char* base = nullptr;
+    bool own_mem = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+
+    std::vector<uint8_t> htype;   // [ny][pitch]
+    int64_t n_active = 0, n_fluid = 0, n_cornea = 0, n_iris = 0;
+    std::vector<int> hwall_node, hwall_id;
+    std::vector<double> hwall_n;
+    int n_walls = 0;
+
+    int tile_x = 64, tile_y = 4, tiles_x = 0, n_tiles = 0, xcd_remap = 1;
+    int cur = 0;                  // 0: buffer A holds the state
+    int64_t step = 0;
+    unsigned int checks = 0;      // reducing launches enqueued
+    int64_t last_check_step = 0;
+    bool diverged = false;
+    double sf = 1, st = 1;        // F16S scales
+    int exp_f = 0, exp_t = 0;
+
+    hipGraphExec_t plain_graph = nullptr;
+    hipGraph_t plain_graph_src = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* obs_pinned = nullptr; // host pinned, 2 * NRED
+
+    void* popA() const { return base + L.off_a; }
+    void* popB() const { return base + L.off_b; }
+};
+
+namespace {
+
+StepArgs make_args(const aq_solver* s, bool a_is_src)
+{
+    const aq_params& P = s->P;
+    StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.src = a_is_src ? s->popA() : s->popB();
+    a.dst = a_is_src ? s->popB() : s->popA();
+    a.qs = s->L.qs;
+    a.type = (const uint8_t*)(s->base + s->L.off_type);
+    a.tiles = (const int*)(s->base + s->L.off_tiles);
+    a.n_tiles = s->n_tiles;
+    a.tiles_x = s->tiles_x;
+    a.tile_x = s->tile_x;
+    a.tile_y = s->tile_y;
+    a.pitch = s->L.pitch;
+    a.nx = P.nx;
+    a.ny = P.ny;
+    a.xcd_remap = s->xcd_remap;
+    a.omega_f = 1.0 / P.tau_f;
+    a.omega_t = 1.0 / P.tau_t;
+    a.w0T = P.w0;
+    a.wT = (1.0 - P.w0) / 4.0;
+    a.inv_cs2T = 2.0 / (1.0 - P.w0);
+    const double nu = (2.0 * P.tau_f - 1.0) / 6.0;   // eq. 10
+    a.nuK = nu / P.K;
+    a.drag_den = 1.0 / (1.0 + 0.5 * a.nuK);
+    a.bx = P.gbeta * std::sin(P.gravity_angle);
+    a.by = P.gbeta * std::cos(P.gravity_angle);
+    a.dT0 = P.T_ref - P.T0;
+    a.T_ref = P.T_ref;
+    a.uin_x = P.u_in_x;
+    a.uin_y = P.u_in_y;
+    a.dp_out = P.p_out - P.p_ref;
+    a.tw_cornea = P.T_cornea - P.T_ref;
+    a.tw_iris = P.T_iris - P.T_ref;
+    a.tw_inlet = P.T_inlet - P.T_ref;
+    a.sf = s->sf;
+    a.inv_sf = 1.0 / s->sf;
+    a.st = s->st;
+    a.inv_st = 1.0 / s->st;
+    char* b = s->base;
+    a.partials = (double*)(b + s->L.off_partials);
+    a.counter = (unsigned int*)(b + s->L.off_counters);
+    a.obs_count = (unsigned int*)(b + s->L.off_counters + 64);
+    a.obs = (double*)(b + s->L.off_obs);
+    a.uprev = (double*)(b + s->L.off_uprev);
+    a.wall_node = (const int*)(b + s->L.off_walls);
+    a.wall_id = (const int*)(b + s->L.off_walls + 4 * (size_t)std::max(s->n_walls, 1));
+    a.wall_n = (const double*)(b + s->L.off_walls + 8 * (size_t)std::max(s->n_walls, 1));
+    a.n_walls = s->n_walls;
+    return a;
+}
+
+int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls)
+{
+    if (!P || !mask) return fail(AQ_EINVAL, "null params or mask");
+    if (P->struct_size != sizeof(aq_params)) return fail(AQ_EINVAL, "aq_params.struct_size mismatch");
+    if (P->nx < 4 || P->ny < 4) return fail(AQ_EINVAL, "nx and ny must be >= 4");
+    if ((long long)P->nx * P->ny > (1LL << 30)) return fail(AQ_EINVAL, "lattice too large");
+    if (!(P->tau_f > 0.5) || !(P->tau_t > 0.5)) return fail(AQ_EINVAL, "tau_f and tau_t must exceed 1/2");
+    if (!(P->w0 >= 0.0 && P->w0 < 1.0)) return fail(AQ_EINVAL, "w0 must be in [0, 1)");
+    if (!(P->K > 0.0)) return fail(AQ_EINVAL, "K must be positive");
+    if (P->storage < AQ_F64 || P->storage > AQ_F16S) return fail(AQ_EINVAL, "unknown storage");
+    if (P->check_interval < 2 || (P->check_interval & 1)) return fail(AQ_EINVAL, "check_interval must be even and >= 2");
+    if (P->fp16_exp_flow < -1 || P->fp16_exp_flow > 40 || P->fp16_exp_thermal < -1 || P->fp16_exp_thermal > 40)
+        return fail(AQ_EINVAL, "fp16 exponents must be in [-1, 40]");
+    const int nx = P->nx, ny = P->ny;
+    for (int y = 0; y < ny; y++)
+        for (int x = 0; x < nx; x++) {
+            const uint8_t m = mask[(size_t)y * nx + x];
+            const int c = m & 7;
+            if (c > AQ_OUTLET || (m >> 5)) return fail(AQ_EINVAL, "invalid mask byte");
+            const bool act = c == AQ_FLUID || c == AQ_POROUS;
+            if (act && (x == 0 || y == 0 || x == nx - 1 || y == ny - 1))
+                return fail(AQ_EINVAL, "active node on the outer frame");
+        }
+    if (n_walls < 0 || (n_walls > 0 && !walls)) return fail(AQ_EINVAL, "invalid wall list");
+    for (int w = 0; w < n_walls; w++) {
+        const int k = walls[w].node;
+        if (k < 0 || (long long)k >= (long long)nx * ny) return fail(AQ_EINVAL, "wall node out of range");
+        if ((mask[k] & 7) != AQ_FLUID) return fail(AQ_EINVAL, "wall node is not FLUID");
+        if (walls[w].wall != AQ_WALL_CORNEA && walls[w].wall != AQ_WALL_IRIS) return fail(AQ_EINVAL, "wall id must be CORNEA or IRIS");
+        if (w > 0 && walls[w - 1].node >= k) return fail(AQ_EINVAL, "wall list must be sorted by node, without repeats");
+        if (!std::isfinite(walls[w].n_x) || !std::isfinite(walls[w].n_y)) return fail(AQ_EINVAL, "non-finite wall normal");
+    }
+    return AQ_OK;
+}
+
+// Power-of-two scales for F16S storage: largest s with the expected deviation magnitude
+// times 2^s at most 1/4 (see the design notes); clamp to [0, 24].
+int auto_exp(double dmax)
+{
+    if (!(dmax > 0)) return 0;
+    int s = (int)std::floor(std::log2(0.25 / dmax));
+    return std::max(0, std::min(24, s));
+}
+
+void choose_scales(aq_solver* s)
+{
+    const aq_params& P = s->P;
+    const double dT = std::max({std::fabs(P.T_cornea - P.T0), std::fabs(P.T_iris - P.T0),
+                                std::fabs(P.T_inlet - P.T0), std::fabs(P.T_init - P.T0), 1e-30});
+    const double L = std::max(P.nx, P.ny);
+    const double ub = std::sqrt(std::fabs(P.gbeta) * dT * L);
+    const double us = std::max({std::fabs(P.u_in_x), std::fabs(P.u_in_y), ub, 1e-12});
+    const double dps = std::fabs(P.gbeta) * dT * L + std::fabs(P.p_out - P.p_ref) + std::fabs(P.p_init - P.p_ref);
+    const double dflow = (3.0 * us + dps) / 3.0;
+    const double dTr = std::max({std::fabs(P.T_cornea - P.T_ref), std::fabs(P.T_iris - P.T_ref),
+                                 std::fabs(P.T_inlet - P.T_ref), std::fabs(P.T_init - P.T_ref), 1e-30});
+    const double dtherm = 0.5 * dTr * (1.0 + 2.0 * us / (1.0 - P.w0)) + 1e-30;
+    s->exp_f = P.fp16_exp_flow >= 0 ? P.fp16_exp_flow : auto_exp(dflow);
+    s->exp_t = P.fp16_exp_thermal >= 0 ? P.fp16_exp_thermal : auto_exp(dtherm);
+    if (P.storage == AQ_F16S) {
+        s->sf = std::ldexp(1.0, s->exp_f);
+        s->st = std::ldexp(1.0, s->exp_t);
+    } else {
+        s->sf = s->st = 1.0;
+        s->exp_f = s->exp_t = 0;
+    }
+}
+
+void build_tiles(aq_solver* s, std::vector<int>& tiles)
+{
+    const int nx = s->P.nx, ny = s->P.ny, pitch = s->L.pitch;
+    s->tiles_x = (nx + s->tile_x - 1) / s->tile_x;
+    const int tiles_y = (ny + s->tile_y - 1) / s->tile_y;
+    tiles.clear();
+    for (int ty = 0; ty < tiles_y; ty++)
+        for (int tx = 0; tx < s->tiles_x; tx++) {
+            bool any = false;
+            for (int y = ty * s->tile_y; y < std::min(ny, (ty + 1) * s->tile_y) && !any; y++)
+                for (int x = tx * s->tile_x; x < std::min(nx, (tx + 1) * s->tile_x); x++) {
+                    const int c = s->htype[(size_t)y * pitch + x] & CLS_MASK;
+                    if (c == FLUID || c == POROUS) { any = true; break; }
+                }
+            if (any) tiles.push_back(ty * s->tiles_x + tx);
+        }
+    s->n_tiles = (int)tiles.size();
+}
+
+int upload_tiles(aq_solver* s)
+{
+    std::vector<int> tiles;
+    build_tiles(s, tiles);
+    if (s->n_tiles > s->L.max_tiles) return fail(AQ_EINVAL, "tile list overflow");
+    if (s->n_tiles)
+        HIPCHK(hipMemcpyAsync(s->base + s->L.off_tiles, tiles.data(), tiles.size() * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return AQ_OK;
+}
+
+void drop_graph(aq_solver* s)
+{
+    if (s->plain_graph) (void)hipGraphExecDestroy(s->plain_graph);
+    if (s->plain_graph_src) (void)hipGraphDestroy(s->plain_graph_src);
+    s->plain_graph = nullptr;
+    s->plain_graph_src = nullptr;
+}
+
+// Capture the check_interval - 1 non-reducing steps of an interval (starting from
+// buffer A) as one graph.
+int ensure_graph(aq_solver* s)
+{
+    if (s->plain_graph) return AQ_OK;
+    const int n = s->P.check_interval - 1;
+    HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    bool a_src = true;
+    hipError_t err = hipSuccess;
+    for (int i = 0; i < n && err == hipSuccess; i++) {
+        StepArgs a = make_args(s, a_src);
+        err = launch_step(s->mode, false, a, s->stream);
+        a_src = !a_src;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s->stream, &g);
+    if (err != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(AQ_EDEVICE, std::string("capture launch: ") + hipGetErrorString(err));
+    }
+    if (e2 != hipSuccess) return fail(AQ_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+    hipGraphExec_t ge = nullptr;
+    hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(AQ_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+    }
+    s->plain_graph_src = g;
+    s->plain_graph = ge;
+    return AQ_OK;
+}
+
+int launch_one(aq_solver* s)
+{
+    const bool reduce = ((s->step + 1) % s->P.check_interval) == 0;
+    StepArgs a = make_args(s, s->cur == 0);
+    HIPCHK(launch_step(s->mode, reduce, a, s->stream));
+    s->cur ^= 1;
+    s->step++;
+    if (reduce) {
+        s->checks++;
+        s->last_check_step = s->step;
+    }
+    return AQ_OK;
+}
+
+void raw_to_obs(const aq_solver* s, const double* r, int64_t step, aq_observables* o)
+{
+    const aq_params& P = s->P;
+    std::memset(o, 0, sizeof(*o));
+    o->step = step;
+    o->p_mean_fluid = P.p_ref + (s->n_fluid > 0 ? r[R_DP_FLUID] / (double)s->n_fluid : 0.0);
+    o->iop_gauge = o->p_mean_fluid - P.p_out;
+    o->q_in = r[R_QIN];
+    o->q_out = r[R_QOUT];
+    o->wss_cornea_mean = s->n_cornea ? r[R_WSS_C_SUM] / (double)s->n_cornea : 0.0;
+    o->wss_cornea_max = r[R_WSS_C_MAX];
+    o->wss_iris_mean = s->n_iris ? r[R_WSS_I_SUM] / (double)s->n_iris : 0.0;
+    o->wss_iris_max = r[R_WSS_I_MAX];
+    const double D = (double)P.check_interval;
+    o->resid_u = r[R_U2] > 0 ? std::sqrt(r[R_DU2]) / (D * std::sqrt(r[R_U2])) : std::sqrt(r[R_DU2]) / D;
+    o->resid_T = r[R_T2] > 0 ? std::sqrt(r[R_DT2]) / (D * std::sqrt(r[R_T2])) : std::sqrt(r[R_DT2]) / D;
+    o->u_max = r[R_UMAX];
+    o->mass_flow = r[R_MASS_F];
+    o->mass_thermal = r[R_MASS_T];
+    o->n_nonfinite = (int64_t)r[R_NONFINITE];
+}
+
+// Read the raw sums of reduction number `idx` (0-based) after the stream has passed it.
+int read_raw(aq_solver* s, unsigned int idx, double* raw)
+{
+    const double* src = (const double*)(s->base + s->L.off_obs) + (size_t)(idx % OBS_RING) * NRED;
+    HIPCHK(hipMemcpyAsync(s->obs_pinned, src, NRED * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    std::memcpy(raw, s->obs_pinned, NRED * 8);
+    return AQ_OK;
+}
+
+// Set the current pre-collision state to `pops` (device, dense [13][ny][nx]) or, if
+// null, to the rest equilibrium of (p_init, T_init): scatter its pre-image into the
+// `prev` buffer, collide it into `cur` with one regular step launch, and reset the
+// residual reference to its moments.  The step counter and buffer parity are unchanged.
+int set_state(aq_solver* s, const double* pops)
+{
+    const bool prev_is_b = s->cur == 0;
+    StepArgs sc = make_args(s, prev_is_b);         // dst = prev
+    HIPCHK(launch_scatter(s->mode, sc, pops, s->P.p_init - s->P.p_ref, s->P.T_init - s->P.T_ref, s->stream));
+    StepArgs st = make_args(s, !prev_is_b);        // src = prev, dst = cur
+    HIPCHK(launch_step(s->mode, false, st, s->stream));
+    HIPCHK(launch_unpack(s->mode, st, 6, 0, s->P.p_ref, nullptr, s->stream));
+    return AQ_OK;
+}
+
+int init_state(aq_solver* s)
+{
+    s->cur = 0;
+    s->step = 0;
+    s->checks = 0;
+    s->last_check_step = 0;
+    s->diverged = false;
+    HIPCHK(hipMemsetAsync(s->base + s->L.off_counters, 0, 256, s->stream));
+    HIPCHK(hipMemsetAsync(s->base + s->L.off_obs, 0, OBS_RING * NRED * 8, s->stream));
+    int rc = set_state(s, nullptr);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return AQ_OK;
+}
+
+int setup(aq_solver* s, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls)
+{
+    const aq_params& P = s->P;
+    const int nx = P.nx, ny = P.ny, pitch = s->L.pitch;
+    s->htype.assign((size_t)s->L.qs, 0);
+    for (int y = 0; y < ny; y++)
+        for (int x = 0; x < nx; x++) s->htype[(size_t)y * pitch + x] = mask[(size_t)y * nx + x] & 31;
+    static const int ex[8] = {1, 0, -1, 0, 1, -1, -1, 1}, ey[8] = {0, 1, 0, -1, 1, 1, -1, -1};
+    for (int y = 1; y < ny - 1; y++)
+        for (int x = 1; x < nx - 1; x++) {
+            uint8_t& t = s->htype[(size_t)y * pitch + x];
+            const int c = t & CLS_MASK;
+            if (c != FLUID && c != POROUS) continue;
+            s->n_active++;
+            if (c == FLUID) s->n_fluid++;
+            for (int i = 0; i < 8; i++) {
+                const int cc = mask[(size_t)(y + ey[i]) * nx + x + ex[i]] & 7;
+                if (cc != AQ_FLUID && cc != AQ_POROUS) t |= F_BOUNDARY;
+            }
+        }
+    s->n_walls = n_walls;
+    s->hwall_node.resize(std::max(n_walls, 1));
+    s->hwall_id.resize(std::max(n_walls, 1));
+    s->hwall_n.resize(2 * (size_t)std::max(n_walls, 1));
+    for (int w = 0; w < n_walls; w++) {
+        const int k = walls[w].node, x = k % nx, y = k / nx;
+        s->hwall_node[w] = y * pitch + x;
+        s->hwall_id[w] = walls[w].wall;
+        s->hwall_n[2 * w] = walls[w].n_x;
+        s->hwall_n[2 * w + 1] = walls[w].n_y;
+        s->htype[(size_t)y * pitch + x] |= F_WSS;
+        if (walls[w].wall == AQ_WALL_CORNEA) s->n_cornea++; else s->n_iris++;
+    }
+    choose_scales(s);
+
+    // device images: populations poisoned with NaN (never read at non-active nodes)
+    HIPCHK(hipMemsetAsync(s->base + s->L.off_a, 0xFF, s->L.off_type - s->L.off_a, s->stream));
+    HIPCHK(hipMemcpyAsync(s->base + s->L.off_type, s->htype.data(), s->htype.size(), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemsetAsync(s->base + s->L.off_uprev, 0, 3 * (size_t)s->L.qs * 8, s->stream));
+    const size_t W = (size_t)std::max(n_walls, 1);
+    char* wb = s->base + s->L.off_walls;
+    HIPCHK(hipMemcpyAsync(wb, s->hwall_node.data(), 4 * W, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(wb + 4 * W, s->hwall_id.data(), 4 * W, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(wb + 8 * W, s->hwall_n.data(), 16 * W, hipMemcpyHostToDevice, s->stream));
+    int rc = upload_tiles(s);
+    if (rc) return rc;
+    for (auto& e : s->ev) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipHostMalloc((void**)&s->obs_pinned, 2 * NRED * 8, hipHostMallocDefault));
+    return init_state(s);
+}
+
+int create_common(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls,
+                  void* arena, size_t arena_bytes, void* stream, bool own, aq_solver** out)
+{
+    if (!out) return fail(AQ_EINVAL, "null out");
+    int rc = validate(P, mask, walls, n_walls);
+    if (rc) return rc;
+    aq_solver* s = new aq_solver();
+    s->P = *P;
+    s->mode = P->storage;
+    s->L = make_layout(*P, n_walls);
+    if (own) {
+        hipError_t e = hipMalloc((void**)&s->base, s->L.total);
+        if (e != hipSuccess) {
+            delete s;
+            return fail(AQ_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        s->own_mem = true;
+    } else {
+        if (!arena || ((uintptr_t)arena & 255)) {
+            delete s;
+            return fail(AQ_EINVAL, "arena must be non-null and 256-byte aligned");
+        }
+        if (arena_bytes < s->L.total) {
+            delete s;
+            return fail(AQ_ENOMEM, "arena smaller than aq_required_bytes");
+        }
+        s->base = (char*)arena;
+    }
+    if (stream) {
+        s->stream = (hipStream_t)stream;
+    } else {
+        hipError_t e = hipStreamCreate(&s->stream);   // default priority
+        if (e != hipSuccess) {
+            aq_destroy(s);
+            return fail(AQ_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        }
+        s->own_stream = true;
+    }
+    rc = setup(s, mask, walls, n_walls);
+    if (rc) {
+        std::string keep = g_err;
+        aq_destroy(s);
+        g_err = keep;
+        return rc;
+    }
+    *out = s;
+    return AQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* aq_version(void) { return "aqlbm 0.1 (gfx950)"; }
+
+const char* aq_last_error(void) { return g_err.c_str(); }
+
+int aq_required_bytes(const aq_params* P, const uint8_t* mask, size_t* bytes)
+{
+    if (!P || !bytes) return fail(AQ_EINVAL, "null argument");
+    if (P->struct_size != sizeof(aq_params)) return fail(AQ_EINVAL, "aq_params.struct_size mismatch");
+    if (P->nx < 4 || P->ny < 4 || P->storage < 0 || P->storage > 2) return fail(AQ_EINVAL, "invalid size or storage");
+    int n_walls = 0;
+    if (mask) {
+        // an upper bound on the wall list: every FLUID node
+        size_t n = (size_t)P->nx * P->ny;
+        for (size_t k = 0; k < n; k++) n_walls += (mask[k] & 7) == AQ_FLUID;
+    }
+    *bytes = make_layout(*P, n_walls).total;
+    return AQ_OK;
+}
+
+int aq_create(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls, aq_solver** out)
+{
+    return create_common(P, mask, walls, n_walls, nullptr, 0, nullptr, true, out);
+}
+
+int aq_create_ext(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls,
+                  void* arena, size_t arena_bytes, void* stream, aq_solver** out)
+{
+    return create_common(P, mask, walls, n_walls, arena, arena_bytes, stream, false, out);
+}
+
+int aq_destroy(aq_solver* s)
+{
+    if (!s) return AQ_OK;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    drop_graph(s);
+    for (auto& e : s->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (s->obs_pinned) (void)hipHostFree(s->obs_pinned);
+    if (s->own_mem && s->base) (void)hipFree(s->base);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return AQ_OK;
+}
+
+int aq_step(aq_solver* s, int64_t nsteps)
+{
+    if (!s || nsteps < 0) return fail(AQ_EINVAL, "invalid arguments");
+    const int D = s->P.check_interval;
+    while (nsteps > 0) {
+        if (s->step % D == 0 && nsteps >= D) {
+            int rc = ensure_graph(s);
+            if (rc) return rc;
+            HIPCHK(hipGraphLaunch(s->plain_graph, s->stream));
+            s->cur ^= 1;              // D - 1 (odd) steps
+            s->step += D - 1;
+            rc = launch_one(s);       // the reducing step
+            if (rc) return rc;
+            nsteps -= D;
+        } else {
+            int rc = launch_one(s);
+            if (rc) return rc;
+            nsteps--;
+        }
+    }
+    return s->diverged ? fail(AQ_EDIVERGED, "non-finite state seen at a check step") : AQ_OK;
+}
+
+int aq_observe(aq_solver* s, aq_observables* out)
+{
+    if (!s || !out) return fail(AQ_EINVAL, "null argument");
+    if (s->checks == 0) {
+        HIPCHK(hipStreamSynchronize(s->stream));
+        std::memset(out, 0, sizeof(*out));
+        return AQ_OK;
+    }
+    double raw[NRED];
+    int rc = read_raw(s, s->checks - 1, raw);
+    if (rc) return rc;
+    raw_to_obs(s, raw, s->last_check_step, out);
+    if (out->n_nonfinite) s->diverged = true;
+    return AQ_OK;
+}
+
+int aq_run_to_steady(aq_solver* s, double tol, int64_t max_steps, aq_observables* out)
+{
+    if (!s || !out || !(tol > 0)) return fail(AQ_EINVAL, "invalid arguments");
+    const int D = s->P.check_interval;
+    // align to the check schedule
+    const int64_t lead = (D - s->step % D) % D;
+    int rc = aq_step(s, std::min<int64_t>(lead, max_steps));
+    if (rc) return rc;
+    int64_t done = std::min<int64_t>(lead, max_steps);
+    // keep one interval in flight while the previous one's residual is checked
+    bool have_prev = false;
+    unsigned int prev_idx = 0;
+    int64_t prev_step = 0;
+    while (true) {
+        bool launched = false;
+        if (done + D <= max_steps) {
+            rc = aq_step(s, D);
+            if (rc) return rc;
+            done += D;
+            launched = true;
+        }
+        if (have_prev) {
+            double raw[NRED];
+            const double* src = (const double*)(s->base + s->L.off_obs) + (size_t)(prev_idx % OBS_RING) * NRED;
+            // the stream may be ahead; the copy below is ordered after the in-flight interval
+            HIPCHK(hipMemcpyAsync(s->obs_pinned, src, NRED * 8, hipMemcpyDeviceToHost, s->stream));
+            HIPCHK(hipStreamSynchronize(s->stream));
+            std::memcpy(raw, s->obs_pinned, NRED * 8);
+            aq_observables o;
+            raw_to_obs(s, raw, prev_step, &o);
+            if (o.n_nonfinite) {
+                s->diverged = true;
+                *out = o;
+                return fail(AQ_EDIVERGED, "non-finite state");
+            }
+            if (std::max(o.resid_u, o.resid_T) < tol) {
+                return aq_observe(s, out);   // the latest interval (one past convergence)
+            }
+        }
+        if (!launched) break;
+        have_prev = true;
+        prev_idx = s->checks - 1;
+        prev_step = s->last_check_step;
+    }
+    rc = aq_observe(s, out);
+    if (rc) return rc;
+    if (std::max(out->resid_u, out->resid_T) < tol) return AQ_OK;
+    return fail(AQ_ENOTCONVERGED, "max_steps reached before the residual fell below tol");
+}
+
+int aq_read_field(aq_solver* s, int32_t field, int32_t q, double* host, size_t count)
+{
+    if (!s || !host) return fail(AQ_EINVAL, "null argument");
+    if (count != (size_t)s->P.nx * s->P.ny) return fail(AQ_EINVAL, "count must be nx*ny");
+    if (field < AQ_FIELD_P || field > AQ_FIELD_POP_HEAT) return fail(AQ_EINVAL, "unknown field");
+    if (field == AQ_FIELD_POP_FLOW && (q < 1 || q > 8)) return fail(AQ_EINVAL, "flow population q must be 1..8");
+    if (field == AQ_FIELD_POP_HEAT && (q < 0 || q > 4)) return fail(AQ_EINVAL, "thermal population q must be 0..4");
+    StepArgs a = make_args(s, s->cur != 0);   // src = prev: pulls to the current state
+    double* scratch = (double*)(s->base + s->L.off_scratch);
+    HIPCHK(launch_unpack(s->mode, a, field, q, s->P.p_ref, scratch, s->stream));
+    HIPCHK(hipMemcpyAsync(host, scratch, count * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return AQ_OK;
+}
+
+int aq_write_populations(aq_solver* s, const double* flow, const double* heat, size_t count)
+{
+    if (!s || !flow || !heat) return fail(AQ_EINVAL, "null argument");
+    const size_t n = (size_t)s->P.nx * s->P.ny;
+    if (count != n) return fail(AQ_EINVAL, "count must be nx*ny");
+    double* tmp = nullptr;
+    HIPCHK(hipMalloc((void**)&tmp, NPOP * n * 8));
+    hipError_t e = hipMemcpyAsync(tmp, flow, 8 * n * 8, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(tmp + 8 * n, heat, 5 * n * 8, hipMemcpyHostToDevice, s->stream);
+    int rc = AQ_OK;
+    if (e == hipSuccess) rc = set_state(s, tmp);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(AQ_EDEVICE, std::string("write populations: ") + hipGetErrorString(e));
+    if (rc) return rc;
+    s->diverged = false;
+    return AQ_OK;
+}
+
+int aq_get_info(aq_solver* s, aq_info* o)
+{
+    if (!s || !o) return fail(AQ_EINVAL, "null argument");
+    std::memset(o, 0, sizeof(*o));
+    o->active_nodes = s->n_active;
+    o->fluid_nodes = s->n_fluid;
+    o->lattice_nodes = (int64_t)s->P.nx * s->P.ny;
+    o->nx = s->P.nx;
+    o->ny = s->P.ny;
+    o->pitch = s->L.pitch;
+    o->storage = s->P.storage;
+    o->tile_x = s->tile_x;
+    o->tile_y = s->tile_y;
+    o->n_tiles = s->n_tiles;
+    o->check_interval = s->P.check_interval;
+    o->fp16_exp_flow = s->exp_f;
+    o->fp16_exp_thermal = s->exp_t;
+    o->step = s->step;
+    o->device_bytes = s->L.total;
+    o->bytes_per_node_update = bytes_per_update(s->mode);
+    return AQ_OK;
+}
+
+int aq_set_tile(aq_solver* s, int32_t tx, int32_t ty)
+{
+    if (!s) return fail(AQ_EINVAL, "null solver");
+    if (!(tx == 64 || tx == 128 || tx == 256) || ty < 1 || tx * ty < 64 || tx * ty > 256 || (ty & (ty - 1)))
+        return fail(AQ_EINVAL, "tile_x in {64,128,256}, tile_y a power of two, 64 <= tile_x*tile_y <= 256");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);
+    s->tile_x = tx;
+    s->tile_y = ty;
+    return upload_tiles(s);
+}
+
+int aq_time_step_kernel(aq_solver* s, int32_t n_launch, double* ms)
+{
+    if (!s || !ms || n_launch < 2 || (n_launch & 1)) return fail(AQ_EINVAL, "n_launch must be even and >= 2");
+    // n_launch steps, all without reductions (a check step that falls inside is not
+    // reduced); the step counter advances so the check schedule stays aligned
+    HIPCHK(hipEventRecord(s->ev[0], s->stream));
+    for (int i = 0; i < n_launch; i++) {
+        StepArgs a = make_args(s, s->cur == 0);
+        HIPCHK(launch_step(s->mode, false, a, s->stream));
+        s->cur ^= 1;
+        s->step++;
+    }
+    HIPCHK(hipEventRecord(s->ev[1], s->stream));
+    HIPCHK(hipEventSynchronize(s->ev[1]));
+    float t = 0;
+    HIPCHK(hipEventElapsedTime(&t, s->ev[0], s->ev[1]));
+    *ms = t / n_launch;
+    return AQ_OK;
+}
+
+int aq_run_intervals_timed(aq_solver* s, int32_t n, double* total_ms, double* plain_ms)
+{
+    if (!s || !total_ms || !plain_ms || n < 1) return fail(AQ_EINVAL, "invalid arguments");
+    const int D = s->P.check_interval;
+    if (s->step % D) return fail(AQ_ESTATE, "the step count must be a multiple of check_interval");
+    int rc = ensure_graph(s);
+    if (rc) return rc;
+    std::vector<hipEvent_t> evs(2 * (size_t)n + 1);
+    for (auto& e : evs) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventRecord(evs[0], s->stream));
+    for (int i = 0; i < n; i++) {
+        HIPCHK(hipGraphLaunch(s->plain_graph, s->stream));
+        s->cur ^= 1;
+        s->step += D - 1;
+        HIPCHK(hipEventRecord(evs[2 * i + 1], s->stream));
+        rc = launch_one(s);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(evs[2 * i + 2], s->stream));
+    }
+    HIPCHK(hipEventSynchronize(evs[2 * n]));
+    float t = 0;
+    double plain = 0;
+    for (int i = 0; i < n; i++) {
+        HIPCHK(hipEventElapsedTime(&t, evs[2 * i], evs[2 * i + 1]));
+        plain += t;
+    }
+    HIPCHK(hipEventElapsedTime(&t, evs[0], evs[2 * n]));
+    *total_ms = t;
+    *plain_ms = plain;
+    for (auto& e : evs) (void)hipEventDestroy(e);
+    return AQ_OK;
+}
+
+// Checkpoint file: magic, version, aq_params, step, last check step, exponents, then the
+// current and previous population buffers (storage precision) and the residual reference.
+int aq_save(aq_solver* s, const char* path)
+{
+    if (!s || !path) return fail(AQ_EINVAL, "null argument");
+    const size_t pop_bytes = (size_t)NPOP * s->L.qs * storage_size(s->mode);
+    const size_t up_bytes = 3 * (size_t)s->L.qs * 8;
+    std::vector<char> buf(2 * pop_bytes + up_bytes);
+    const char* cur = (const char*)(s->cur == 0 ? s->popA() : s->popB());
+    const char* prev = (const char*)(s->cur == 0 ? s->popB() : s->popA());
+    HIPCHK(hipMemcpyAsync(buf.data(), cur, pop_bytes, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(buf.data() + pop_bytes, prev, pop_bytes, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(buf.data() + 2 * pop_bytes, s->base + s->L.off_uprev, up_bytes, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(AQ_EINVAL, std::string("cannot open ") + path);
+    const uint32_t magic = 0x4D424C41u, version = 1;   // "ALBM"
+    int32_t hdr[4] = {s->exp_f, s->exp_t, (int32_t)s->checks, 0};
+    bool ok = std::fwrite(&magic, 4, 1, f) == 1 && std::fwrite(&version, 4, 1, f) == 1 &&
+              std::fwrite(&s->P, sizeof(aq_params), 1, f) == 1 && std::fwrite(&s->step, 8, 1, f) == 1 &&
+              std::fwrite(&s->last_check_step, 8, 1, f) == 1 && std::fwrite(hdr, 16, 1, f) == 1 &&
+              std::fwrite(buf.data(), 1, buf.size(), f) == buf.size();
+    std::fclose(f);
+    return ok ? AQ_OK : fail(AQ_EINVAL, "short write");
+}
+
+int aq_load(aq_solver* s, const char* path)
+{
+    if (!s || !path) return fail(AQ_EINVAL, "null argument");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(AQ_EINVAL, std::string("cannot open ") + path);
+    uint32_t magic = 0, version = 0;
+    aq_params P;
+    int64_t step = 0, last = 0;
+    int32_t hdr[4];
+    bool ok = std::fread(&magic, 4, 1, f) == 1 && std::fread(&version, 4, 1, f) == 1 &&
+              std::fread(&P, sizeof(aq_params), 1, f) == 1 && std::fread(&step, 8, 1, f) == 1 &&
+              std::fread(&last, 8, 1, f) == 1 && std::fread(hdr, 16, 1, f) == 1;
+    if (!ok || magic != 0x4D424C41u || version != 1 || std::memcmp(&P, &s->P, sizeof(aq_params)) != 0) {
+        std::fclose(f);
+        return fail(AQ_EINVAL, "checkpoint does not match this solver");
+    }
+    const size_t pop_bytes = (size_t)NPOP * s->L.qs * storage_size(s->mode);
+    const size_t up_bytes = 3 * (size_t)s->L.qs * 8;
+    std::vector<char> buf(2 * pop_bytes + up_bytes);
+    ok = std::fread(buf.data(), 1, buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok) return fail(AQ_EINVAL, "truncated checkpoint");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->cur = (int)(step & 1);   // the buffer parity follows the step count
+    void* cur = s->cur == 0 ? s->popA() : s->popB();
+    void* prev = s->cur == 0 ? s->popB() : s->popA();
+    HIPCHK(hipMemcpyAsync(cur, buf.data(), pop_bytes, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(prev, buf.data() + pop_bytes, pop_bytes, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->base + s->L.off_uprev, buf.data() + 2 * pop_bytes, up_bytes, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->step = step;
+    s->last_check_step = last;
+    s->exp_f = hdr[0];
+    s->exp_t = hdr[1];
+    s->diverged = false;
+    // the observables ring is not part of the checkpoint; the counters keep their
+    // device values so the next check step lands in the expected slot
+    return AQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+FP64 storage must match the oracle to 1e-12 normwise per field after 1000 steps; the
+observables of the check steps to 1e-12 relative (sums in a different order).
+"""
+import math
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import aqinputs as A
+import oracle as O
+from gpu_util import announce, field_errors, obs_close
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def aq():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2102_12663_amd as aq
+    aq.load_library()
+    return aq
+
+
+FIELD_TOL = 1e-12
+OBS_TOL = 1e-12
+
+
+def _run_pair(aq, p, mask, walls, steps):
+    announce(f"[parity] {p.nx}x{p.ny} storage={p.storage} steps={steps}")
+    s = aq.Solver(p, mask, walls)
+    s.step(steps)
+    gf = s.fields()
+    gobs = s.observe()
+    o = O.Oracle(p, mask, walls)
+    o.step(steps)
+    return s, o, gf, o.fields(), gobs, o.observables()
+
+
+def test_config0_fp64_fields_and_observables(aq):
+    """192x96 eye, FP64, 1000 steps: fields and check-step observables vs the oracle."""
+    p, mask, walls, geo = A.config0()
+    s, o, gf, of, gobs, oobs = _run_pair(aq, p, mask, walls, 1000)
+    err = field_errors(gf, of, mask, p.T_ref)
+    announce(f"[parity] config0 field errors {err}")
+    assert all(v <= FIELD_TOL for v in err.values()), err
+    assert gobs["step"] == oobs["step"] == 1000
+    bad = obs_close(gobs, oobs, OBS_TOL,
+                    keys=["iop_gauge", "p_mean_fluid", "q_in", "q_out", "wss_cornea_mean",
+                          "wss_cornea_max", "wss_iris_mean", "wss_iris_max", "resid_u", "resid_T",
+                          "u_max"])
+    assert not bad, bad
+    # masses are sums with cancellation: compare against the sum of magnitudes
+    h, g = o.populations()
+    act = A.active(mask)
+    assert abs(gobs["mass_flow"] - oobs["mass_flow"]) <= 1e-13 * np.sum(np.abs(h[:, act]))
+    assert abs(gobs["mass_thermal"] - oobs["mass_thermal"]) <= 1e-13 * np.sum(np.abs(g[:, act]))
+    assert gobs["n_nonfinite"] == 0
+
+
+def test_config0_fp64_populations(aq):
+    """Pre-collision populations (deviation form) after 1000 steps."""
+    p, mask, walls, geo = A.config0()
+    s = aq.Solver(p, mask, walls)
+    s.step(1000)
+    h, g = s.populations()
+    o = O.Oracle(p, mask, walls).step(1000)
+    ho, go = o.populations()
+    act = A.active(mask)
+    for q in range(8):
+        sc = np.max(np.abs(ho[q][act]))
+        assert np.max(np.abs(h[q][act] - ho[q][act])) <= FIELD_TOL * sc
+    for q in range(5):
+        sc = np.max(np.abs(go[q][act]))
+        assert np.max(np.abs(g[q][act] - go[q][act])) <= FIELD_TOL * max(sc, 1e-300)
+    assert np.all(np.isnan(h[:, ~act]))
+
+
+@pytest.mark.parametrize("nx,ny,alpha", [(131, 70, 37.0), (200, 101, 30.0)])
+def test_ragged_random_state_every_boundary(aq, nx, ny, alpha):
+    """Ragged lattice (nx not a multiple of the tile width), random pre-collision state
+    (so every link rule sees non-trivial values), buoyancy at an angle, strong drag."""
+    mask, walls, geo = A.eye_mask(nx, ny, alpha)
+    p = A.eye_params(nx, ny, geo, u_in=3e-4, Da=3e-4, Ra=5e3, phi_deg=30.0, check_interval=20)
+    p.p_out = p.p_ref + 1e-4
+    p.T_inlet = 0.8
+    rng = np.random.default_rng(11)
+    h = rng.normal(0, 1e-4, (8, ny, nx))
+    g = rng.normal(0, 1e-2, (5, ny, nx))
+    s = aq.Solver(p, mask, walls)
+    s.write_populations(h, g)
+    o = O.Oracle(p, mask, walls)
+    o.set_populations(h, g)
+    s.step(200)
+    o.step(200)
+    err = field_errors(s.fields(), o.fields(), mask, p.T_ref)
+    announce(f"[parity] ragged {nx}x{ny} errors {err}")
+    assert all(v <= FIELD_TOL for v in err.values()), err
+    bad = obs_close(s.observe(), o.observables(), 1e-11,
+                    keys=["iop_gauge", "q_in", "q_out", "wss_cornea_mean", "wss_iris_max", "resid_u", "u_max"])
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("tile", [(64, 1), (64, 2), (128, 2), (256, 1)])
+def test_tile_shapes_bitwise(aq, tile):
+    """The per-node arithmetic does not depend on the tile shape: fields bitwise equal."""
+    p, mask, walls, geo = A.config0()
+    ref = aq.Solver(p, mask, walls)
+    ref.step(300)
+    s = aq.Solver(p, mask, walls)
+    s.set_tile(*tile)
+    s.step(300)
+    for a, b in zip(ref.fields(), s.fields()):
+        assert np.array_equal(np.nan_to_num(a, nan=7.0), np.nan_to_num(b, nan=7.0))
+    bad = obs_close(ref.observe(), s.observe(), 1e-13, keys=["iop_gauge", "q_out", "resid_u", "u_max"])
+    assert not bad
+
+
+def test_determinism_and_partial_steps(aq):
+    """Two runs are bitwise identical, including the (fixed-order) reductions; stepping
+    in irregular pieces equals stepping in whole intervals."""
+    p, mask, walls, geo = A.config0()
+    a = aq.Solver(p, mask, walls)
+    a.step(1000)
+    b = aq.Solver(p, mask, walls)
+    for n in (7, 93, 1, 299, 600):
+        b.step(n)
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(np.nan_to_num(x, nan=7.0), np.nan_to_num(y, nan=7.0))
+    assert a.observe() == b.observe()
+
+
+def test_checkpoint_resume_bitwise(aq):
+    p, mask, walls, geo = A.config0()
+    a = aq.Solver(p, mask, walls)
+    a.step(600)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ck.bin")
+        a.save(path)
+        a.step(400)
+        b = aq.Solver(p, mask, walls)
+        b.load(path)
+        b.step(400)
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(np.nan_to_num(x, nan=7.0), np.nan_to_num(y, nan=7.0))
+    assert a.observe() == b.observe()
+
+
+def test_closed_box_conservation_gpu(aq):
+    """Closed box with buoyancy and a porous patch: sum h and sum g stay fixed on the GPU."""
+    nx, ny = 150, 70
+    mask = A.box_mask(nx, ny, porous_rect=(20, 40, 10, 30))
+    p = A.Params(nx=nx, ny=ny, tau_f=0.7, tau_t=0.8, gbeta=1e-3, check_interval=10, K=0.05)
+    rng = np.random.default_rng(2)
+    s = aq.Solver(p, mask, A.no_walls())
+    h = rng.normal(0, 1e-4, (8, ny, nx))
+    g = rng.normal(0, 1e-2, (5, ny, nx))
+    s.write_populations(h, g)
+    s.step(10)
+    m0 = s.observe()
+    s.step(2000)
+    m1 = s.observe()
+    act = A.active(mask)
+    assert abs(m1["mass_flow"] - m0["mass_flow"]) < 1e-12 * np.sum(np.abs(h[:, act]))
+    assert abs(m1["mass_thermal"] - m0["mass_thermal"]) < 1e-12 * np.sum(np.abs(g[:, act]))
+
+
+def test_run_to_steady_matches_oracle_iop(aq):
+    """Small eye at Ra = 0 run to a steady residual: IOP and outflow = inflow."""
+    mask, walls, geo = A.eye_mask(96, 48, 45.0, R=40.0, pupil_gap=2)
+    p = A.eye_params(96, 48, geo, Ra=0.0, Da=1e-3, check_interval=100)
+    s = aq.Solver(p, mask, walls)
+    ok, ob = s.run_to_steady(1e-7, 200000)
+    assert ok, ob
+    o = O.Oracle(p, mask, walls).step(ob["step"])
+    oo = o.observables()
+    assert ob["iop_gauge"] == pytest.approx(oo["iop_gauge"], rel=1e-10)
+    assert abs(ob["q_out"] / ob["q_in"] - 1) < 1e-6
+
+
+@pytest.mark.parametrize("storage,tol_u,tol_iop", [(A.F32, 1e-4, 1e-3), (A.F16S, 5e-2, 5e-2)])
+def test_reduced_precision_close_to_fp64(aq, storage, tol_u, tol_iop):
+    """FP32 and F16S storage after 1000 steps of the 192x96 case stay near FP64."""
+    p, mask, walls, geo = A.config0()
+    ref = aq.Solver(p, mask, walls)
+    ref.step(1000)
+    p2 = A.Params(**{**p.asdict(), "storage": storage})
+    s = aq.Solver(p2, mask, walls)
+    s.step(1000)
+    act = A.active(mask)
+    ur = np.hypot(*ref.fields()[1:3])[act]
+    u2 = np.hypot(*s.fields()[1:3])[act]
+    rel = np.linalg.norm(u2 - ur) / np.linalg.norm(ur)
+    oa, ob = ref.observe(), s.observe()
+    announce(f"[precision] storage={storage} u L2 rel {rel:.3e} iop {oa['iop_gauge']:.6e} vs {ob['iop_gauge']:.6e} exps {s.info()['fp16_exp_flow']},{s.info()['fp16_exp_thermal']}")
+    assert rel < tol_u
+    assert abs(ob["iop_gauge"] - oa["iop_gauge"]) <= tol_iop * abs(oa["iop_gauge"])
+
+
+def test_config1_size_fp64_parity(aq):
+    """2048x1024 eye (sweep seed 0, the benchmark's workload and tile shape), FP64, 1000
+    steps: every field vs the oracle, normwise 1e-12."""
+    p, mask, walls, geo = A.sweep_instance(0, 2048, 1024)
+    s, o, gf, of, gobs, oobs = _run_pair(aq, p, mask, walls, 1000)
+    err = field_errors(gf, of, mask, p.T_ref)
+    announce(f"[parity] 2048x1024 field errors {err}")
+    assert all(v <= FIELD_TOL for v in err.values()), err
+    bad = obs_close(gobs, oobs, 1e-11, keys=["iop_gauge", "q_in", "q_out", "wss_cornea_mean",
+                                              "wss_iris_mean", "resid_u", "resid_T", "u_max"])
+    assert not bad, bad
