@@ -31,7 +31,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage, workload_key):
+def measured_traffic(key):
     """HBM bytes per launch of the plain step kernel from the committed rocprofv3 PMC
     summary, if it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
@@ -39,10 +39,14 @@ def measured_traffic(storage, workload_key):
         return None
     with open(path) as f:
         d = json.load(f)
-    e = d.get(f"{workload_key}/{storage}")
+    e = d.get(key)
     if not e or e.get("kernel_hash") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
+
+
+def workload_key_of(args):
+    return f"eye{args.nx}x{args.ny}s{args.seed}/{args.storage}"
 
 
 def cpu_baseline(p, mask, walls, budget_s=12.0):
@@ -78,6 +82,9 @@ def main():
     ap.add_argument("--tile", default="64x4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra-storages", action="store_true", help="also time f32 and f16s")
+    ap.add_argument("--probe", action="store_true",
+                    help="for hardware-counter runs: 10 plain step launches of the workload, then "
+                         "3 device copies of 256 MiB (a copy kernel of known size for calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
@@ -92,6 +99,22 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     tx, ty = (int(v) for v in args.tile.split("x"))
+    if args.probe:
+        p, mask, walls, geo = A.sweep_instance(args.seed, args.nx, args.ny, storage=STORAGES[args.storage])
+        s = aq.Solver(p, mask, walls)
+        s.set_tile(tx, ty)
+        s.time_step_kernel(10)
+        x = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        info = s.info()
+        print(json.dumps({"probe": workload_key_of(args), "active_nodes": info["active_nodes"],
+                          "bytes_per_node_update": info["bytes_per_node_update"],
+                          "kernel_hash": kernel_source_hash(), "copy_bytes": 256 << 20}), flush=True)
+        return
 
     def run(storage_name, steps, warmup):
         p, mask, walls, geo = A.sweep_instance(args.seed, args.nx, args.ny,
@@ -120,8 +143,7 @@ def main():
     act = info["active_nodes"]
     bpu = info["bytes_per_node_update"]
     achieved = bpu * act / (r["plain_launch_ms"] * 1e-3) / 1e9
-    workload_key = f"eye{args.nx}x{args.ny}s{args.seed}"
-    traffic = measured_traffic(args.storage, workload_key)
+    traffic = measured_traffic(workload_key_of(args))
     out = {
         "metric": METRIC,
         "value": round(r["mlups"], 2),

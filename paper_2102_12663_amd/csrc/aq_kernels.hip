@@ -69,87 +69,70 @@ __device__ __forceinline__ bool is_active(uint8_t t)
 }
 
 // ------------------------------------------------------------------------------ pull
-template <int MODE, int I>
-__device__ __forceinline__ void pull_flow(const StepArgs& a, const typename Traits<MODE>::S* src, int k,
-                                          bool boundary, Node<typename Traits<MODE>::R>& n)
-{
-    using T = Traits<MODE>;
-    using R = typename T::R;
-    const R inv = R(a.inv_sf);
-    const int ks = k - EY[I] * a.pitch - EX[I];
-    const typename T::S* ps = src + (long long)(I - 1) * a.qs;
-    if (!boundary) {
-        n.h[I] = T::ld(ps + ks, inv);
-        return;
-    }
-    const uint8_t c = a.type[ks] & CLS_MASK;
-    if (c == FLUID || c == POROUS) {
-        n.h[I] = T::ld(ps + ks, inv);
-        return;
-    }
-    const R v = T::ld(src + (long long)(OPP[I] - 1) * a.qs + k, inv);
-    if (c == SOLID) {
-        n.h[I] = v;                                        // half-way bounce-back
-    } else if (c == INLET) {
-        const R corr = R(6.0) * wflow<R>(I) * (R(EX[I]) * R(a.uin_x) + R(EY[I]) * R(a.uin_y));
-        n.h[I] = v + corr;                                 // moving wall at u_in
-        n.qin += corr;
-    } else {
-        const R out = -v + R(2.0) * lam<R>(I) * R(a.dp_out); // pressure anti-bounce-back
-        n.qout += v - out;
-        n.h[I] = out;
-    }
-}
-
-template <int MODE, int I>
-__device__ __forceinline__ void pull_heat(const StepArgs& a, const typename Traits<MODE>::S* src, int k,
-                                          bool boundary, Node<typename Traits<MODE>::R>& n)
-{
-    using T = Traits<MODE>;
-    using R = typename T::R;
-    const R inv = R(a.inv_st);
-    const typename T::S* base = src + 8LL * a.qs;
-    const int ks = k - EY[I] * a.pitch - EX[I];
-    if (!boundary) {
-        n.g[I] = T::ld(base + (long long)I * a.qs + ks, inv);
-        return;
-    }
-    const uint8_t t = a.type[ks];
-    const uint8_t c = t & CLS_MASK;
-    if (c == FLUID || c == POROUS) {
-        n.g[I] = T::ld(base + (long long)I * a.qs + ks, inv);
-        return;
-    }
-    const R v = T::ld(base + (long long)OPP[I] * a.qs + k, inv);
-    const uint8_t wall = (t >> WALL_SHIFT) & 3;
-    if (c == INLET || (c == SOLID && wall != WALL_BOX)) {
-        const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
-        n.g[I] = -v + R(2.0) * R(a.wT) * R(tw);          // Dirichlet anti-bounce-back
-    } else {
-        n.g[I] = v;                                        // adiabatic bounce-back
-    }
-}
-
+// All 13 loads are issued without intervening branches: a boundary node first reads its
+// 8 neighbours' type bytes, each load address is then selected (upstream slot, or the
+// node's own opposite slot for a link into a non-active node), and the link rules are
+// applied to the loaded values afterwards.  Interior nodes skip the type reads.
 template <int MODE>
 __device__ __forceinline__ void pull_all(const StepArgs& a, const typename Traits<MODE>::S* src, int k,
                                          bool boundary, Node<typename Traits<MODE>::R>& n)
 {
-    using R = typename Traits<MODE>::R;
+    using T = Traits<MODE>;
+    using R = typename T::R;
+    const R inv_f = R(a.inv_sf), inv_t = R(a.inv_st);
+    uint8_t nt[9];
+    if (boundary) {
+#pragma unroll
+        for (int i = 1; i <= 8; i++) nt[i] = a.type[k - EY[i] * a.pitch - EX[i]];
+    } else {
+#pragma unroll
+        for (int i = 1; i <= 8; i++) nt[i] = FLUID;
+    }
+    bool up[9];
+#pragma unroll
+    for (int i = 1; i <= 8; i++) up[i] = is_active(nt[i]);
+#pragma unroll
+    for (int i = 1; i <= 8; i++) {
+        const long long off = up[i] ? (long long)(i - 1) * a.qs + (k - EY[i] * a.pitch - EX[i])
+                                    : (long long)(OPP[i] - 1) * a.qs + k;
+        n.h[i] = T::ld(src + off, inv_f);
+    }
+    const typename T::S* tsrc = src + 8LL * a.qs;
+    n.g[0] = T::ld(tsrc + k, inv_t);
+#pragma unroll
+    for (int i = 1; i <= 4; i++) {
+        const long long off = up[i] ? (long long)i * a.qs + (k - EY[i] * a.pitch - EX[i])
+                                    : (long long)OPP[i] * a.qs + k;
+        n.g[i] = T::ld(tsrc + off, inv_t);
+    }
     n.qin = R(0);
     n.qout = R(0);
-    pull_flow<MODE, 1>(a, src, k, boundary, n);
-    pull_flow<MODE, 2>(a, src, k, boundary, n);
-    pull_flow<MODE, 3>(a, src, k, boundary, n);
-    pull_flow<MODE, 4>(a, src, k, boundary, n);
-    pull_flow<MODE, 5>(a, src, k, boundary, n);
-    pull_flow<MODE, 6>(a, src, k, boundary, n);
-    pull_flow<MODE, 7>(a, src, k, boundary, n);
-    pull_flow<MODE, 8>(a, src, k, boundary, n);
-    n.g[0] = Traits<MODE>::ld(src + 8LL * a.qs + k, R(a.inv_st));
-    pull_heat<MODE, 1>(a, src, k, boundary, n);
-    pull_heat<MODE, 2>(a, src, k, boundary, n);
-    pull_heat<MODE, 3>(a, src, k, boundary, n);
-    pull_heat<MODE, 4>(a, src, k, boundary, n);
+    if (!boundary) return;
+#pragma unroll
+    for (int i = 1; i <= 8; i++) {
+        if (up[i]) continue;
+        const uint8_t c = nt[i] & CLS_MASK;
+        const R v = n.h[i];
+        if (c == INLET) {                                      // moving wall at u_in
+            const R corr = R(6.0) * wflow<R>(i) * (R(EX[i]) * R(a.uin_x) + R(EY[i]) * R(a.uin_y));
+            n.h[i] = v + corr;
+            n.qin += corr;
+        } else if (c == OUTLET) {                              // pressure anti-bounce-back
+            const R out = -v + R(2.0) * lam<R>(i) * R(a.dp_out);
+            n.qout += v - out;
+            n.h[i] = out;
+        }                                                      // SOLID: half-way bounce-back
+    }
+#pragma unroll
+    for (int i = 1; i <= 4; i++) {
+        if (up[i]) continue;
+        const uint8_t c = nt[i] & CLS_MASK;
+        const uint8_t wall = (nt[i] >> WALL_SHIFT) & 3;
+        if (c == INLET || (c == SOLID && wall != WALL_BOX)) {  // Dirichlet anti-bounce-back
+            const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
+            n.g[i] = -n.g[i] + R(2.0) * R(a.wT) * R(tw);
+        }                                                      // else adiabatic bounce-back
+    }
 }
 
 // ------------------------------------------------------------------------------ moments
@@ -261,13 +244,6 @@ __device__ __forceinline__ void store_all(const StepArgs& a, typename Traits<MOD
 // ------------------------------------------------------------------------------ reduction
 __device__ __forceinline__ bool red_is_max(int j) { return j == R_WSS_C_MAX || j == R_WSS_I_MAX || j == R_UMAX; }
 
-__device__ __forceinline__ double load_coherent(const double* p)
-{
-    unsigned long long v = __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double((long long)v);
-}
-
 __device__ void block_reduce_publish(double* r, const StepArgs& a)
 {
     __shared__ double sm[16][NRED];
@@ -277,14 +253,16 @@ __device__ void block_reduce_publish(double* r, const StepArgs& a)
         double v = r[j];
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
-            double o = __shfl_xor(v, off, 64);
+            const double o = __shfl_xor(v, off, 64);
             v = red_is_max(j) ? fmax(v, o) : v + o;
         }
         r[j] = v;
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-    if (lane == 0)
+    if (lane == 0) {
+#pragma unroll
         for (int j = 0; j < NRED; j++) sm[w][j] = r[j];
+    }
     __syncthreads();
     if (threadIdx.x < NRED) {
         const int j = threadIdx.x;
@@ -292,35 +270,46 @@ __device__ void block_reduce_publish(double* r, const StepArgs& a)
         for (int q = 1; q < nw; q++) acc = red_is_max(j) ? fmax(acc, sm[q][j]) : acc + sm[q][j];
         a.partials[(long long)blockIdx.x * NRED + j] = acc;
     }
+    // publish this block's partial (agent-scope release), then take a ticket
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) last = (atomicAdd(a.counter, 1u) == gridDim.x - 1);
     __syncthreads();
     if (!last) return;
+    // the last block: acquire, then sum all partials in a fixed order
     __threadfence();
-    // last block: fixed-order sum of all partials
     const int nb = gridDim.x;
+    double acc[NRED];
+#pragma unroll
+    for (int j = 0; j < NRED; j++) acc[j] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const double* pb = a.partials + (long long)b * NRED;
+#pragma unroll
+        for (int j = 0; j < NRED; j++) acc[j] = red_is_max(j) ? fmax(acc[j], pb[j]) : acc[j] + pb[j];
+    }
+#pragma unroll
     for (int j = 0; j < NRED; j++) {
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-            double v = load_coherent(a.partials + (long long)b * NRED + j);
-            acc = red_is_max(j) ? fmax(acc, v) : acc + v;
-        }
+        double v = acc[j];
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
-            double o = __shfl_xor(acc, off, 64);
-            acc = red_is_max(j) ? fmax(acc, o) : acc + o;
+            const double o = __shfl_xor(v, off, 64);
+            v = red_is_max(j) ? fmax(v, o) : v + o;
         }
-        if (lane == 0) sm[w][j] = acc;
+        acc[j] = v;
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NRED; j++) sm[w][j] = acc[j];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned int c = *a.obs_count;
         double* o = a.obs + (long long)(c % OBS_RING) * NRED;
         for (int j = 0; j < NRED; j++) {
-            double acc = sm[0][j];
-            for (int q = 1; q < nw; q++) acc = red_is_max(j) ? fmax(acc, sm[q][j]) : acc + sm[q][j];
-            o[j] = acc;
+            double v = sm[0][j];
+            for (int q = 1; q < nw; q++) v = red_is_max(j) ? fmax(v, sm[q][j]) : v + sm[q][j];
+            o[j] = v;
         }
         *a.obs_count = c + 1;
         *a.counter = 0;
