@@ -49,7 +49,6 @@ struct StepArgs {
 
     // reductions (check steps only)
     double* partials;         // [gridDim][NRED]
-    unsigned int* counter;    // blocks done; reset by the last block
     double* obs;              // [OBS_RING][NRED]
     unsigned int* obs_count;  // check steps reduced so far
     double* uprev;            // 3 arrays (u_x, u_y, T) of qs doubles

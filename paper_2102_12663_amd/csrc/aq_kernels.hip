@@ -17,9 +17,9 @@
 // node is one read and one write of each live population plus the type byte.
 //
 // On check steps the same kernel also reduces the IOP, outlet/inlet fluxes, wall shear
-// stress, residuals, masses and max |u| in double: wavefront shuffles, one partial per
-// block, one atomic ticket per block, and the last block sums the partials in a fixed
-// order (deterministic).
+// stress, residuals, masses and max |u| in double: wavefront shuffles and one partial per
+// block, then a one-block kernel sums the partials in a fixed order (deterministic, with
+// no fences or atomics inside the step kernel).
 #include "aq_device.h"
 
 #include <math.h>
@@ -244,10 +244,12 @@ __device__ __forceinline__ void store_all(const StepArgs& a, typename Traits<MOD
 // ------------------------------------------------------------------------------ reduction
 __device__ __forceinline__ bool red_is_max(int j) { return j == R_WSS_C_MAX || j == R_WSS_I_MAX || j == R_UMAX; }
 
-__device__ void block_reduce_publish(double* r, const StepArgs& a)
+// Block-level part of the check-step reduction: wavefront shuffles, then one partial
+// per block.  The fixed-order sum over blocks is a separate one-block kernel, so no
+// fence or atomic is needed and the result is deterministic.
+__device__ void block_reduce_store(double* r, const StepArgs& a)
 {
     __shared__ double sm[16][NRED];
-    __shared__ int last;
 #pragma unroll
     for (int j = 0; j < NRED; j++) {
         double v = r[j];
@@ -270,19 +272,18 @@ __device__ void block_reduce_publish(double* r, const StepArgs& a)
         for (int q = 1; q < nw; q++) acc = red_is_max(j) ? fmax(acc, sm[q][j]) : acc + sm[q][j];
         a.partials[(long long)blockIdx.x * NRED + j] = acc;
     }
-    // publish this block's partial (agent-scope release), then take a ticket
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = (atomicAdd(a.counter, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!last) return;
-    // the last block: acquire, then sum all partials in a fixed order
-    __threadfence();
-    const int nb = gridDim.x;
+}
+
+// Sum the n_tiles block partials in a fixed order and append the result to the
+// observables ring.  One block of 256 threads.
+__global__ __launch_bounds__(256) void finish_kernel(StepArgs a)
+{
+    __shared__ double sm[4][NRED];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double acc[NRED];
 #pragma unroll
     for (int j = 0; j < NRED; j++) acc[j] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    for (int b = threadIdx.x; b < a.n_tiles; b += 256) {
         const double* pb = a.partials + (long long)b * NRED;
 #pragma unroll
         for (int j = 0; j < NRED; j++) acc[j] = red_is_max(j) ? fmax(acc[j], pb[j]) : acc[j] + pb[j];
@@ -297,7 +298,6 @@ __device__ void block_reduce_publish(double* r, const StepArgs& a)
         }
         acc[j] = v;
     }
-    __syncthreads();
     if (lane == 0) {
 #pragma unroll
         for (int j = 0; j < NRED; j++) sm[w][j] = acc[j];
@@ -308,11 +308,10 @@ __device__ void block_reduce_publish(double* r, const StepArgs& a)
         double* o = a.obs + (long long)(c % OBS_RING) * NRED;
         for (int j = 0; j < NRED; j++) {
             double v = sm[0][j];
-            for (int q = 1; q < nw; q++) v = red_is_max(j) ? fmax(v, sm[q][j]) : v + sm[q][j];
+            for (int q = 1; q < 4; q++) v = red_is_max(j) ? fmax(v, sm[q][j]) : v + sm[q][j];
             o[j] = v;
         }
         *a.obs_count = c + 1;
-        *a.counter = 0;
     }
 }
 
@@ -422,7 +421,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a)
             r[R_NONFINITE] = (isfinite(dp) && isfinite(ux) && isfinite(uy) && isfinite(th)) ? 0.0 : 1.0;
         }
     }
-    if (REDUCE) block_reduce_publish(r, a);
+    if (REDUCE) block_reduce_store(r, a);
 }
 
 // ------------------------------------------------------------------------------ scatter / unpack
@@ -530,8 +529,14 @@ static hipError_t launch_step_t(bool reduce, const StepArgs& a, hipStream_t s)
 {
     const dim3 grid(a.n_tiles), block(a.tile_x * a.tile_y);
     if (a.n_tiles == 0) return hipSuccess;
-    if (reduce) hipLaunchKernelGGL((step_kernel<MODE, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((step_kernel<MODE, false>), grid, block, 0, s, a);
+    if (reduce) {
+        hipLaunchKernelGGL((step_kernel<MODE, true>), grid, block, 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((step_kernel<MODE, false>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 

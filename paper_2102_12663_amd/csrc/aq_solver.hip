@@ -148,7 +148,6 @@ StepArgs make_args(const aq_solver* s, bool a_is_src)
     a.inv_st = 1.0 / s->st;
     char* b = s->base;
     a.partials = (double*)(b + s->L.off_partials);
-    a.counter = (unsigned int*)(b + s->L.off_counters);
     a.obs_count = (unsigned int*)(b + s->L.off_counters + 64);
     a.obs = (double*)(b + s->L.off_obs);
     a.uprev = (double*)(b + s->L.off_uprev);
