@@ -223,6 +223,81 @@ int aq_time_step_kernel(aq_solver* s, int32_t n_launch, double* ms_per_launch);
 int aq_run_intervals_timed(aq_solver* s, int32_t n_intervals, double* total_ms,
                            double* plain_ms);
 
+/* ------------------------------------------------------------------------------------
+ * Batched serving form: many independent solves (parameter sweeps of uneven lattice
+ * sizes) resident in one device arena and stepped together, one multi-instance kernel
+ * launch per storage mode and time step, replayed from a captured HIP graph per check
+ * interval.  Requests are admitted while others run (continuous batching); each one runs
+ * to its own steady-state residual.  An admitted instance computes exactly what the
+ * single-lattice solver computes for the same parameters, mask and tile shape (fields and
+ * observables bitwise equal).
+ * ------------------------------------------------------------------------------------ */
+typedef struct aq_batch aq_batch;
+
+/* A finished request.  status: AQ_OK (residual below tol), AQ_ENOTCONVERGED (max_steps),
+ * AQ_EDIVERGED (non-finite moments), or AQ_ENOMEM when an F16S solve failed the drift
+ * check and no memory was free for its F32 continuation.  storage: the storage the final
+ * state is held in; fallback: 1 when an F16S solve failed the IOP drift check and was
+ * continued in F32 storage. */
+typedef struct aq_result {
+    int64_t request_id;
+    int32_t slot, status, storage, fallback;
+    int64_t steps;
+    aq_observables obs;
+} aq_result;
+
+typedef struct aq_batch_info {
+    int32_t max_slots, running, finished;
+    int32_t n_work[3];              /* tiles per storage mode in the work lists */
+    int64_t active_nodes;           /* over running instances */
+    size_t budget_bytes, used_bytes, largest_free_bytes;
+    int64_t step;                   /* time steps run by the batch */
+} aq_batch_info;
+
+/* Create a batch: budget_bytes of device memory for instances (allocated once), at most
+ * max_slots instances, at most max_active_nodes active nodes running at once (0 = no cap),
+ * work lists of max_tiles tiles per storage mode, and a common check_interval (even).
+ * hip_stream may be NULL (the batch creates its own). */
+int aq_batch_create(size_t budget_bytes, int32_t max_slots, int64_t max_active_nodes, int32_t max_tiles,
+                    int32_t check_interval, void* hip_stream, aq_batch** out);
+
+/* Admit one solve.  Parameters, mask and walls as for aq_create; tile_x * tile_y must be
+ * 256.  tol: residual at which the solve is done (an F16S solve first runs to
+ * max(tol, 2e-5), its binary16 noise floor); drift_tol: for F16S storage, the largest
+ * |Q_out/Q_in - 1| at that point accepted without continuing in F32 to tol; max_steps:
+ * step cap; request_id: returned with the result; keep != 0 keeps the finished state
+ * readable (aq_batch_read_field) until aq_batch_release.  *slot receives the slot.
+ * AQ_EBUSY when no slot, arena space, active-node or work-list capacity is free. */
+int aq_batch_admit(aq_batch* b, const aq_params* params, const uint8_t* mask, const aq_wall_node* walls,
+                   int32_t n_walls, int32_t tile_x, int32_t tile_y, double tol, double drift_tol,
+                   int64_t max_steps, int64_t request_id, int32_t keep, int32_t* slot);
+
+/* Run n_intervals check intervals of every running instance, then retire the instances
+ * that converged, diverged or reached max_steps (synchronises the stream). */
+int aq_batch_run(aq_batch* b, int32_t n_intervals);
+
+/* Collect up to cap finished results not yet collected; their slots and memory are freed
+ * unless they were admitted with keep. */
+int aq_batch_poll(aq_batch* b, aq_result* done, int32_t cap, int32_t* n_done);
+
+/* aq_read_field / aq_observe on the instance in a slot (running, or finished and kept). */
+int aq_batch_read_field(aq_batch* b, int32_t slot, int32_t field, int32_t q, double* host, size_t count);
+int aq_batch_observe(aq_batch* b, int32_t slot, aq_observables* out);
+
+/* Free a slot (running or finished). */
+int aq_batch_release(aq_batch* b, int32_t slot);
+
+int aq_batch_get_info(aq_batch* b, aq_batch_info* out);
+
+/* Autotune the tile shape of a solver: time n_launch plain launches for each candidate
+ * shape (64x4, 128x2, 256x1, and 64x1, 64x2, 128x1 unless only_256 is set) and keep the
+ * fastest; *tile_x, *tile_y and *ms_per_launch receive it.  The state advances by the
+ * launched steps (n_launch even; reductions are skipped, as in aq_time_step_kernel). */
+int aq_autotune_tile(aq_solver* s, int32_t n_launch, int32_t only_256, int32_t* tile_x, int32_t* tile_y,
+                     double* ms_per_launch);
+
+int aq_batch_destroy(aq_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,9 @@ FIELDS = {"p": 0, "ux": 1, "uy": 2, "T": 3, "pop_flow": 4, "pop_heat": 5}
 EXPORTS = ("aq_version", "aq_last_error", "aq_required_bytes", "aq_create", "aq_create_ext",
            "aq_destroy", "aq_step", "aq_run_to_steady", "aq_observe", "aq_read_field",
            "aq_write_populations", "aq_save", "aq_load", "aq_get_info", "aq_set_tile",
-           "aq_time_step_kernel", "aq_run_intervals_timed")
+           "aq_time_step_kernel", "aq_run_intervals_timed", "aq_autotune_tile",
+           "aq_batch_create", "aq_batch_admit", "aq_batch_run", "aq_batch_poll", "aq_batch_read_field",
+           "aq_batch_observe", "aq_batch_release", "aq_batch_get_info", "aq_batch_destroy")
 
 
 class AqParams(C.Structure):
@@ -64,6 +66,28 @@ class AqInfo(C.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class AqResult(C.Structure):
+    _fields_ = [("request_id", C.c_int64), ("slot", C.c_int32), ("status", C.c_int32),
+                ("storage", C.c_int32), ("fallback", C.c_int32), ("steps", C.c_int64),
+                ("obs", AqObservables)]
+
+    def asdict(self):
+        d = {n: getattr(self, n) for n, _ in self._fields_ if n != "obs"}
+        d["obs"] = self.obs.asdict()
+        return d
+
+
+class AqBatchInfo(C.Structure):
+    _fields_ = [("max_slots", C.c_int32), ("running", C.c_int32), ("finished", C.c_int32),
+                ("n_work", C.c_int32 * 3), ("active_nodes", C.c_int64), ("budget_bytes", C.c_size_t),
+                ("used_bytes", C.c_size_t), ("largest_free_bytes", C.c_size_t), ("step", C.c_int64)]
+
+    def asdict(self):
+        d = {n: getattr(self, n) for n, _ in self._fields_ if n != "n_work"}
+        d["n_work"] = list(self.n_work)
+        return d
+
+
 class AqError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"aqlbm error {code}: {msg}")
@@ -99,6 +123,18 @@ def load_library(path: str = LIB_PATH):
     L.aq_set_tile.argtypes = [vp, i32, i32]
     L.aq_time_step_kernel.argtypes = [vp, i32, dp]
     L.aq_run_intervals_timed.argtypes = [vp, i32, dp, dp]
+    ip = C.POINTER(i32)
+    L.aq_autotune_tile.argtypes = [vp, i32, i32, ip, ip, dp]
+    L.aq_batch_create.argtypes = [sz, i32, i64, i32, i32, vp, C.POINTER(vp)]
+    L.aq_batch_admit.argtypes = [vp, C.POINTER(AqParams), vp, vp, i32, i32, i32, C.c_double, C.c_double,
+                                 i64, i64, i32, ip]
+    L.aq_batch_run.argtypes = [vp, i32]
+    L.aq_batch_poll.argtypes = [vp, C.POINTER(AqResult), i32, ip]
+    L.aq_batch_read_field.argtypes = [vp, i32, i32, i32, dp, sz]
+    L.aq_batch_observe.argtypes = [vp, i32, C.POINTER(AqObservables)]
+    L.aq_batch_release.argtypes = [vp, i32]
+    L.aq_batch_get_info.argtypes = [vp, C.POINTER(AqBatchInfo)]
+    L.aq_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("aq_version", "aq_last_error"):
             getattr(L, name).restype = C.c_int
@@ -244,11 +280,99 @@ class Solver:
         _check(_lib.aq_run_intervals_timed(self._h, int(n), C.byref(tot), C.byref(plain)))
         return tot.value, plain.value
 
+    def autotune(self, n_launch: int = 20, only_256: bool = False):
+        tx, ty, ms = C.c_int32(), C.c_int32(), C.c_double()
+        _check(_lib.aq_autotune_tile(self._h, int(n_launch), int(only_256), C.byref(tx), C.byref(ty), C.byref(ms)))
+        return tx.value, ty.value, ms.value
+
     def save(self, path: str):
         _check(_lib.aq_save(self._h, path.encode()))
 
     def load(self, path: str):
         _check(_lib.aq_load(self._h, path.encode()))
+
+
+class Batch:
+    """Continuously batched solves (include/aqlbm.h, aq_batch_*).  The batch allocates its
+    instance arena once; work runs on a torch stream (default priority) owned here."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 512, max_active_nodes: int = 0,
+                 max_tiles: int = 1 << 20, check_interval: int = 100, device="cuda:0", stream=None):
+        import torch
+        load_library()
+        self._stream = stream if stream is not None else torch.cuda.Stream(device=torch.device(device))
+        h = C.c_void_p()
+        _check(_lib.aq_batch_create(int(budget_bytes), int(max_slots), int(max_active_nodes), int(max_tiles),
+                                    int(check_interval), C.c_void_p(self._stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self._keep = {}
+        self.shapes = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.aq_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, params, mask, walls=None, tile=(64, 4), tol=1e-6, drift_tol=1e-3,
+              max_steps=10 ** 7, request_id=0, keep=False):
+        """Slot number, or None when the batch is full (AQ_EBUSY)."""
+        p = make_params(params)
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        wptr, nw, warr = _walls(walls)
+        slot = C.c_int32()
+        rc = _lib.aq_batch_admit(self._h, C.byref(p), mask.ctypes.data, wptr, nw, int(tile[0]), int(tile[1]),
+                                 float(tol), float(drift_tol), int(max_steps), int(request_id), int(keep),
+                                 C.byref(slot))
+        if rc == AQ_EBUSY:
+            return None
+        _check(rc)
+        self.shapes[slot.value] = mask.shape
+        return slot.value
+
+    def run(self, n_intervals: int = 1):
+        _check(_lib.aq_batch_run(self._h, int(n_intervals)))
+
+    def poll(self, cap: int = 4096):
+        buf = (AqResult * cap)()
+        n = C.c_int32()
+        _check(_lib.aq_batch_poll(self._h, buf, int(cap), C.byref(n)))
+        return [buf[i].asdict() for i in range(n.value)]
+
+    def read_field(self, slot: int, name: str, q: int = 0):
+        ny, nx = self.shapes[slot]
+        out = np.empty(nx * ny)
+        _check(_lib.aq_batch_read_field(self._h, int(slot), FIELDS[name], int(q),
+                                        out.ctypes.data_as(C.POINTER(C.c_double)), out.size))
+        return out.reshape(ny, nx)
+
+    def observe(self, slot: int) -> dict:
+        o = AqObservables()
+        _check(_lib.aq_batch_observe(self._h, int(slot), C.byref(o)))
+        return o.asdict()
+
+    def release(self, slot: int):
+        _check(_lib.aq_batch_release(self._h, int(slot)))
+
+    def info(self) -> dict:
+        i = AqBatchInfo()
+        _check(_lib.aq_batch_get_info(self._h, C.byref(i)))
+        return i.asdict()
+
+
+def required_bytes(params, mask) -> int:
+    """Device bytes one lattice needs (aq_required_bytes)."""
+    load_library()
+    p = make_params(params)
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    n = C.c_size_t()
+    _check(_lib.aq_required_bytes(C.byref(p), m.ctypes.data, C.byref(n)))
+    return n.value
 
 
 def version() -> str:

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libaqlbm.so")
-SOURCES = [os.path.join(HERE, "csrc", "aq_kernels.hip"), os.path.join(HERE, "csrc", "aq_solver.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("aq_kernels.hip", "aq_solver.hip", "aq_batch.hip")]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,539 @@
+// Batched serving form of the aqlbm library: many independent lattices (parameter-sweep
+// solves of uneven sizes) resident in one HBM arena and stepped together by one
+// multi-instance kernel per storage mode, with a captured HIP graph per check interval.
+//
+// - Admission checks the free arena (first-fit pool), free slots, the work-list capacity
+//   and an active-node cap; each admitted instance is an ordinary single-lattice solver
+//   carved out of the arena, so its state, fields and checkpoints behave exactly as alone.
+// - The graph reads the instance table and the (slot, tile) work lists from device
+//   memory, so admissions and retirements between intervals need no re-capture.
+// - After each call to aq_batch_run the latest reductions of every running instance are
+//   read back in one copy; converged, diverged and capped instances are retired.
+// - An F16S instance whose residual falls below max(tol, 2e-5) passes the IOP drift check
+//   when its outflow balances its inflow (|Q_out/Q_in - 1| <= drift_tol: a steady
+//   pressure level needs exact mass balance, and rounding that does not conserve mass
+//   shows up first as this imbalance); otherwise its state is converted to F32 storage
+//   and the solve continues there until the residual falls below tol.
+#include "aq_internal.h"
+
+#include <map>
+
+using namespace aq;
+
+namespace {
+
+// binary16 rounding keeps the per-step residual of an F16S solve above ~1e-6; its phase
+// ends at max(tol, this floor)
+constexpr double kF16ResidFloor = 2e-5;
+
+// First-fit allocator over [0, size) with coalescing free blocks (offsets in bytes).
+class Pool {
+public:
+    void init(size_t size)
+    {
+        free_.clear();
+        if (size) free_[0] = size;
+        size_ = size;
+        used_ = 0;
+    }
+    bool alloc(size_t bytes, size_t* off)
+    {
+        bytes = align_up(bytes, 256);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t noff = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[noff] = rest;
+                used_ += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = align_up(bytes, 256);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+    size_t largest() const
+    {
+        size_t m = 0;
+        for (auto& kv : free_) m = std::max(m, kv.second);
+        return m;
+    }
+
+private:
+    std::map<size_t, size_t> free_;
+    size_t size_ = 0, used_ = 0;
+};
+
+struct Slot {
+    bool used = false, running = false, done = false, reported = false, keep = false;
+    aq_solver* s = nullptr;
+    size_t off = 0, bytes = 0;
+    double tol = 0, drift_tol = 0;
+    int64_t max_steps = 0, request_id = 0, steps = 0;
+    int status = AQ_OK, fallback = 0;
+    aq_observables obs;
+};
+
+}  // namespace
+
+struct aq_batch {
+    size_t budget = 0;
+    char* arena = nullptr;
+    Pool pool;
+    int max_slots = 0, max_tiles = 0, grid = 2048, interval = 0;
+    int64_t max_active = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<Slot> slots;
+    int64_t step = 0;
+
+    InstDesc* d_inst = nullptr;
+    int2* d_work[3] = {nullptr, nullptr, nullptr};
+    int* d_nwork = nullptr;
+    double* d_partials[3] = {nullptr, nullptr, nullptr};
+    double* d_latest = nullptr;
+    double* h_latest = nullptr;     // pinned
+    std::vector<InstDesc> h_inst;
+    int n_work[3] = {0, 0, 0};
+
+    int graph_mask = -1;
+    hipGraph_t graph_src = nullptr;
+    hipGraphExec_t graph = nullptr;
+};
+
+namespace {
+
+BatchArgs batch_args(const aq_batch* b, int mode, int parity)
+{
+    BatchArgs a;
+    a.inst = b->d_inst;
+    a.work = b->d_work[mode];
+    a.n_work = b->d_nwork + mode;
+    a.partials = b->d_partials[mode];
+    a.latest = b->d_latest;
+    a.parity = parity;
+    a.max_slots = b->max_slots;
+    a.mode = mode;
+    return a;
+}
+
+int active_mask(const aq_batch* b)
+{
+    int m = 0;
+    for (int i = 0; i < 3; i++)
+        if (b->n_work[i] > 0) m |= 1 << i;
+    return m;
+}
+
+void drop_graph(aq_batch* b)
+{
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->graph_src) (void)hipGraphDestroy(b->graph_src);
+    b->graph = nullptr;
+    b->graph_src = nullptr;
+    b->graph_mask = -1;
+}
+
+// One check interval for every storage mode present: interval-1 plain steps, the
+// reducing step, and the per-instance finishing sums.
+int ensure_graph(aq_batch* b)
+{
+    const int mask = active_mask(b);
+    if (b->graph && b->graph_mask == mask) return AQ_OK;
+    drop_graph(b);
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int t = 0; t < b->interval && err == hipSuccess; t++) {
+        const bool reduce = t == b->interval - 1;
+        for (int m = 0; m < 3 && err == hipSuccess; m++)
+            if (mask & (1 << m)) err = launch_batch_step(m, reduce, batch_args(b, m, t & 1), b->grid, b->stream);
+    }
+    for (int m = 0; m < 3 && err == hipSuccess; m++)
+        if (mask & (1 << m)) err = launch_batch_finish(batch_args(b, m, 0), b->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (err != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(AQ_EDEVICE, std::string("batch graph capture: ") + hipGetErrorString(err != hipSuccess ? err : e2));
+    }
+    hipGraphExec_t ge = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(AQ_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+    }
+    b->graph_src = g;
+    b->graph = ge;
+    b->graph_mask = mask;
+    return AQ_OK;
+}
+
+// Rebuild the instance table and the per-mode work lists from the running slots and
+// copy them to the device (ordered on the batch stream, then synchronised).
+int upload_tables(aq_batch* b)
+{
+    std::vector<int2> work[3];
+    for (int i = 0; i < b->max_slots; i++) {
+        InstDesc& d = b->h_inst[i];
+        std::memset(&d, 0, sizeof(d));
+        const Slot& sl = b->slots[i];
+        if (!sl.used || !sl.running) continue;
+        const int m = sl.s->mode;
+        d.a = make_args(sl.s, true);
+        d.work_start = (int)work[m].size();
+        d.work_count = sl.s->n_tiles;
+        d.running = 1;
+        d.mode = m;
+        for (int t : sl.s->htiles) work[m].push_back(make_int2(i, t));
+    }
+    for (int m = 0; m < 3; m++) {
+        if ((int)work[m].size() > b->max_tiles) return fail(AQ_EBUSY, "work list capacity exceeded");
+        b->n_work[m] = (int)work[m].size();
+        if (!work[m].empty())
+            HIPCHK(hipMemcpyAsync(b->d_work[m], work[m].data(), work[m].size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+    }
+    HIPCHK(hipMemcpyAsync(b->d_nwork, b->n_work, 3 * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_inst, b->h_inst.data(), b->h_inst.size() * sizeof(InstDesc), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    return AQ_OK;
+}
+
+int64_t running_active(const aq_batch* b)
+{
+    int64_t n = 0;
+    for (const Slot& sl : b->slots)
+        if (sl.used && sl.running) n += sl.s->n_active;
+    return n;
+}
+
+void free_slot(aq_batch* b, int i)
+{
+    Slot& sl = b->slots[i];
+    if (sl.s) aq_destroy(sl.s);
+    if (sl.bytes) b->pool.release(sl.off, sl.bytes);
+    sl = Slot();
+}
+
+// Continue an F16S solve in F32 storage from its current state.
+int convert_to_f32(aq_batch* b, int i)
+{
+    Slot& sl = b->slots[i];
+    aq_solver* s16 = sl.s;
+    const size_t n = (size_t)s16->P.nx * s16->P.ny;
+    aq_params P = s16->P;
+    P.storage = AQ_F32;
+    // the new solver needs the mask and the wall list again: rebuild them from the old one
+    std::vector<uint8_t> mask(n);
+    for (int y = 0; y < P.ny; y++)
+        for (int x = 0; x < P.nx; x++) mask[(size_t)y * P.nx + x] = s16->htype[(size_t)y * s16->L.pitch + x] & 31;
+    std::vector<aq_wall_node> walls(std::max(s16->n_walls, 1));
+    for (int w = 0; w < s16->n_walls; w++) {
+        const int k = s16->hwall_node[w];
+        walls[w].node = (k / s16->L.pitch) * P.nx + k % s16->L.pitch;
+        walls[w].wall = s16->hwall_id[w];
+        walls[w].n_x = s16->hwall_n[2 * w];
+        walls[w].n_y = s16->hwall_n[2 * w + 1];
+    }
+    const Layout L32 = make_layout(P, s16->n_walls);
+    size_t off = 0;
+    if (!b->pool.alloc(L32.total, &off)) return fail(AQ_ENOMEM, "no arena space for the F32 fallback");
+    double* dense = nullptr;
+    hipError_t e = hipMalloc((void**)&dense, NPOP * n * 8);
+    if (e != hipSuccess) {
+        b->pool.release(off, L32.total);
+        return fail(AQ_ENOMEM, "no device memory for the state conversion");
+    }
+    StepArgs a = make_args(s16, s16->cur != 0);   // src = prev: pulls to the current state
+    e = launch_unpack(s16->mode, a, 7, 0, P.p_ref, dense, b->stream);
+    aq_solver* s32 = nullptr;
+    int rc = AQ_OK;
+    if (e == hipSuccess) {
+        rc = create_common(&P, mask.data(), walls.data(), s16->n_walls, b->arena + off, L32.total, b->stream, false, &s32);
+        if (rc == AQ_OK) rc = aq_set_tile(s32, s16->tile_x, s16->tile_y);
+        if (rc == AQ_OK) rc = set_state(s32, dense);
+        if (rc == AQ_OK) {
+            s32->step = s16->step;
+            s32->checks = 0;
+            s32->last_check_step = s16->last_check_step;
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(dense);
+    if (e != hipSuccess || rc != AQ_OK) {
+        if (s32) aq_destroy(s32);
+        b->pool.release(off, L32.total);
+        return rc != AQ_OK ? rc : fail(AQ_EDEVICE, std::string("state conversion: ") + hipGetErrorString(e));
+    }
+    aq_destroy(s16);
+    b->pool.release(sl.off, sl.bytes);
+    sl.s = s32;
+    sl.off = off;
+    sl.bytes = L32.total;
+    sl.fallback = 1;
+    return AQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int aq_batch_create(size_t budget_bytes, int32_t max_slots, int64_t max_active_nodes, int32_t max_tiles,
+                    int32_t check_interval, void* hip_stream, aq_batch** out)
+{
+    if (!out || max_slots < 1 || max_slots > 65536 || max_tiles < 1 || budget_bytes < (1u << 20) ||
+        check_interval < 2 || (check_interval & 1) || max_active_nodes < 0)
+        return fail(AQ_EINVAL, "invalid batch parameters");
+    aq_batch* b = new aq_batch();
+    b->budget = align_up(budget_bytes, 256);
+    b->max_slots = max_slots;
+    b->max_tiles = max_tiles;
+    b->max_active = max_active_nodes;
+    b->interval = check_interval;
+    b->slots.resize(max_slots);
+    b->h_inst.resize(max_slots);
+    auto cleanup = [&](int rc) {
+        std::string keep = aq_last_error();
+        aq_batch_destroy(b);
+        g_err = keep;
+        return rc;
+    };
+    if (hipMalloc((void**)&b->arena, b->budget) != hipSuccess) return cleanup(fail(AQ_ENOMEM, "cannot allocate the batch arena"));
+    b->pool.init(b->budget);
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&b->stream) != hipSuccess) return cleanup(fail(AQ_EDEVICE, "hipStreamCreate failed"));
+        b->own_stream = true;
+    }
+    bool ok = hipMalloc((void**)&b->d_inst, (size_t)max_slots * sizeof(InstDesc)) == hipSuccess &&
+              hipMalloc((void**)&b->d_nwork, 64) == hipSuccess &&
+              hipMalloc((void**)&b->d_latest, (size_t)max_slots * NRED * 8) == hipSuccess &&
+              hipHostMalloc((void**)&b->h_latest, (size_t)max_slots * NRED * 8, hipHostMallocDefault) == hipSuccess;
+    for (int m = 0; m < 3 && ok; m++)
+        ok = hipMalloc((void**)&b->d_work[m], (size_t)max_tiles * sizeof(int2)) == hipSuccess &&
+             hipMalloc((void**)&b->d_partials[m], (size_t)max_tiles * NRED * 8) == hipSuccess;
+    if (!ok) return cleanup(fail(AQ_ENOMEM, "cannot allocate the batch tables"));
+    int rc = upload_tables(b);
+    if (rc) return cleanup(rc);
+    *out = b;
+    return AQ_OK;
+}
+
+int aq_batch_destroy(aq_batch* b)
+{
+    if (!b) return AQ_OK;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    for (int i = 0; i < (int)b->slots.size(); i++)
+        if (b->slots[i].used) free_slot(b, i);
+    (void)hipFree(b->d_inst);
+    (void)hipFree(b->d_nwork);
+    (void)hipFree(b->d_latest);
+    if (b->h_latest) (void)hipHostFree(b->h_latest);
+    for (int m = 0; m < 3; m++) {
+        (void)hipFree(b->d_work[m]);
+        (void)hipFree(b->d_partials[m]);
+    }
+    (void)hipFree(b->arena);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return AQ_OK;
+}
+
+int aq_batch_admit(aq_batch* b, const aq_params* P, const uint8_t* mask, const aq_wall_node* walls,
+                   int32_t n_walls, int32_t tile_x, int32_t tile_y, double tol, double drift_tol,
+                   int64_t max_steps, int64_t request_id, int32_t keep, int32_t* slot)
+{
+    if (!b || !slot) return fail(AQ_EINVAL, "null argument");
+    if (!(tol > 0) || !(drift_tol > 0) || max_steps < 1) return fail(AQ_EINVAL, "tol, drift_tol and max_steps must be positive");
+    if (tile_x * tile_y != 256) return fail(AQ_EINVAL, "batched instances use 256-thread tiles");
+    int rc = validate(P, mask, walls, n_walls);
+    if (rc) return rc;
+    if (P->check_interval != b->interval) return fail(AQ_EINVAL, "check_interval differs from the batch's");
+    int free_i = -1;
+    for (int i = 0; i < b->max_slots; i++)
+        if (!b->slots[i].used) { free_i = i; break; }
+    if (free_i < 0) return fail(AQ_EBUSY, "no free slot");
+    const Layout L = make_layout(*P, n_walls);
+    size_t off = 0;
+    if (!b->pool.alloc(L.total, &off)) return fail(AQ_EBUSY, "not enough free HBM in the batch arena");
+    aq_solver* s = nullptr;
+    rc = create_common(P, mask, walls, n_walls, b->arena + off, L.total, b->stream, false, &s);
+    if (rc == AQ_OK) rc = aq_set_tile(s, tile_x, tile_y);
+    int tiles_now = 0;
+    for (int m = 0; m < 3; m++) tiles_now += b->n_work[m];
+    if (rc == AQ_OK && b->max_active && running_active(b) + s->n_active > b->max_active)
+        rc = fail(AQ_EBUSY, "active-node cap reached");
+    if (rc == AQ_OK && b->n_work[s->mode] + s->n_tiles > b->max_tiles)
+        rc = fail(AQ_EBUSY, "work list capacity reached");
+    if (rc != AQ_OK) {
+        std::string keep_err = aq_last_error();
+        if (s) aq_destroy(s);
+        b->pool.release(off, L.total);
+        g_err = keep_err;
+        return rc;
+    }
+    Slot& sl = b->slots[free_i];
+    sl = Slot();
+    sl.used = sl.running = true;
+    sl.keep = keep != 0;
+    sl.s = s;
+    sl.off = off;
+    sl.bytes = L.total;
+    sl.tol = tol;
+    sl.drift_tol = drift_tol;
+    sl.max_steps = max_steps;
+    sl.request_id = request_id;
+    std::memset(&sl.obs, 0, sizeof(sl.obs));
+    rc = upload_tables(b);
+    if (rc) {
+        std::string keep_err = aq_last_error();
+        free_slot(b, free_i);
+        (void)upload_tables(b);
+        g_err = keep_err;
+        return rc;
+    }
+    *slot = free_i;
+    return AQ_OK;
+}
+
+int aq_batch_run(aq_batch* b, int32_t n_intervals)
+{
+    if (!b || n_intervals < 1) return fail(AQ_EINVAL, "invalid arguments");
+    if (active_mask(b) == 0) return AQ_OK;
+    int rc = ensure_graph(b);
+    if (rc) return rc;
+    for (int i = 0; i < n_intervals; i++) HIPCHK(hipGraphLaunch(b->graph, b->stream));
+    const int64_t dn = (int64_t)n_intervals * b->interval;
+    b->step += dn;
+    HIPCHK(hipMemcpyAsync(b->h_latest, b->d_latest, (size_t)b->max_slots * NRED * 8, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    bool changed = false;
+    for (int i = 0; i < b->max_slots; i++) {
+        Slot& sl = b->slots[i];
+        if (!sl.used || !sl.running) continue;
+        aq_solver* s = sl.s;
+        s->step += dn;
+        s->checks += n_intervals;
+        s->last_check_step = s->step;
+        sl.steps += dn;
+        raw_to_obs(s, b->h_latest + (size_t)i * NRED, s->step, &sl.obs);
+        bool finish = false;
+        if (sl.obs.n_nonfinite > 0) {
+            sl.status = AQ_EDIVERGED;
+            s->diverged = true;
+            finish = true;
+        } else if (std::max(sl.obs.resid_u, sl.obs.resid_T) < (s->mode == AQ_F16S ? std::max(sl.tol, kF16ResidFloor) : sl.tol)) {
+            const double imbalance = sl.obs.q_in != 0 ? std::fabs(sl.obs.q_out / sl.obs.q_in - 1.0) : 0.0;
+            if (s->mode == AQ_F16S && !(imbalance <= sl.drift_tol)) {
+                rc = convert_to_f32(b, i);
+                if (rc != AQ_OK) {
+                    sl.status = rc;
+                    finish = true;
+                }
+                changed = true;
+            } else {
+                sl.status = AQ_OK;
+                finish = true;
+            }
+        } else if (sl.steps >= sl.max_steps) {
+            sl.status = AQ_ENOTCONVERGED;
+            finish = true;
+        }
+        if (finish) {
+            sl.running = false;
+            sl.done = true;
+            changed = true;
+        }
+    }
+    if (changed) {
+        rc = upload_tables(b);
+        if (rc) return rc;
+    }
+    return AQ_OK;
+}
+
+int aq_batch_poll(aq_batch* b, aq_result* done, int32_t cap, int32_t* n_done)
+{
+    if (!b || !n_done || (cap > 0 && !done)) return fail(AQ_EINVAL, "invalid arguments");
+    int n = 0;
+    for (int i = 0; i < b->max_slots && n < cap; i++) {
+        Slot& sl = b->slots[i];
+        if (!sl.used || !sl.done || sl.reported) continue;
+        aq_result& r = done[n++];
+        std::memset(&r, 0, sizeof(r));
+        r.request_id = sl.request_id;
+        r.slot = i;
+        r.status = sl.status;
+        r.storage = sl.s->mode;
+        r.fallback = sl.fallback;
+        r.steps = sl.steps;
+        r.obs = sl.obs;
+        sl.reported = true;
+        if (!sl.keep) free_slot(b, i);
+    }
+    *n_done = n;
+    return AQ_OK;
+}
+
+int aq_batch_read_field(aq_batch* b, int32_t slot, int32_t field, int32_t q, double* host, size_t count)
+{
+    if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(AQ_EINVAL, "no such slot");
+    return aq_read_field(b->slots[slot].s, field, q, host, count);
+}
+
+int aq_batch_observe(aq_batch* b, int32_t slot, aq_observables* out)
+{
+    if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(AQ_EINVAL, "no such slot");
+    return aq_observe(b->slots[slot].s, out);
+}
+
+int aq_batch_release(aq_batch* b, int32_t slot)
+{
+    if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(AQ_EINVAL, "no such slot");
+    Slot& sl = b->slots[slot];
+    const bool was_running = sl.running;
+    free_slot(b, slot);
+    if (was_running) return upload_tables(b);
+    return AQ_OK;
+}
+
+int aq_batch_get_info(aq_batch* b, aq_batch_info* o)
+{
+    if (!b || !o) return fail(AQ_EINVAL, "null argument");
+    std::memset(o, 0, sizeof(*o));
+    o->max_slots = b->max_slots;
+    for (const Slot& sl : b->slots) {
+        if (!sl.used) continue;
+        if (sl.running) o->running++;
+        else o->finished++;
+    }
+    for (int m = 0; m < 3; m++) o->n_work[m] = b->n_work[m];
+    o->active_nodes = running_active(b);
+    o->budget_bytes = b->budget;
+    o->used_bytes = b->pool.used();
+    o->largest_free_bytes = b->pool.largest();
+    o->step = b->step;
+    return AQ_OK;
+}
+
+}  // extern "C"

@@ -58,15 +58,37 @@ struct StepArgs {
     int n_walls;
 };
 
+// One instance of a batch (device table entry).  `a` has buffer A as src (even parity).
+struct InstDesc {
+    StepArgs a;
+    int work_start, work_count;   // this instance's run in its storage mode's work list
+    int running, mode;
+};
+
+// Arguments of the batched kernels (one storage mode per launch).
+struct BatchArgs {
+    const InstDesc* inst;
+    const int2* work;          // (slot, tile) items, grouped by slot
+    const int* n_work;         // number of items (device memory, read at run time)
+    double* partials;          // [work capacity][NRED]
+    double* latest;            // [max_slots][NRED]: latest raw sums of every instance
+    int parity;                // 0: buffer A is src
+    int max_slots;
+    int mode;
+};
+
 // Host-side launchers (defined in aq_kernels.hip).
 hipError_t launch_step(int mode, bool reduce, const StepArgs& a, hipStream_t s);
+hipError_t launch_batch_step(int mode, bool reduce, const BatchArgs& b, int grid, hipStream_t s);
+hipError_t launch_batch_finish(const BatchArgs& b, hipStream_t s);
 // Write into a.dst the buffer whose pull gives the pre-collision populations `pops`
 // (dense [13][ny][nx] doubles), or, if pops is null, the rest equilibrium with
 // p - p_ref = dp0 and T - T_ref = th0.
 hipError_t launch_scatter(int mode, const StepArgs& a, const double* pops, double dp0, double th0,
                           hipStream_t s);
 // Pull a.src and write one field (0 p, 1 u_x, 2 u_y, 3 T, 4 flow population q, 5 thermal
-// population q) to out[ny][nx]; field 6 stores the moments as the residual reference.
+// population q) to out[ny][nx]; field 6 stores the moments as the residual reference;
+// field 7 writes all 13 populations to out[13][ny][nx].
 hipError_t launch_unpack(int mode, const StepArgs& a, int field, int q, double p_ref, double* out,
                          hipStream_t s);
 

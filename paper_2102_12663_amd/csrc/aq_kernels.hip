@@ -247,7 +247,7 @@ __device__ __forceinline__ bool red_is_max(int j) { return j == R_WSS_C_MAX || j
 // Block-level part of the check-step reduction: wavefront shuffles, then one partial
 // per block.  The fixed-order sum over blocks is a separate one-block kernel, so no
 // fence or atomic is needed and the result is deterministic.
-__device__ void block_reduce_store(double* r, const StepArgs& a)
+__device__ void block_reduce_store(double* r, double* out)
 {
     __shared__ double sm[16][NRED];
 #pragma unroll
@@ -270,21 +270,23 @@ __device__ void block_reduce_store(double* r, const StepArgs& a)
         const int j = threadIdx.x;
         double acc = sm[0][j];
         for (int q = 1; q < nw; q++) acc = red_is_max(j) ? fmax(acc, sm[q][j]) : acc + sm[q][j];
-        a.partials[(long long)blockIdx.x * NRED + j] = acc;
+        out[j] = acc;
     }
 }
 
-// Sum the n_tiles block partials in a fixed order and append the result to the
-// observables ring.  One block of 256 threads.
-__global__ __launch_bounds__(256) void finish_kernel(StepArgs a)
+// Sum n tile partials in a fixed order (thread t takes t, t+256, ...; then shuffles and
+// the 4 waves in order) and append the result to an observables ring.  Called by one
+// block of 256 threads.  Single-lattice and batched runs use this same function, so an
+// instance gives bitwise the same observables alone or in a batch.
+__device__ void finish_sum(const double* partials, int n, double* obs, unsigned int* obs_count, double* latest)
 {
     __shared__ double sm[4][NRED];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double acc[NRED];
 #pragma unroll
     for (int j = 0; j < NRED; j++) acc[j] = 0.0;
-    for (int b = threadIdx.x; b < a.n_tiles; b += 256) {
-        const double* pb = a.partials + (long long)b * NRED;
+    for (int b = threadIdx.x; b < n; b += 256) {
+        const double* pb = partials + (long long)b * NRED;
 #pragma unroll
         for (int j = 0; j < NRED; j++) acc[j] = red_is_max(j) ? fmax(acc[j], pb[j]) : acc[j] + pb[j];
     }
@@ -304,15 +306,22 @@ __global__ __launch_bounds__(256) void finish_kernel(StepArgs a)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned int c = *a.obs_count;
-        double* o = a.obs + (long long)(c % OBS_RING) * NRED;
+        const unsigned int c = *obs_count;
+        double* o = obs + (long long)(c % OBS_RING) * NRED;
         for (int j = 0; j < NRED; j++) {
             double v = sm[0][j];
             for (int q = 1; q < 4; q++) v = red_is_max(j) ? fmax(v, sm[q][j]) : v + sm[q][j];
             o[j] = v;
+            if (latest) latest[j] = v;
         }
-        *a.obs_count = c + 1;
+        *obs_count = c + 1;
     }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void finish_kernel(StepArgs a)
+{
+    finish_sum(a.partials, a.n_tiles, a.obs, a.obs_count, nullptr);
 }
 
 // Wall-shear stress |t - (t.n) n| with t = sigma n, sigma = -(1 - omega/2) Pi^neq.
@@ -363,12 +372,13 @@ __device__ __forceinline__ int tile_of_block(const StepArgs& a)
     return xcd * q + min(xcd, r) + seq;
 }
 
+// One tile of one time step: pull, moments, forces, both collisions, store; on check
+// steps also this tile's partial sums (written to `partial`).
 template <int MODE, bool REDUCE>
-__global__ __launch_bounds__(256) void step_kernel(StepArgs a)
+__device__ __forceinline__ void process_tile(const StepArgs& a, int tile, double* partial)
 {
     using T = Traits<MODE>;
     using R = typename T::R;
-    const int tile = a.tiles[tile_of_block(a)];
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int lx = threadIdx.x % a.tile_x, ly = threadIdx.x / a.tile_x;
     const int x = tx * a.tile_x + lx, y = ty * a.tile_y + ly;
@@ -421,7 +431,50 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a)
             r[R_NONFINITE] = (isfinite(dp) && isfinite(ux) && isfinite(uy) && isfinite(th)) ? 0.0 : 1.0;
         }
     }
-    if (REDUCE) block_reduce_store(r, a);
+    if (REDUCE) block_reduce_store(r, partial);
+}
+
+// One time step of one lattice: one block per active tile.  The partial of a tile is
+// stored at its index in the tile list.
+template <int MODE, bool REDUCE>
+__global__ __launch_bounds__(256) void step_kernel(StepArgs a)
+{
+    const int ti = tile_of_block(a);
+    process_tile<MODE, REDUCE>(a, a.tiles[ti], a.partials + (long long)ti * NRED);
+}
+
+// One time step of every running instance of a batch whose storage is MODE.  A fixed grid
+// walks the (slot, tile) work list, which lives in device memory with its length, so a
+// captured graph stays valid while instances are admitted and retired.  Each block takes
+// a contiguous run of work items (neighbouring tiles of one instance stay on one CU).
+template <int MODE, bool REDUCE>
+__global__ __launch_bounds__(256) void batch_step_kernel(BatchArgs b)
+{
+    const int n = *b.n_work;
+    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int w0 = blockIdx.x * per, w1 = min(n, w0 + per);
+    for (int w = w0; w < w1; w++) {
+        const int2 it = b.work[w];
+        StepArgs a = b.inst[it.x].a;
+        if (b.parity) {
+            void* t = (void*)a.src;
+            a.src = a.dst;
+            a.dst = t;
+        }
+        process_tile<MODE, REDUCE>(a, it.y, b.partials + (long long)w * NRED);
+        if (REDUCE) __syncthreads();
+    }
+}
+
+// Per-instance fixed-order sums of the batch's check step (one block per instance).
+__global__ __launch_bounds__(256) void batch_finish_kernel(BatchArgs b)
+{
+    for (int sl = blockIdx.x; sl < b.max_slots; sl += gridDim.x) {
+        const InstDesc* d = b.inst + sl;
+        if (!d->running || d->mode != b.mode) continue;
+        finish_sum(b.partials + (long long)d->work_start * NRED, d->work_count, d->a.obs, d->a.obs_count,
+                   b.latest + (long long)sl * NRED);
+    }
 }
 
 // ------------------------------------------------------------------------------ scatter / unpack
@@ -499,12 +552,23 @@ __global__ __launch_bounds__(256) void unpack_kernel(StepArgs a, int field, int 
     const long long d = (long long)y * a.nx + x;
     const uint8_t t = a.type[k];
     if (!is_active(t)) {
-        if (field != 6) out[d] = __builtin_nan("");
+        if (field == 7) {
+            const long long n2 = (long long)a.nx * a.ny;
+            for (int i = 0; i < NPOP; i++) out[i * n2 + d] = __builtin_nan("");
+        } else if (field != 6) {
+            out[d] = __builtin_nan("");
+        }
         return;
     }
     Node<R> n;
     pull_all<MODE>(a, (const typename T::S*)a.src, k, (t & F_BOUNDARY) != 0, n);
     const Moments<R> m = moments(n);
+    if (field == 7) {                        // all 13 populations, dense [13][ny][nx]
+        const long long n2 = (long long)a.nx * a.ny;
+        for (int i = 1; i <= 8; i++) out[(i - 1) * n2 + d] = n.h[i];
+        for (int i = 0; i <= 4; i++) out[(8 + i) * n2 + d] = n.g[i];
+        return;
+    }
     if (field == 6) {
         a.uprev[k] = m.ux;
         a.uprev[a.qs + k] = m.uy;
@@ -548,6 +612,30 @@ hipError_t launch_step(int mode, bool reduce, const StepArgs& a, hipStream_t s)
     case 2: return launch_step_t<2>(reduce, a, s);
     }
     return hipErrorInvalidValue;
+}
+
+template <int MODE>
+static hipError_t launch_batch_t(bool reduce, const BatchArgs& b, int grid, hipStream_t s)
+{
+    if (reduce) hipLaunchKernelGGL((batch_step_kernel<MODE, true>), dim3(grid), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((batch_step_kernel<MODE, false>), dim3(grid), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(int mode, bool reduce, const BatchArgs& b, int grid, hipStream_t s)
+{
+    switch (mode) {
+    case 0: return launch_batch_t<0>(reduce, b, grid, s);
+    case 1: return launch_batch_t<1>(reduce, b, grid, s);
+    case 2: return launch_batch_t<2>(reduce, b, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_finish(const BatchArgs& b, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_finish_kernel, dim3(256), dim3(256), 0, s, b);
+    return hipGetLastError();
 }
 
 static dim3 lattice_grid(const StepArgs& a) { return dim3((a.nx + 63) / 64, (a.ny + 3) / 4); }

@@ -1,8 +1,6 @@
 // Host side of the aqlbm C-ABI (include/aqlbm.h): solver creation, device layout,
 // tile lists, HIP-graph chunks, observables and checkpoints.  No kernels live here.
-#include "aq_device.h"
-
-#include "../../include/aqlbm.h"
+#include "aq_internal.h"
 
 #include <algorithm>
 #include <cmath>
@@ -13,7 +11,7 @@
 
 using namespace aq;
 
-namespace {
+namespace aq {
 
 thread_local std::string g_err;
 
@@ -22,89 +20,6 @@ int fail(int code, const std::string& msg)
     g_err = msg;
     return code;
 }
-
-#define HIPCHK(expr)                                                                     \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return fail(AQ_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-size_t storage_size(int mode) { return mode == AQ_F64 ? 8 : (mode == AQ_F32 ? 4 : 2); }
-
-struct Layout {
-    int pitch;
-    long long qs;
-    size_t off_a, off_b, off_type, off_uprev, off_tiles, off_partials, off_counters, off_obs,
-        off_walls, off_scratch, total;
-    int max_tiles;
-};
-
-Layout make_layout(const aq_params& P, int n_walls)
-{
-    Layout L;
-    L.pitch = (int)align_up((size_t)P.nx, 64);
-    // population arrays sit 64*11 elements past a multiple of 64, so the 13 streams of a
-    // node do not start on the same DRAM channel
-    L.qs = (long long)align_up((size_t)P.ny * L.pitch, 64) + 64 * 11;
-    const size_t es = storage_size(P.storage);
-    const size_t pop_bytes = align_up((size_t)NPOP * L.qs * es, 256);
-    L.max_tiles = (int)(((P.nx + 63) / 64) * (size_t)P.ny);   // smallest tile is 64x1
-    size_t o = 0;
-    L.off_a = o; o += pop_bytes;
-    L.off_b = o; o += pop_bytes;
-    L.off_type = o; o += align_up((size_t)L.qs, 256);
-    L.off_uprev = o; o += align_up(3 * (size_t)L.qs * 8, 256);
-    L.off_tiles = o; o += align_up((size_t)L.max_tiles * 4, 256);
-    L.off_partials = o; o += align_up((size_t)L.max_tiles * NRED * 8, 256);
-    L.off_counters = o; o += 256;
-    L.off_obs = o; o += align_up((size_t)OBS_RING * NRED * 8, 256);
-    L.off_walls = o; o += align_up((size_t)std::max(n_walls, 1) * (4 + 4 + 16), 256);
-    L.off_scratch = o; o += align_up((size_t)P.nx * P.ny * 8, 256);
-    L.total = o;
-    return L;
-}
-
-double bytes_per_update(int mode) { return 2.0 * NPOP * storage_size(mode) + 1.0; }
-
-}  // namespace
-
-struct aq_solver {
-    aq_params P;
-    Layout L;
-    int mode;
-    char* base = nullptr;
-    bool own_mem = false;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-
-    std::vector<uint8_t> htype;   // [ny][pitch]
-    int64_t n_active = 0, n_fluid = 0, n_cornea = 0, n_iris = 0;
-    std::vector<int> hwall_node, hwall_id;
-    std::vector<double> hwall_n;
-    int n_walls = 0;
-
-    int tile_x = 64, tile_y = 4, tiles_x = 0, n_tiles = 0, xcd_remap = 1;
-    int cur = 0;                  // 0: buffer A holds the state
-    int64_t step = 0;
-    unsigned int checks = 0;      // reducing launches enqueued
-    int64_t last_check_step = 0;
-    bool diverged = false;
-    double sf = 1, st = 1;        // F16S scales
-    int exp_f = 0, exp_t = 0;
-
-    hipGraphExec_t plain_graph = nullptr;
-    hipGraph_t plain_graph_src = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    double* obs_pinned = nullptr; // host pinned, 2 * NRED
-
-    void* popA() const { return base + L.off_a; }
-    void* popB() const { return base + L.off_b; }
-};
-
-namespace {
 
 StepArgs make_args(const aq_solver* s, bool a_is_src)
 {
@@ -247,7 +162,7 @@ void build_tiles(aq_solver* s, std::vector<int>& tiles)
 
 int upload_tiles(aq_solver* s)
 {
-    std::vector<int> tiles;
+    std::vector<int>& tiles = s->htiles;
     build_tiles(s, tiles);
     if (s->n_tiles > s->L.max_tiles) return fail(AQ_EINVAL, "tile list overflow");
     if (s->n_tiles)
@@ -695,6 +610,35 @@ int aq_time_step_kernel(aq_solver* s, int32_t n_launch, double* ms)
     float t = 0;
     HIPCHK(hipEventElapsedTime(&t, s->ev[0], s->ev[1]));
     *ms = t / n_launch;
+    return AQ_OK;
+}
+
+int aq_autotune_tile(aq_solver* s, int32_t n_launch, int32_t only_256, int32_t* tile_x, int32_t* tile_y,
+                     double* ms_per_launch)
+{
+    if (!s || !tile_x || !tile_y || !ms_per_launch || n_launch < 2 || (n_launch & 1))
+        return fail(AQ_EINVAL, "invalid arguments");
+    static const int cand[6][2] = {{64, 4}, {128, 2}, {256, 1}, {64, 1}, {64, 2}, {128, 1}};
+    const int nc = only_256 ? 3 : 6;
+    int best = -1;
+    double best_ms = 0;
+    for (int c = 0; c < nc; c++) {
+        int rc = aq_set_tile(s, cand[c][0], cand[c][1]);
+        if (rc) return rc;
+        double ms = 0;
+        rc = aq_time_step_kernel(s, 2, &ms);          // warm up
+        if (rc == AQ_OK) rc = aq_time_step_kernel(s, n_launch, &ms);
+        if (rc) return rc;
+        if (best < 0 || ms < best_ms) {
+            best = c;
+            best_ms = ms;
+        }
+    }
+    int rc = aq_set_tile(s, cand[best][0], cand[best][1]);
+    if (rc) return rc;
+    *tile_x = cand[best][0];
+    *tile_y = cand[best][1];
+    *ms_per_launch = best_ms;
     return AQ_OK;
 }
 
