@@ -70,6 +70,35 @@ def cpu_baseline(p, mask, walls, budget_s=12.0):
             "sample": f"{n} time steps of the same 2048x1024 lattice ({act} active nodes), {dt:.1f} s"}
 
 
+def batched_vs_one_at_a_time(n, cap=50000, tol=1e-6):
+    """Solves/s and latency (all requests submitted at t = 0) of n sweep requests
+    (lattices 256x128 .. 1024x512, per-request tau, Da, inflow, angle, Ra, orientation):
+    continuously batched in F32 storage, and the same requests one at a time through the
+    single-lattice FP64 solver.  Each runs to residual tol or cap time steps."""
+    import numpy as np
+    import paper_2102_12663_amd as aq
+    from paper_2102_12663_amd import serve as S
+
+    res = S.sweep(n=n, storage=aq.F32, tol=tol, budget_bytes=16 << 30, max_steps=cap, intervals_per_call=5)
+    recs = res.pop("records")
+    lat, t0 = [], time.perf_counter()
+    conv = 0
+    for i in range(n):
+        p, m, w = S.sweep_request(i, aq.F64)
+        s = aq.Solver(p, m, w)
+        ok, _ = s.run_to_steady(tol, cap)
+        s.close()
+        conv += ok
+        lat.append(time.perf_counter() - t0)
+    wall = time.perf_counter() - t0
+    return {"workload": f"{n} sweep requests (seeds 0..{n - 1}), residual {tol}, cap {cap} time steps",
+            "batched_f32": {"solves_per_s": round(res["solves_per_s"], 3), "p50_s": round(res["latency_p50_s"], 3),
+                            "p99_s": round(res["latency_p99_s"], 3), "converged": res["converged"],
+                            "aggregate_active_mlups": round(res["aggregate_active_mlups"], 1)},
+            "one_at_a_time_f64": {"solves_per_s": round(n / wall, 3), "p50_s": round(float(np.percentile(lat, 50)), 3),
+                                  "p99_s": round(float(np.percentile(lat, 99)), 3), "converged": int(conv)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +111,8 @@ def main():
     ap.add_argument("--tile", default="64x4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra-storages", action="store_true", help="also time f32 and f16s")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-requests", type=int, default=16)
     ap.add_argument("--probe", action="store_true",
                     help="for hardware-counter runs: 10 plain step launches of the workload, then "
                          "3 device copies of 256 MiB (a copy kernel of known size for calibration)")
@@ -182,6 +213,8 @@ def main():
             extra[st] = {"mlups": round(e["mlups"], 1), "kernel_ms": round(e["plain_launch_ms"], 5),
                          "achieved_GBs": round(a2, 1), "frac": round(a2 / HBM_PEAK_GBS, 4)}
         out["other_storages"] = extra
+    if not args.no_batched:
+        out["batched"] = batched_vs_one_at_a_time(args.batched_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r["p"], r["mask"], r["walls"])
     print(json.dumps(out), flush=True)

@@ -263,7 +263,8 @@ int aq_batch_create(size_t budget_bytes, int32_t max_slots, int64_t max_active_n
 
 /* Admit one solve.  Parameters, mask and walls as for aq_create; tile_x * tile_y must be
  * 256.  tol: residual at which the solve is done (an F16S solve first runs to
- * max(tol, 2e-5), its binary16 noise floor); drift_tol: for F16S storage, the largest
+ * max(tol, 2e-5), or until its residual stops falling by 10% over 50 check intervals:
+ * binary16 rounding noise sets a floor); drift_tol: for F16S storage, the largest
  * |Q_out/Q_in - 1| at that point accepted without continuing in F32 to tol; max_steps:
  * step cap; request_id: returned with the result; keep != 0 keeps the finished state
  * readable (aq_batch_read_field) until aq_batch_release.  *slot receives the slot.

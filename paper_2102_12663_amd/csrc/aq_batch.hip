@@ -9,7 +9,8 @@
 //   memory, so admissions and retirements between intervals need no re-capture.
 // - After each call to aq_batch_run the latest reductions of every running instance are
 //   read back in one copy; converged, diverged and capped instances are retired.
-// - An F16S instance whose residual falls below max(tol, 2e-5) passes the IOP drift check
+// - An F16S instance whose residual falls below max(tol, 2e-5), or stops falling for 50
+//   check intervals, passes the IOP drift check
 //   when its outflow balances its inflow (|Q_out/Q_in - 1| <= drift_tol: a steady
 //   pressure level needs exact mass balance, and rounding that does not conserve mass
 //   shows up first as this imbalance); otherwise its state is converted to F32 storage
@@ -25,6 +26,7 @@ namespace {
 // binary16 rounding keeps the per-step residual of an F16S solve above ~1e-6; its phase
 // ends at max(tol, this floor)
 constexpr double kF16ResidFloor = 2e-5;
+constexpr int kF16Stall = 50;
 
 // First-fit allocator over [0, size) with coalescing free blocks (offsets in bytes).
 class Pool {
@@ -85,6 +87,8 @@ private:
 
 struct Slot {
     bool used = false, running = false, done = false, reported = false, keep = false;
+    double best_resid = 1e300;   // F16S phase: smallest residual so far
+    int since_best = 0;          // check intervals since it last fell by 10%
     aq_solver* s = nullptr;
     size_t off = 0, bytes = 0;
     double tol = 0, drift_tol = 0;
@@ -92,6 +96,23 @@ struct Slot {
     int status = AQ_OK, fallback = 0;
     aq_observables obs;
 };
+
+// Has the current phase reached its residual?  F32/F64: max(resid_u, resid_T) < tol.
+// F16S: below max(tol, kF16ResidFloor), or stagnating (no 10% improvement over the last
+// kF16Stall check intervals: binary16 rounding noise sets a problem-dependent floor).
+bool resid_done(Slot& sl, int mode, int n_intervals)
+{
+    const double r = std::max(sl.obs.resid_u, sl.obs.resid_T);
+    if (mode != AQ_F16S) return r < sl.tol;
+    if (r < std::max(sl.tol, kF16ResidFloor)) return true;
+    if (r < 0.9 * sl.best_resid) {
+        sl.best_resid = r;
+        sl.since_best = 0;
+    } else {
+        sl.since_best += n_intervals;
+    }
+    return sl.since_best >= kF16Stall;
+}
 
 }  // namespace
 
@@ -115,6 +136,7 @@ struct aq_batch {
     std::vector<InstDesc> h_inst;
     int n_work[3] = {0, 0, 0};
 
+    int nt_store = 0;               // non-temporal stores for the current working set
     int graph_mask = -1;
     hipGraph_t graph_src = nullptr;
     hipGraphExec_t graph = nullptr;
@@ -133,6 +155,7 @@ BatchArgs batch_args(const aq_batch* b, int mode, int parity)
     a.parity = parity;
     a.max_slots = b->max_slots;
     a.mode = mode;
+    a.nt_store = b->nt_store;
     return a;
 }
 
@@ -192,6 +215,14 @@ int ensure_graph(aq_batch* b)
 int upload_tables(aq_batch* b)
 {
     std::vector<int2> work[3];
+    double bytes = 0;
+    for (const Slot& sl : b->slots)
+        if (sl.used && sl.running) bytes += (double)sl.s->n_active * bytes_per_update(sl.s->mode);
+    const int nt = bytes > kMallBytes ? 1 : 0;
+    if (nt != b->nt_store) {
+        b->nt_store = nt;
+        drop_graph(b);                 // the captured launches bake the store policy in
+    }
     for (int i = 0; i < b->max_slots; i++) {
         InstDesc& d = b->h_inst[i];
         std::memset(&d, 0, sizeof(d));
@@ -199,6 +230,7 @@ int upload_tables(aq_batch* b)
         if (!sl.used || !sl.running) continue;
         const int m = sl.s->mode;
         d.a = make_args(sl.s, true);
+        d.a.nt_store = nt;
         d.work_start = (int)work[m].size();
         d.work_count = sl.s->n_tiles;
         d.running = 1;
@@ -442,7 +474,7 @@ int aq_batch_run(aq_batch* b, int32_t n_intervals)
             sl.status = AQ_EDIVERGED;
             s->diverged = true;
             finish = true;
-        } else if (std::max(sl.obs.resid_u, sl.obs.resid_T) < (s->mode == AQ_F16S ? std::max(sl.tol, kF16ResidFloor) : sl.tol)) {
+        } else if (resid_done(sl, s->mode, n_intervals)) {
             const double imbalance = sl.obs.q_in != 0 ? std::fabs(sl.obs.q_out / sl.obs.q_in - 1.0) : 0.0;
             if (s->mode == AQ_F16S && !(imbalance <= sl.drift_tol)) {
                 rc = convert_to_f32(b, i);

@@ -35,6 +35,7 @@ struct StepArgs {
     const int* tiles;         // active tile indices (ty * tiles_x + tx)
     int n_tiles, tiles_x, tile_x, tile_y;
     int pitch, nx, ny, xcd_remap;
+    int nt_store;             // non-temporal population stores (working set beyond the MALL)
 
     double omega_f, omega_t;  // 1/tau_f, 1/tau_t
     double w0T, wT, inv_cs2T; // thermal weights (rest, axis) and 1/c_sT^2
@@ -75,6 +76,7 @@ struct BatchArgs {
     int parity;                // 0: buffer A is src
     int max_slots;
     int mode;
+    int nt_store;              // non-temporal population stores
 };
 
 // Host-side launchers (defined in aq_kernels.hip).

@@ -3,7 +3,7 @@
 #pragma once
 #include "aq_device.h"
 
-#include "../../include/aqlbm.h"
+#include "aqlbm.h"
 
 #include <algorithm>
 #include <cstring>
@@ -61,6 +61,10 @@ inline Layout make_layout(const aq_params& P, int n_walls)
 
 inline double bytes_per_update(int mode) { return 2.0 * NPOP * storage_size(mode) + 1.0; }
 
+// Working sets (bytes moved per step) above this use non-temporal population stores; the
+// MI355X last-level cache (MALL) holds 256 MB.
+constexpr double kMallBytes = 192.0 * 1024 * 1024;
+
 }  // namespace aq
 
 
@@ -81,6 +85,7 @@ struct aq_solver {
     int n_walls = 0;
 
     int tile_x = 64, tile_y = 4, tiles_x = 0, n_tiles = 0, xcd_remap = 1;
+    int nt_store = 0;
     std::vector<int> htiles;      // active tile indices (host copy of the device list)
     int cur = 0;                  // 0: buffer A holds the state
     int64_t step = 0;

@@ -38,18 +38,24 @@ template <> struct Traits<0> {   // AQ_F64
     using R = double;
     __device__ static R ld(const S* p, R) { return *p; }
     __device__ static void st(S* p, R v, R) { *p = v; }
+    __device__ static S enc(double v, R) { return v; }
+    __device__ static double dec(S s, R) { return s; }
 };
 template <> struct Traits<1> {   // AQ_F32
     using S = float;
     using R = float;
     __device__ static R ld(const S* p, R) { return *p; }
     __device__ static void st(S* p, R v, R) { *p = v; }
+    __device__ static S enc(double v, R) { return (S)v; }
+    __device__ static double dec(S s, R) { return s; }
 };
 template <> struct Traits<2> {   // AQ_F16S: binary16 of (deviation * 2^s)
     using S = _Float16;
     using R = float;
     __device__ static R ld(const S* p, R inv) { return (R)(*p) * inv; }
     __device__ static void st(S* p, R v, R sc) { *p = (S)(v * sc); }
+    __device__ static S enc(double v, R sc) { return (S)((R)v * sc); }
+    __device__ static double dec(S s, R inv) { return (double)((R)s * inv); }
 };
 
 template <typename R> struct Node {
@@ -227,7 +233,23 @@ __device__ __forceinline__ void collide(const StepArgs& a, bool porous, const No
     gs[4] = omTc * n.g[4] + omT * (wT * (m.th - k2 * uy));
 }
 
-template <int MODE>
+// Write the 13 encoded values of a node.  Past the last-level cache (working sets larger
+// than the 256 MB MALL) non-temporal stores keep the written stream from evicting the data
+// the step still has to read; below it, ordinary stores keep the next step's reads cached.
+template <int MODE, bool NT>
+__device__ __forceinline__ void put_all(const StepArgs& a, typename Traits<MODE>::S* dst, int k,
+                                        const typename Traits<MODE>::S* e)
+{
+    if (NT) {
+#pragma unroll
+        for (int i = 0; i < NPOP; i++) __builtin_nontemporal_store(e[i], dst + (long long)i * a.qs + k);
+    } else {
+#pragma unroll
+        for (int i = 0; i < NPOP; i++) dst[(long long)i * a.qs + k] = e[i];
+    }
+}
+
+template <int MODE, bool NT>
 __device__ __forceinline__ void store_all(const StepArgs& a, typename Traits<MODE>::S* dst, int k,
                                           const typename Traits<MODE>::R* hs,
                                           const typename Traits<MODE>::R* gs)
@@ -235,10 +257,63 @@ __device__ __forceinline__ void store_all(const StepArgs& a, typename Traits<MOD
     using T = Traits<MODE>;
     using R = typename T::R;
     const R sf = R(a.sf), st = R(a.st);
+    typename T::S e[NPOP];
 #pragma unroll
-    for (int i = 1; i <= 8; i++) T::st(dst + (long long)(i - 1) * a.qs + k, hs[i], sf);
+    for (int i = 1; i <= 8; i++) e[i - 1] = T::enc((double)hs[i], sf);
 #pragma unroll
-    for (int i = 0; i <= 4; i++) T::st(dst + (8LL + i) * a.qs + k, gs[i], st);
+    for (int i = 0; i <= 4; i++) e[8 + i] = T::enc((double)gs[i], st);
+    put_all<MODE, NT>(a, dst, k, e);
+}
+
+// Reduced-precision store that keeps the node's mass exact.  Collision conserves sum h and
+// sum g, but rounding each post-collision value to the storage format does not, and at a
+// steady state the same rounding repeats every step: a persistent mass source that shifts
+// the pressure level (the IOP) by the source over the outflow resistance.  Here the
+// rounded values are decoded, their sum is compared (in double, exactly for these few
+// terms) with the sum of the node's incoming values, and the difference is added to the
+// value of smallest magnitude, where the format resolves finest.
+template <int MODE, int N>
+__device__ __forceinline__ void conserve_encode(const typename Traits<MODE>::R* in,
+                                                const typename Traits<MODE>::R* out,
+                                                typename Traits<MODE>::S* enc, typename Traits<MODE>::R sc,
+                                                typename Traits<MODE>::R inv)
+{
+    using T = Traits<MODE>;
+    double target = 0.0, sum = 0.0, amin = 0.0;
+    int kmin = 0;
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        target += (double)in[i];
+        enc[i] = T::enc((double)out[i], sc);
+        const double d = T::dec(enc[i], inv);
+        sum += d;
+        if (i == 0 || fabs(d) < amin) {
+            amin = fabs(d);
+            kmin = i;
+        }
+    }
+    const double r = target - sum;
+#pragma unroll
+    for (int i = 0; i < N; i++)
+        if (i == kmin) enc[i] = T::enc(T::dec(enc[i], inv) + r, sc);
+}
+
+template <int MODE, bool NT>
+__device__ __forceinline__ void store_conserving(const StepArgs& a, typename Traits<MODE>::S* dst, int k,
+                                                 const Node<typename Traits<MODE>::R>& n,
+                                                 const typename Traits<MODE>::R* hs,
+                                                 const typename Traits<MODE>::R* gs)
+{
+    using T = Traits<MODE>;
+    using R = typename T::R;
+    if (MODE == 0) {
+        store_all<MODE, NT>(a, dst, k, hs, gs);
+        return;
+    }
+    typename T::S e[NPOP];
+    conserve_encode<MODE, 8>(n.h + 1, hs + 1, e, R(a.sf), R(a.inv_sf));
+    conserve_encode<MODE, 5>(n.g, gs, e + 8, R(a.st), R(a.inv_st));
+    put_all<MODE, NT>(a, dst, k, e);
 }
 
 // ------------------------------------------------------------------------------ reduction
@@ -374,7 +449,7 @@ __device__ __forceinline__ int tile_of_block(const StepArgs& a)
 
 // One tile of one time step: pull, moments, forces, both collisions, store; on check
 // steps also this tile's partial sums (written to `partial`).
-template <int MODE, bool REDUCE>
+template <int MODE, bool REDUCE, bool NT>
 __device__ __forceinline__ void process_tile(const StepArgs& a, int tile, double* partial)
 {
     using T = Traits<MODE>;
@@ -401,7 +476,7 @@ __device__ __forceinline__ void process_tile(const StepArgs& a, int tile, double
         const Moments<R> m = moments(n);
         R hs[9], gs[5];
         collide(a, (t & CLS_MASK) == POROUS, n, m, hs, gs);
-        store_all<MODE>(a, dst, k, hs, gs);
+        store_conserving<MODE, NT>(a, dst, k, n, hs, gs);
         if (REDUCE) {
             const double ux = m.ux, uy = m.uy, th = m.th, dp = m.dp;
             const double Tabs = a.T_ref + th;
@@ -436,32 +511,65 @@ __device__ __forceinline__ void process_tile(const StepArgs& a, int tile, double
 
 // One time step of one lattice: one block per active tile.  The partial of a tile is
 // stored at its index in the tile list.
-template <int MODE, bool REDUCE>
+template <int MODE, bool REDUCE, bool NT>
 __global__ __launch_bounds__(256) void step_kernel(StepArgs a)
 {
     const int ti = tile_of_block(a);
-    process_tile<MODE, REDUCE>(a, a.tiles[ti], a.partials + (long long)ti * NRED);
+    process_tile<MODE, REDUCE, NT>(a, a.tiles[ti], a.partials + (long long)ti * NRED);
+}
+
+// The instance table and the work list do not change during a launch: read them through
+// the constant address space so they land in scalar registers (the host compilation pass
+// only needs a declaration-compatible body).
+__device__ __forceinline__ StepArgs load_desc(const InstDesc* table, int i)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) InstDesc ConstDesc;
+    return ((ConstDesc*)table)[i].a;
+#else
+    return table[i].a;
+#endif
+}
+
+__device__ __forceinline__ int2 load_item(const int2* work, int w)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) int2 ConstItem;
+    return ((ConstItem*)work)[w];
+#else
+    return work[w];
+#endif
 }
 
 // One time step of every running instance of a batch whose storage is MODE.  A fixed grid
 // walks the (slot, tile) work list, which lives in device memory with its length, so a
 // captured graph stays valid while instances are admitted and retired.  Each block takes
-// a contiguous run of work items (neighbouring tiles of one instance stay on one CU).
-template <int MODE, bool REDUCE>
+// a contiguous run of work items (neighbouring tiles of one instance stay on one CU); the
+// next item is fetched while the current tile is processed, and an instance's arguments
+// are reloaded only when the slot changes.
+template <int MODE, bool REDUCE, bool NT>
 __global__ __launch_bounds__(256) void batch_step_kernel(BatchArgs b)
 {
     const int n = *b.n_work;
     const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
     const int w0 = blockIdx.x * per, w1 = min(n, w0 + per);
+    if (w0 >= w1) return;
+    int2 nxt = load_item(b.work, w0);
+    int cur_slot = -1;
+    StepArgs a;
     for (int w = w0; w < w1; w++) {
-        const int2 it = b.work[w];
-        StepArgs a = b.inst[it.x].a;
-        if (b.parity) {
-            void* t = (void*)a.src;
-            a.src = a.dst;
-            a.dst = t;
+        const int2 it = nxt;
+        if (w + 1 < w1) nxt = load_item(b.work, w + 1);
+        if (it.x != cur_slot) {
+            a = load_desc(b.inst, it.x);
+            if (b.parity) {
+                void* t = (void*)a.src;
+                a.src = a.dst;
+                a.dst = t;
+            }
+            cur_slot = it.x;
         }
-        process_tile<MODE, REDUCE>(a, it.y, b.partials + (long long)w * NRED);
+        process_tile<MODE, REDUCE, NT>(a, it.y, b.partials + (long long)w * NRED);
         if (REDUCE) __syncthreads();
     }
 }
@@ -588,46 +696,52 @@ __global__ __launch_bounds__(256) void unpack_kernel(StepArgs a, int field, int 
 }
 
 // ------------------------------------------------------------------------------ launchers
-template <int MODE>
+template <int MODE, bool NT>
 static hipError_t launch_step_t(bool reduce, const StepArgs& a, hipStream_t s)
 {
     const dim3 grid(a.n_tiles), block(a.tile_x * a.tile_y);
     if (a.n_tiles == 0) return hipSuccess;
     if (reduce) {
-        hipLaunchKernelGGL((step_kernel<MODE, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((step_kernel<MODE, true, NT>), grid, block, 0, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, a);
     } else {
-        hipLaunchKernelGGL((step_kernel<MODE, false>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((step_kernel<MODE, false, NT>), grid, block, 0, s, a);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_step(int mode, bool reduce, const StepArgs& a, hipStream_t s)
 {
-    switch (mode) {
-    case 0: return launch_step_t<0>(reduce, a, s);
-    case 1: return launch_step_t<1>(reduce, a, s);
-    case 2: return launch_step_t<2>(reduce, a, s);
+    switch (mode * 2 + (a.nt_store ? 1 : 0)) {
+    case 0: return launch_step_t<0, false>(reduce, a, s);
+    case 1: return launch_step_t<0, true>(reduce, a, s);
+    case 2: return launch_step_t<1, false>(reduce, a, s);
+    case 3: return launch_step_t<1, true>(reduce, a, s);
+    case 4: return launch_step_t<2, false>(reduce, a, s);
+    case 5: return launch_step_t<2, true>(reduce, a, s);
     }
     return hipErrorInvalidValue;
 }
 
-template <int MODE>
+template <int MODE, bool NT>
 static hipError_t launch_batch_t(bool reduce, const BatchArgs& b, int grid, hipStream_t s)
 {
-    if (reduce) hipLaunchKernelGGL((batch_step_kernel<MODE, true>), dim3(grid), dim3(256), 0, s, b);
-    else hipLaunchKernelGGL((batch_step_kernel<MODE, false>), dim3(grid), dim3(256), 0, s, b);
+    if (reduce) hipLaunchKernelGGL((batch_step_kernel<MODE, true, NT>), dim3(grid), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((batch_step_kernel<MODE, false, NT>), dim3(grid), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_step(int mode, bool reduce, const BatchArgs& b, int grid, hipStream_t s)
 {
-    switch (mode) {
-    case 0: return launch_batch_t<0>(reduce, b, grid, s);
-    case 1: return launch_batch_t<1>(reduce, b, grid, s);
-    case 2: return launch_batch_t<2>(reduce, b, grid, s);
+    switch (mode * 2 + (b.nt_store ? 1 : 0)) {
+    case 0: return launch_batch_t<0, false>(reduce, b, grid, s);
+    case 1: return launch_batch_t<0, true>(reduce, b, grid, s);
+    case 2: return launch_batch_t<1, false>(reduce, b, grid, s);
+    case 3: return launch_batch_t<1, true>(reduce, b, grid, s);
+    case 4: return launch_batch_t<2, false>(reduce, b, grid, s);
+    case 5: return launch_batch_t<2, true>(reduce, b, grid, s);
     }
     return hipErrorInvalidValue;
 }

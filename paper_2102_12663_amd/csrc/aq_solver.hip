@@ -39,6 +39,7 @@ StepArgs make_args(const aq_solver* s, bool a_is_src)
     a.nx = P.nx;
     a.ny = P.ny;
     a.xcd_remap = s->xcd_remap;
+    a.nt_store = s->nt_store;
     a.omega_f = 1.0 / P.tau_f;
     a.omega_t = 1.0 / P.tau_t;
     a.w0T = P.w0;
@@ -307,6 +308,8 @@ int setup(aq_solver* s, const uint8_t* mask, const aq_wall_node* walls, int32_t 
                 if (cc != AQ_FLUID && cc != AQ_POROUS) t |= F_BOUNDARY;
             }
         }
+    // the read and written populations of a step exceed the last-level cache: stream the writes
+    s->nt_store = (double)s->n_active * bytes_per_update(s->mode) > kMallBytes ? 1 : 0;
     s->n_walls = n_walls;
     s->hwall_node.resize(std::max(n_walls, 1));
     s->hwall_id.resize(std::max(n_walls, 1));
@@ -440,7 +443,7 @@ int aq_step(aq_solver* s, int64_t nsteps)
     if (!s || nsteps < 0) return fail(AQ_EINVAL, "invalid arguments");
     const int D = s->P.check_interval;
     while (nsteps > 0) {
-        if (s->step % D == 0 && nsteps >= D) {
+        if (s->step % D == 0 && nsteps >= D && s->n_tiles > 0) {
             int rc = ensure_graph(s);
             if (rc) return rc;
             HIPCHK(hipGraphLaunch(s->plain_graph, s->stream));
@@ -647,6 +650,7 @@ int aq_run_intervals_timed(aq_solver* s, int32_t n, double* total_ms, double* pl
     if (!s || !total_ms || !plain_ms || n < 1) return fail(AQ_EINVAL, "invalid arguments");
     const int D = s->P.check_interval;
     if (s->step % D) return fail(AQ_ESTATE, "the step count must be a multiple of check_interval");
+    if (s->n_tiles == 0) return fail(AQ_ESTATE, "the lattice has no active node");
     int rc = ensure_graph(s);
     if (rc) return rc;
     std::vector<hipEvent_t> evs(2 * (size_t)n + 1);

@@ -136,6 +136,7 @@ def test_run_to_steady_and_f16_fallback(aq):
             results[r["request_id"]] = r
         if len(results) == 3:
             break
+    announce(f"[batch] results {results}")
     assert set(results) == {1, 2, 3}
     r1 = results[1]
     assert r1["status"] == aq.AQ_OK

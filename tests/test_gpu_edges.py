@@ -1,0 +1,114 @@
+"""Edge cases of the HIP path: empty and one-node lattices, the paper-exact D2Q4 thermal
+mode, a standing eye (gravity along -x), and properties at the 8192x4096 size."""
+import math
+
+import numpy as np
+import pytest
+
+import aqinputs as A
+import oracle as O
+from gpu_util import announce, field_errors
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def aq():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2102_12663_amd as aq
+    aq.load_library()
+    return aq
+
+
+def _parity(aq, p, mask, walls, steps, tol=1e-12):
+    s = aq.Solver(p, mask, walls)
+    s.step(steps)
+    o = O.Oracle(p, mask, walls).step(steps)
+    err = field_errors(s.fields(), o.fields(), mask, p.T_ref)
+    s.close()
+    return err
+
+
+def test_empty_lattice(aq):
+    """No active node: every call works and the observables stay zero."""
+    mask = np.zeros((32, 70), np.uint8)
+    p = A.Params(nx=70, ny=32, check_interval=10)
+    s = aq.Solver(p, mask, A.no_walls())
+    s.step(35)
+    ob = s.observe()
+    assert ob["step"] == 30 and ob["mass_flow"] == 0 and ob["u_max"] == 0
+    assert np.all(np.isnan(s.read_field("ux")))
+    s.close()
+
+
+def test_single_active_node(aq):
+    """One fluid node surrounded by every kind of link rule (walls, inlet, outlet)."""
+    mask = np.zeros((5, 5), np.uint8)
+    mask[2, 2] = A.encode(A.FLUID)
+    mask[1, 2] = A.encode(A.INLET)
+    mask[2, 3] = A.encode(A.OUTLET)
+    mask[3, 2] = A.encode(A.SOLID, A.WALL_CORNEA)
+    mask[2, 1] = A.encode(A.SOLID, A.WALL_IRIS)
+    p = A.Params(nx=5, ny=5, u_in_y=1e-3, p_out=1 / 3 + 1e-4, gbeta=1e-3, check_interval=10, T_init=0.3)
+    err = _parity(aq, p, mask, A.no_walls(), 100)
+    assert all(v <= 1e-12 for v in err.values()), err
+
+
+def test_paper_d2q4_thermal_mode(aq):
+    """w0 = 0: the thermal lattice is the paper's D2Q4 (eq. 11-14) exactly."""
+    p, mask, walls, geo = A.config0()
+    p.w0 = 0.0
+    err = _parity(aq, p, mask, walls, 1000)
+    assert all(v <= 1e-12 for v in err.values()), err
+
+
+def test_standing_eye_gravity_along_x(aq):
+    """Standing orientation (section 3.1): gravity along -x, one vortex."""
+    p, mask, walls, geo = A.config0()
+    p.gravity_angle = math.pi / 2
+    p.gbeta *= 10
+    err = _parity(aq, p, mask, walls, 1000)
+    assert all(v <= 1e-12 for v in err.values()), err
+
+
+def test_config2_size_fp64_parity_100_steps(aq):
+    """8192x4096 (33.5M nodes), FP64, 100 steps: every field vs the oracle."""
+    p, mask, walls, geo = A.sweep_instance(0, 8192, 4096)
+    announce("[edges] 8192x4096 oracle run (CPU)")
+    err = _parity(aq, p, mask, walls, 100)
+    announce(f"[edges] 8192x4096 errors {err}")
+    assert all(v <= 1e-12 for v in err.values()), err
+
+
+@pytest.mark.parametrize("storage", [A.F64, A.F32, A.F16S])
+def test_config2_size_mirror_symmetry(aq, storage):
+    """Gravity along -y and a mirror-symmetric section: the state stays mirror symmetric
+    at 8192x4096 (u_x odd, the rest even) in every storage."""
+    p, mask, walls, geo = A.sweep_instance(0, 8192, 4096, storage=storage)
+    s = aq.Solver(p, mask, walls)
+    s.step(600)
+    act = A.active(mask)
+    dp, ux, uy, T = s.fields()
+    tol = {A.F64: 1e-11, A.F32: 1e-5, A.F16S: 1e-2}[storage]
+    for F, sign in ((dp, 1), (ux, -1), (uy, 1), (T - p.T_ref, 1)):
+        sc = np.max(np.abs(F[act]))
+        assert np.max(np.abs(F[act] - sign * F[:, ::-1][act])) <= tol * sc
+    s.close()
+
+
+def test_full_box_conservation_8192(aq):
+    """All-interior box at 8192x4096 with buoyancy: sum h and sum g stay fixed."""
+    nx, ny = 8192, 4096
+    mask = A.box_mask(nx, ny)
+    p = A.Params(nx=nx, ny=ny, gbeta=1e-4, check_interval=100, T_init=0.7, T_cornea=0.0)
+    s = aq.Solver(p, mask, A.no_walls())
+    s.step(100)
+    a = s.observe()
+    s.step(1000)
+    b = s.observe()
+    assert abs(b["mass_thermal"] - a["mass_thermal"]) <= 1e-12 * abs(a["mass_thermal"])
+    assert abs(b["mass_flow"] - a["mass_flow"]) <= 1e-8
+    s.close()
