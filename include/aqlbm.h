@@ -216,6 +216,15 @@ int aq_set_tile(aq_solver* s, int32_t tile_x, int32_t tile_y);
  * advances by n_launch steps (n_launch must be even). */
 int aq_time_step_kernel(aq_solver* s, int32_t n_launch, double* ms_per_launch);
 
+/* Two-steps-per-launch (temporal blocking) on the plain steps of each check interval: on
+ * (enable != 0, the default) or off.  Results are bitwise the same either way. */
+int aq_set_fusion(aq_solver* s, int32_t enable);
+
+/* Time n_launch back-to-back two-step launches (HIP events on the solver's stream);
+ * *ms_per_launch receives the average per launch (two time steps).  One single step
+ * follows, untimed.  The state advances by 2 * n_launch + 1 steps without reductions. */
+int aq_time_fused_kernel(aq_solver* s, int32_t n_launch, double* ms_per_launch);
+
 /* Whole-interval graph replays with HIP events around the non-reducing part of each
  * interval: runs n_intervals * check_interval steps (the current step must be a multiple
  * of check_interval) and returns the total elapsed milliseconds and the milliseconds

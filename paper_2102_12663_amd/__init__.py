@@ -25,7 +25,8 @@ FIELDS = {"p": 0, "ux": 1, "uy": 2, "T": 3, "pop_flow": 4, "pop_heat": 5}
 EXPORTS = ("aq_version", "aq_last_error", "aq_required_bytes", "aq_create", "aq_create_ext",
            "aq_destroy", "aq_step", "aq_run_to_steady", "aq_observe", "aq_read_field",
            "aq_write_populations", "aq_save", "aq_load", "aq_get_info", "aq_set_tile",
-           "aq_time_step_kernel", "aq_run_intervals_timed", "aq_autotune_tile",
+           "aq_time_step_kernel", "aq_run_intervals_timed", "aq_autotune_tile", "aq_set_fusion",
+           "aq_time_fused_kernel",
            "aq_batch_create", "aq_batch_admit", "aq_batch_run", "aq_batch_poll", "aq_batch_read_field",
            "aq_batch_observe", "aq_batch_release", "aq_batch_get_info", "aq_batch_destroy")
 
@@ -124,6 +125,8 @@ def load_library(path: str = LIB_PATH):
     L.aq_time_step_kernel.argtypes = [vp, i32, dp]
     L.aq_run_intervals_timed.argtypes = [vp, i32, dp, dp]
     ip = C.POINTER(i32)
+    L.aq_set_fusion.argtypes = [vp, i32]
+    L.aq_time_fused_kernel.argtypes = [vp, i32, dp]
     L.aq_autotune_tile.argtypes = [vp, i32, i32, ip, ip, dp]
     L.aq_batch_create.argtypes = [sz, i32, i64, i32, i32, vp, C.POINTER(vp)]
     L.aq_batch_admit.argtypes = [vp, C.POINTER(AqParams), vp, vp, i32, i32, i32, C.c_double, C.c_double,
@@ -269,6 +272,14 @@ class Solver:
     # --- tuning and timing
     def set_tile(self, tx: int, ty: int):
         _check(_lib.aq_set_tile(self._h, int(tx), int(ty)))
+
+    def set_fusion(self, enable: bool):
+        _check(_lib.aq_set_fusion(self._h, int(bool(enable))))
+
+    def time_fused_kernel(self, n_launch: int) -> float:
+        ms = C.c_double()
+        _check(_lib.aq_time_fused_kernel(self._h, int(n_launch), C.byref(ms)))
+        return ms.value
 
     def time_step_kernel(self, n_launch: int) -> float:
         ms = C.c_double()

@@ -11,6 +11,9 @@ SOURCES = [os.path.join(HERE, "csrc", f) for f in ("aq_kernels.hip", "aq_solver.
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
+    # no implicit multiply-add contraction: the kernels write their fused multiply-adds
+    # explicitly, so every kernel that inlines the same step rounds it identically
+    "-ffp-contract=off",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",

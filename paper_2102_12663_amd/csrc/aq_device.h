@@ -82,6 +82,9 @@ struct BatchArgs {
 // Host-side launchers (defined in aq_kernels.hip).
 hipError_t launch_step(int mode, bool reduce, const StepArgs& a, hipStream_t s);
 hipError_t launch_batch_step(int mode, bool reduce, const BatchArgs& b, int grid, hipStream_t s);
+// Two plain time steps in one launch (tiles 64 x fused_tile_rows(mode) from a.tiles).
+hipError_t launch_step2(int mode, const StepArgs& a, hipStream_t s);
+int fused_tile_rows(int mode);
 hipError_t launch_batch_finish(const BatchArgs& b, hipStream_t s);
 // Write into a.dst the buffer whose pull gives the pre-collision populations `pops`
 // (dense [13][ny][nx] doubles), or, if pops is null, the rest equilibrium with

@@ -29,9 +29,9 @@ inline size_t storage_size(int mode) { return mode == AQ_F64 ? 8 : (mode == AQ_F
 struct Layout {
     int pitch;
     long long qs;
-    size_t off_a, off_b, off_type, off_uprev, off_tiles, off_partials, off_counters, off_obs,
+    size_t off_a, off_b, off_type, off_uprev, off_tiles, off_tiles2, off_partials, off_counters, off_obs,
         off_walls, off_scratch, total;
-    int max_tiles;
+    int max_tiles, max_tiles2;
 };
 
 inline Layout make_layout(const aq_params& P, int n_walls)
@@ -50,6 +50,8 @@ inline Layout make_layout(const aq_params& P, int n_walls)
     L.off_type = o; o += align_up((size_t)L.qs, 256);
     L.off_uprev = o; o += align_up(3 * (size_t)L.qs * 8, 256);
     L.off_tiles = o; o += align_up((size_t)L.max_tiles * 4, 256);
+    L.max_tiles2 = (int)(((P.nx + 63) / 64) * (size_t)((P.ny + 3) / 4));   // fused tiles are 64 x >= 4
+    L.off_tiles2 = o; o += align_up((size_t)L.max_tiles2 * 4, 256);
     L.off_partials = o; o += align_up((size_t)L.max_tiles * NRED * 8, 256);
     L.off_counters = o; o += 256;
     L.off_obs = o; o += align_up((size_t)OBS_RING * NRED * 8, 256);
@@ -86,6 +88,9 @@ struct aq_solver {
 
     int tile_x = 64, tile_y = 4, tiles_x = 0, n_tiles = 0, xcd_remap = 1;
     int nt_store = 0;
+    int fuse = 1;                 // two steps per launch on the plain steps of an interval
+    std::vector<int> htiles2;     // active 64 x fused_tile_rows tiles
+    int tiles_x2 = 0, n_tiles2 = 0;
     std::vector<int> htiles;      // active tile indices (host copy of the device list)
     int cur = 0;                  // 0: buffer A holds the state
     int64_t step = 0;
@@ -95,8 +100,8 @@ struct aq_solver {
     double sf = 1, st = 1;        // F16S scales
     int exp_f = 0, exp_t = 0;
 
-    hipGraphExec_t plain_graph = nullptr;
-    hipGraph_t plain_graph_src = nullptr;
+    hipGraphExec_t plain_graph[2] = {nullptr, nullptr};   // by the buffer holding the state
+    hipGraph_t plain_graph_src[2] = {nullptr, nullptr};
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     double* obs_pinned = nullptr; // host pinned, 2 * NRED
 

@@ -37,6 +37,7 @@ template <> struct Traits<0> {   // AQ_F64
     using S = double;
     using R = double;
     __device__ static R ld(const S* p, R) { return *p; }
+    __device__ static R ldv(S v, R) { return v; }
     __device__ static void st(S* p, R v, R) { *p = v; }
     __device__ static S enc(double v, R) { return v; }
     __device__ static double dec(S s, R) { return s; }
@@ -45,6 +46,7 @@ template <> struct Traits<1> {   // AQ_F32
     using S = float;
     using R = float;
     __device__ static R ld(const S* p, R) { return *p; }
+    __device__ static R ldv(S v, R) { return v; }
     __device__ static void st(S* p, R v, R) { *p = v; }
     __device__ static S enc(double v, R) { return (S)v; }
     __device__ static double dec(S s, R) { return s; }
@@ -53,6 +55,7 @@ template <> struct Traits<2> {   // AQ_F16S: binary16 of (deviation * 2^s)
     using S = _Float16;
     using R = float;
     __device__ static R ld(const S* p, R inv) { return (R)(*p) * inv; }
+    __device__ static R ldv(S v, R inv) { return (R)v * inv; }
     __device__ static void st(S* p, R v, R sc) { *p = (S)(v * sc); }
     __device__ static S enc(double v, R sc) { return (S)((R)v * sc); }
     __device__ static double dec(S s, R inv) { return (double)((R)s * inv); }
@@ -154,7 +157,7 @@ __device__ __forceinline__ Moments<R> moments(const Node<R>& n)
     m.sum = ((h[1] + h[2]) + (h[3] + h[4])) + ((h[5] + h[6]) + (h[7] + h[8]));
     m.ux = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
     m.uy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
-    m.uu = m.ux * m.ux + m.uy * m.uy;
+    m.uu = fma(m.ux, m.ux, m.uy * m.uy);
     // p - p_ref = c^2/(4 sigma) [sum h_i + S_0(u)], S_0 = -(2/3)|u|^2, sigma = 5/12
     m.dp = R(0.6) * (m.sum - R(2.0 / 3.0) * m.uu);
     m.th = (n.g[0] + n.g[1]) + (n.g[2] + n.g[3]) + n.g[4];
@@ -184,53 +187,53 @@ __device__ __forceinline__ void collide(const StepArgs& a, bool porous, const No
     // eq. 7-8 equilibria, eq. 6 relaxation, eq. 17 / drag force terms
     {
         const R eu = ux;
-        const R heq = l1 + w1 * (R(3) * eu + R(4.5) * eu * eu - u15);
-        hs[1] = omc * n.h[1] + om * heq + (R(0.5) * Bx + d3 * Dx);
+        const R heq = fma(w1, fma(R(4.5) * eu, eu, R(3) * eu) - u15, l1);
+        hs[1] = fma(omc, n.h[1], fma(om, heq, ((R(0.5) * Bx + d3 * Dx))));
     }
     {
         const R eu = uy;
-        const R heq = l1 + w1 * (R(3) * eu + R(4.5) * eu * eu - u15);
-        hs[2] = omc * n.h[2] + om * heq + (R(0.5) * By + d3 * Dy);
+        const R heq = fma(w1, fma(R(4.5) * eu, eu, R(3) * eu) - u15, l1);
+        hs[2] = fma(omc, n.h[2], fma(om, heq, ((R(0.5) * By + d3 * Dy))));
     }
     {
         const R eu = -ux;
-        const R heq = l1 + w1 * (R(3) * eu + R(4.5) * eu * eu - u15);
-        hs[3] = omc * n.h[3] + om * heq - (R(0.5) * Bx + d3 * Dx);
+        const R heq = fma(w1, fma(R(4.5) * eu, eu, R(3) * eu) - u15, l1);
+        hs[3] = fma(omc, n.h[3], fma(om, heq, -((R(0.5) * Bx + d3 * Dx))));
     }
     {
         const R eu = -uy;
-        const R heq = l1 + w1 * (R(3) * eu + R(4.5) * eu * eu - u15);
-        hs[4] = omc * n.h[4] + om * heq - (R(0.5) * By + d3 * Dy);
+        const R heq = fma(w1, fma(R(4.5) * eu, eu, R(3) * eu) - u15, l1);
+        hs[4] = fma(omc, n.h[4], fma(om, heq, -((R(0.5) * By + d3 * Dy))));
     }
     {
         const R eu = ux + uy;
-        const R heq = l5 + w5 * (R(3) * eu + R(4.5) * eu * eu - u15);
-        hs[5] = omc * n.h[5] + om * heq + d12 * (Dx + Dy);
+        const R heq = fma(w5, fma(R(4.5) * eu, eu, R(3) * eu) - u15, l5);
+        hs[5] = fma(omc, n.h[5], fma(om, heq, (d12 * (Dx + Dy))));
     }
     {
         const R eu = uy - ux;
-        const R heq = l5 + w5 * (R(3) * eu + R(4.5) * eu * eu - u15);
-        hs[6] = omc * n.h[6] + om * heq + d12 * (Dy - Dx);
+        const R heq = fma(w5, fma(R(4.5) * eu, eu, R(3) * eu) - u15, l5);
+        hs[6] = fma(omc, n.h[6], fma(om, heq, (d12 * (Dy - Dx))));
     }
     {
         const R eu = -ux - uy;
-        const R heq = l5 + w5 * (R(3) * eu + R(4.5) * eu * eu - u15);
-        hs[7] = omc * n.h[7] + om * heq - d12 * (Dx + Dy);
+        const R heq = fma(w5, fma(R(4.5) * eu, eu, R(3) * eu) - u15, l5);
+        hs[7] = fma(omc, n.h[7], fma(om, heq, -(d12 * (Dx + Dy))));
     }
     {
         const R eu = ux - uy;
-        const R heq = l5 + w5 * (R(3) * eu + R(4.5) * eu * eu - u15);
-        hs[8] = omc * n.h[8] + om * heq + d12 * (Dx - Dy);
+        const R heq = fma(w5, fma(R(4.5) * eu, eu, R(3) * eu) - u15, l5);
+        hs[8] = fma(omc, n.h[8], fma(om, heq, (d12 * (Dx - Dy))));
     }
     // eq. 11-12: thermal relaxation toward w_i [(T - T_ref) + T e_i.u / c_sT^2]
     const R omT = R(a.omega_t), omTc = R(1) - omT;
     const R T = R(a.T_ref) + m.th;
     const R wT = R(a.wT), k2 = R(a.inv_cs2T) * T;
-    gs[0] = omTc * n.g[0] + omT * (R(a.w0T) * m.th);
-    gs[1] = omTc * n.g[1] + omT * (wT * (m.th + k2 * ux));
-    gs[2] = omTc * n.g[2] + omT * (wT * (m.th + k2 * uy));
-    gs[3] = omTc * n.g[3] + omT * (wT * (m.th - k2 * ux));
-    gs[4] = omTc * n.g[4] + omT * (wT * (m.th - k2 * uy));
+    gs[0] = fma(omTc, n.g[0], omT * (R(a.w0T) * m.th));
+    gs[1] = fma(omTc, n.g[1], omT * (wT * fma(k2, ux, m.th)));
+    gs[2] = fma(omTc, n.g[2], omT * (wT * fma(k2, uy, m.th)));
+    gs[3] = fma(omTc, n.g[3], omT * (wT * fma(-k2, ux, m.th)));
+    gs[4] = fma(omTc, n.g[4], omT * (wT * fma(-k2, uy, m.th)));
 }
 
 // Write the 13 encoded values of a node.  Past the last-level cache (working sets larger
@@ -584,6 +587,178 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(BatchArgs b)
                    b.latest + (long long)sl * NRED);
     }
 }
+
+// ------------------------------------------------------------------------------ two steps per launch
+// Temporal blocking: one launch advances a 64 x TY tile by two time steps.  Step A
+// computes step n+1 on the tile plus a one-node halo (pulling from global memory), keeps
+// it in LDS, and step B computes step n+2 on the tile from LDS and stores it.  The
+// intermediate values are rounded to the storage format exactly as a store and reload
+// through HBM would round them (including the mass-conserving encode), so two fused steps
+// are bitwise identical to two single-step launches while the intermediate state never
+// travels to HBM.
+template <int MODE> struct Fuse {
+    static constexpr int TY = (MODE == 0) ? 4 : 8;   // output rows per tile
+    static constexpr int EW = 66, EH = TY + 2;        // tile plus a one-node halo
+    static constexpr int EN = EW * EH;
+};
+
+template <int MODE>
+__device__ __forceinline__ int lds_at(int q, int ly, int lx)
+{
+    return (q * Fuse<MODE>::EH + ly) * Fuse<MODE>::EW + lx;
+}
+
+// Pull from the LDS image of step n+1 (E coordinates: the tile node is (ex, ey)).
+template <int MODE>
+__device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Traits<MODE>::R* lds, int k, int ex,
+                                         int ey, bool boundary, Node<typename Traits<MODE>::R>& n)
+{
+    using R = typename Traits<MODE>::R;
+    uint8_t nt[9];
+    if (boundary) {
+#pragma unroll
+        for (int i = 1; i <= 8; i++) nt[i] = a.type[k - EY[i] * a.pitch - EX[i]];
+    } else {
+#pragma unroll
+        for (int i = 1; i <= 8; i++) nt[i] = FLUID;
+    }
+    bool up[9];
+#pragma unroll
+    for (int i = 1; i <= 8; i++) up[i] = is_active(nt[i]);
+#pragma unroll
+    for (int i = 1; i <= 8; i++)
+        n.h[i] = up[i] ? lds[lds_at<MODE>(i - 1, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE>(OPP[i] - 1, ey, ex)];
+    n.g[0] = lds[lds_at<MODE>(8, ey, ex)];
+#pragma unroll
+    for (int i = 1; i <= 4; i++)
+        n.g[i] = up[i] ? lds[lds_at<MODE>(8 + i, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE>(8 + OPP[i], ey, ex)];
+    n.qin = R(0);
+    n.qout = R(0);
+    if (!boundary) return;
+#pragma unroll
+    for (int i = 1; i <= 8; i++) {
+        if (up[i]) continue;
+        const uint8_t c = nt[i] & CLS_MASK;
+        const R v = n.h[i];
+        if (c == INLET) {
+            const R corr = R(6.0) * wflow<R>(i) * (R(EX[i]) * R(a.uin_x) + R(EY[i]) * R(a.uin_y));
+            n.h[i] = v + corr;
+        } else if (c == OUTLET) {
+            n.h[i] = -v + R(2.0) * lam<R>(i) * R(a.dp_out);
+        }
+    }
+#pragma unroll
+    for (int i = 1; i <= 4; i++) {
+        if (up[i]) continue;
+        const uint8_t c = nt[i] & CLS_MASK;
+        const uint8_t wall = (nt[i] >> WALL_SHIFT) & 3;
+        if (c == INLET || (c == SOLID && wall != WALL_BOX)) {
+            const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
+            n.g[i] = -n.g[i] + R(2.0) * R(a.wT) * R(tw);
+        }
+    }
+}
+
+// Encode the post-collision values exactly as the single-step store would (the same
+// mass-conserving rounding), and return them decoded, as the next step would load them.
+template <int MODE>
+__device__ __forceinline__ void encode_decoded(const StepArgs& a, const Node<typename Traits<MODE>::R>& n,
+                                               const typename Traits<MODE>::R* hs, const typename Traits<MODE>::R* gs,
+                                               typename Traits<MODE>::S* e)
+{
+    using T = Traits<MODE>;
+    using R = typename T::R;
+    if (MODE == 0) {
+#pragma unroll
+        for (int i = 1; i <= 8; i++) e[i - 1] = T::enc((double)hs[i], R(a.sf));
+#pragma unroll
+        for (int i = 0; i <= 4; i++) e[8 + i] = T::enc((double)gs[i], R(a.st));
+    } else {
+        conserve_encode<MODE, 8>(n.h + 1, hs + 1, e, R(a.sf), R(a.inv_sf));
+        conserve_encode<MODE, 5>(n.g, gs, e + 8, R(a.st), R(a.inv_st));
+    }
+}
+
+template <int MODE, bool NT>
+__device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typename Traits<MODE>::R* lds)
+{
+    using T = Traits<MODE>;
+    using R = typename T::R;
+    using F = Fuse<MODE>;
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int x0 = tx * 64, y0 = ty * F::TY;
+    const typename T::S* src = (const typename T::S*)a.src;
+    typename T::S* dst = (typename T::S*)a.dst;
+    // step A: step n+1 on the tile and its halo, into LDS
+    for (int e = threadIdx.x; e < F::EN; e += 256) {
+        const int ex = e % F::EW, ey = e / F::EW;
+        const int x = x0 - 1 + ex, y = y0 - 1 + ey;
+        if (x < 0 || y < 0 || x >= a.nx || y >= a.ny) continue;
+        const int k = y * a.pitch + x;
+        const uint8_t t = a.type[k];
+        if (!is_active(t)) continue;
+        Node<R> n;
+        pull_all<MODE>(a, src, k, (t & F_BOUNDARY) != 0, n);
+        const Moments<R> m = moments(n);
+        R hs[9], gs[5];
+        collide(a, (t & CLS_MASK) == POROUS, n, m, hs, gs);
+        typename T::S enc[NPOP];
+        encode_decoded<MODE>(a, n, hs, gs, enc);
+#pragma unroll
+        for (int q = 0; q < 8; q++) lds[lds_at<MODE>(q, ey, ex)] = T::ldv(enc[q], R(a.inv_sf));
+#pragma unroll
+        for (int q = 8; q < NPOP; q++) lds[lds_at<MODE>(q, ey, ex)] = T::ldv(enc[q], R(a.inv_st));
+    }
+    __syncthreads();
+    // step B: step n+2 on the tile, from LDS, to global memory
+#pragma unroll
+    for (int r = 0; r < F::TY / 4; r++) {
+        const int lx = threadIdx.x & 63, ly = (threadIdx.x >> 6) + 4 * r;
+        const int x = x0 + lx, y = y0 + ly;
+        if (x >= a.nx || y >= a.ny) continue;
+        const int k = y * a.pitch + x;
+        const uint8_t t = a.type[k];
+        if (!is_active(t)) continue;
+        Node<R> n;
+        pull_lds<MODE>(a, lds, k, lx + 1, ly + 1, (t & F_BOUNDARY) != 0, n);
+        const Moments<R> m = moments(n);
+        R hs[9], gs[5];
+        collide(a, (t & CLS_MASK) == POROUS, n, m, hs, gs);
+        store_conserving<MODE, NT>(a, dst, k, n, hs, gs);
+    }
+}
+
+// Two time steps of one lattice; one block per active 64 x TY tile (tile list in
+// a.tiles, laid out with a.tiles_x = ceil(nx / 64) tiles per row).
+template <int MODE, bool NT>
+__global__ __launch_bounds__(256) void step2_kernel(StepArgs a)
+{
+    __shared__ typename Traits<MODE>::R lds[NPOP * Fuse<MODE>::EN];
+    process_tile2<MODE, NT>(a, a.tiles[tile_of_block(a)], lds);
+}
+
+template <int MODE, bool NT>
+static hipError_t launch_step2_t(const StepArgs& a, hipStream_t s)
+{
+    if (a.n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL((step2_kernel<MODE, NT>), dim3(a.n_tiles), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_step2(int mode, const StepArgs& a, hipStream_t s)
+{
+    switch (mode * 2 + (a.nt_store ? 1 : 0)) {
+    case 0: return launch_step2_t<0, false>(a, s);
+    case 1: return launch_step2_t<0, true>(a, s);
+    case 2: return launch_step2_t<1, false>(a, s);
+    case 3: return launch_step2_t<1, true>(a, s);
+    case 4: return launch_step2_t<2, false>(a, s);
+    case 5: return launch_step2_t<2, true>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+int fused_tile_rows(int mode) { return mode == 0 ? Fuse<0>::TY : Fuse<1>::TY; }
 
 // ------------------------------------------------------------------------------ scatter / unpack
 // The state after step N is kept as two buffers: `cur` holds the post-collision

@@ -74,6 +74,18 @@ StepArgs make_args(const aq_solver* s, bool a_is_src)
     return a;
 }
 
+// Arguments of the two-steps-per-launch kernel: the same lattice with the fused tile list.
+StepArgs make_args2(const aq_solver* s, bool a_is_src)
+{
+    StepArgs a = make_args(s, a_is_src);
+    a.tiles = (const int*)(s->base + s->L.off_tiles2);
+    a.n_tiles = s->n_tiles2;
+    a.tiles_x = s->tiles_x2;
+    a.tile_x = 64;
+    a.tile_y = fused_tile_rows(s->mode);
+    return a;
+}
+
 int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls)
 {
     if (!P || !mask) return fail(AQ_EINVAL, "null params or mask");
@@ -142,22 +154,29 @@ void choose_scales(aq_solver* s)
     }
 }
 
-void build_tiles(aq_solver* s, std::vector<int>& tiles)
+// Active tiles of shape tw x th in row-major order; returns the tiles per row.
+int list_tiles(const aq_solver* s, int tw, int th, std::vector<int>& tiles)
 {
     const int nx = s->P.nx, ny = s->P.ny, pitch = s->L.pitch;
-    s->tiles_x = (nx + s->tile_x - 1) / s->tile_x;
-    const int tiles_y = (ny + s->tile_y - 1) / s->tile_y;
+    const int tiles_x = (nx + tw - 1) / tw;
+    const int tiles_y = (ny + th - 1) / th;
     tiles.clear();
     for (int ty = 0; ty < tiles_y; ty++)
-        for (int tx = 0; tx < s->tiles_x; tx++) {
+        for (int tx = 0; tx < tiles_x; tx++) {
             bool any = false;
-            for (int y = ty * s->tile_y; y < std::min(ny, (ty + 1) * s->tile_y) && !any; y++)
-                for (int x = tx * s->tile_x; x < std::min(nx, (tx + 1) * s->tile_x); x++) {
+            for (int y = ty * th; y < std::min(ny, (ty + 1) * th) && !any; y++)
+                for (int x = tx * tw; x < std::min(nx, (tx + 1) * tw); x++) {
                     const int c = s->htype[(size_t)y * pitch + x] & CLS_MASK;
                     if (c == FLUID || c == POROUS) { any = true; break; }
                 }
-            if (any) tiles.push_back(ty * s->tiles_x + tx);
+            if (any) tiles.push_back(ty * tiles_x + tx);
         }
+    return tiles_x;
+}
+
+void build_tiles(aq_solver* s, std::vector<int>& tiles)
+{
+    s->tiles_x = list_tiles(s, s->tile_x, s->tile_y, tiles);
     s->n_tiles = (int)tiles.size();
 }
 
@@ -168,32 +187,61 @@ int upload_tiles(aq_solver* s)
     if (s->n_tiles > s->L.max_tiles) return fail(AQ_EINVAL, "tile list overflow");
     if (s->n_tiles)
         HIPCHK(hipMemcpyAsync(s->base + s->L.off_tiles, tiles.data(), tiles.size() * 4, hipMemcpyHostToDevice, s->stream));
+    s->tiles_x2 = list_tiles(s, 64, fused_tile_rows(s->mode), s->htiles2);
+    s->n_tiles2 = (int)s->htiles2.size();
+    if (s->n_tiles2 > s->L.max_tiles2) return fail(AQ_EINVAL, "fused tile list overflow");
+    if (s->n_tiles2)
+        HIPCHK(hipMemcpyAsync(s->base + s->L.off_tiles2, s->htiles2.data(), s->htiles2.size() * 4, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     return AQ_OK;
 }
 
 void drop_graph(aq_solver* s)
 {
-    if (s->plain_graph) (void)hipGraphExecDestroy(s->plain_graph);
-    if (s->plain_graph_src) (void)hipGraphDestroy(s->plain_graph_src);
-    s->plain_graph = nullptr;
-    s->plain_graph_src = nullptr;
+    for (int p = 0; p < 2; p++) {
+        if (s->plain_graph[p]) (void)hipGraphExecDestroy(s->plain_graph[p]);
+        if (s->plain_graph_src[p]) (void)hipGraphDestroy(s->plain_graph_src[p]);
+        s->plain_graph[p] = nullptr;
+        s->plain_graph_src[p] = nullptr;
+    }
 }
 
-// Capture the check_interval - 1 non-reducing steps of an interval (starting from
-// buffer A) as one graph.
-int ensure_graph(aq_solver* s)
+// The plain (non-reducing) part of a check interval: check_interval - 1 steps, as
+// (check_interval - 2)/2 two-step launches and one single step when fusion is on (the
+// interval must end with a single step so the previous buffer pulls back to the current
+// state), else as single steps.  Returns the number of buffer swaps.
+int plain_part_swaps(const aq_solver* s)
 {
-    if (s->plain_graph) return AQ_OK;
     const int n = s->P.check_interval - 1;
-    HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-    bool a_src = true;
-    hipError_t err = hipSuccess;
-    for (int i = 0; i < n && err == hipSuccess; i++) {
-        StepArgs a = make_args(s, a_src);
-        err = launch_step(s->mode, false, a, s->stream);
+    return s->fuse ? (n - 1) / 2 + 1 : n;
+}
+
+int enqueue_plain_part(aq_solver* s, int cur, hipError_t* err)
+{
+    const int n = s->P.check_interval - 1;
+    bool a_src = cur == 0;
+    *err = hipSuccess;
+    int left = n;
+    if (s->fuse) {
+        for (; left >= 3 && *err == hipSuccess; left -= 2) {
+            *err = launch_step2(s->mode, make_args2(s, a_src), s->stream);
+            a_src = !a_src;
+        }
+    }
+    for (; left > 0 && *err == hipSuccess; left--) {
+        *err = launch_step(s->mode, false, make_args(s, a_src), s->stream);
         a_src = !a_src;
     }
+    return AQ_OK;
+}
+
+// Capture the plain part of an interval starting from buffer `cur` as one graph.
+int ensure_graph(aq_solver* s, int cur)
+{
+    if (s->plain_graph[cur]) return AQ_OK;
+    HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    enqueue_plain_part(s, cur, &err);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s->stream, &g);
     if (err != hipSuccess) {
@@ -207,8 +255,8 @@ int ensure_graph(aq_solver* s)
         (void)hipGraphDestroy(g);
         return fail(AQ_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
     }
-    s->plain_graph_src = g;
-    s->plain_graph = ge;
+    s->plain_graph_src[cur] = g;
+    s->plain_graph[cur] = ge;
     return AQ_OK;
 }
 
@@ -444,10 +492,10 @@ int aq_step(aq_solver* s, int64_t nsteps)
     const int D = s->P.check_interval;
     while (nsteps > 0) {
         if (s->step % D == 0 && nsteps >= D && s->n_tiles > 0) {
-            int rc = ensure_graph(s);
+            int rc = ensure_graph(s, s->cur);
             if (rc) return rc;
-            HIPCHK(hipGraphLaunch(s->plain_graph, s->stream));
-            s->cur ^= 1;              // D - 1 (odd) steps
+            HIPCHK(hipGraphLaunch(s->plain_graph[s->cur], s->stream));
+            s->cur ^= plain_part_swaps(s) & 1;
             s->step += D - 1;
             rc = launch_one(s);       // the reducing step
             if (rc) return rc;
@@ -616,6 +664,37 @@ int aq_time_step_kernel(aq_solver* s, int32_t n_launch, double* ms)
     return AQ_OK;
 }
 
+int aq_set_fusion(aq_solver* s, int32_t enable)
+{
+    if (!s) return fail(AQ_EINVAL, "null solver");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);
+    s->fuse = enable ? 1 : 0;
+    return AQ_OK;
+}
+
+int aq_time_fused_kernel(aq_solver* s, int32_t n_launch, double* ms)
+{
+    if (!s || !ms || n_launch < 1) return fail(AQ_EINVAL, "n_launch must be >= 1");
+    // n_launch two-step launches followed by one single step, so the previous buffer
+    // pulls back to the current state again; only the two-step launches are timed
+    HIPCHK(hipEventRecord(s->ev[0], s->stream));
+    for (int i = 0; i < n_launch; i++) {
+        HIPCHK(launch_step2(s->mode, make_args2(s, s->cur == 0), s->stream));
+        s->cur ^= 1;
+        s->step += 2;
+    }
+    HIPCHK(hipEventRecord(s->ev[1], s->stream));
+    HIPCHK(launch_step(s->mode, false, make_args(s, s->cur == 0), s->stream));
+    s->cur ^= 1;
+    s->step++;
+    HIPCHK(hipEventSynchronize(s->ev[1]));
+    float t = 0;
+    HIPCHK(hipEventElapsedTime(&t, s->ev[0], s->ev[1]));
+    *ms = t / n_launch;
+    return AQ_OK;
+}
+
 int aq_autotune_tile(aq_solver* s, int32_t n_launch, int32_t only_256, int32_t* tile_x, int32_t* tile_y,
                      double* ms_per_launch)
 {
@@ -651,14 +730,15 @@ int aq_run_intervals_timed(aq_solver* s, int32_t n, double* total_ms, double* pl
     const int D = s->P.check_interval;
     if (s->step % D) return fail(AQ_ESTATE, "the step count must be a multiple of check_interval");
     if (s->n_tiles == 0) return fail(AQ_ESTATE, "the lattice has no active node");
-    int rc = ensure_graph(s);
+    int rc = ensure_graph(s, 0);
+    if (rc == AQ_OK) rc = ensure_graph(s, 1);
     if (rc) return rc;
     std::vector<hipEvent_t> evs(2 * (size_t)n + 1);
     for (auto& e : evs) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipEventRecord(evs[0], s->stream));
     for (int i = 0; i < n; i++) {
-        HIPCHK(hipGraphLaunch(s->plain_graph, s->stream));
-        s->cur ^= 1;
+        HIPCHK(hipGraphLaunch(s->plain_graph[s->cur], s->stream));
+        s->cur ^= plain_part_swaps(s) & 1;
         s->step += D - 1;
         HIPCHK(hipEventRecord(evs[2 * i + 1], s->stream));
         rc = launch_one(s);
@@ -696,7 +776,7 @@ int aq_save(aq_solver* s, const char* path)
     FILE* f = std::fopen(path, "wb");
     if (!f) return fail(AQ_EINVAL, std::string("cannot open ") + path);
     const uint32_t magic = 0x4D424C41u, version = 1;   // "ALBM"
-    int32_t hdr[4] = {s->exp_f, s->exp_t, (int32_t)s->checks, 0};
+    int32_t hdr[4] = {s->exp_f, s->exp_t, (int32_t)s->checks, s->cur};
     bool ok = std::fwrite(&magic, 4, 1, f) == 1 && std::fwrite(&version, 4, 1, f) == 1 &&
               std::fwrite(&s->P, sizeof(aq_params), 1, f) == 1 && std::fwrite(&s->step, 8, 1, f) == 1 &&
               std::fwrite(&s->last_check_step, 8, 1, f) == 1 && std::fwrite(hdr, 16, 1, f) == 1 &&
@@ -728,7 +808,7 @@ int aq_load(aq_solver* s, const char* path)
     std::fclose(f);
     if (!ok) return fail(AQ_EINVAL, "truncated checkpoint");
     HIPCHK(hipStreamSynchronize(s->stream));
-    s->cur = (int)(step & 1);   // the buffer parity follows the step count
+    s->cur = hdr[3] & 1;        // which buffer held the state
     void* cur = s->cur == 0 ? s->popA() : s->popB();
     void* prev = s->cur == 0 ? s->popB() : s->popA();
     HIPCHK(hipMemcpyAsync(cur, buf.data(), pop_bytes, hipMemcpyHostToDevice, s->stream));

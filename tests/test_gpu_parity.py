@@ -214,3 +214,26 @@ def test_config1_size_fp64_parity(aq):
     bad = obs_close(gobs, oobs, 1e-11, keys=["iop_gauge", "q_in", "q_out", "wss_cornea_mean",
                                               "wss_iris_mean", "resid_u", "resid_T", "u_max"])
     assert not bad, bad
+
+
+@pytest.mark.parametrize("storage", [A.F64, A.F32, A.F16S])
+@pytest.mark.parametrize("size", [(192, 96), (300, 150)])
+def test_two_step_fusion_bitwise(aq, storage, size):
+    """Two steps per launch (temporal blocking through LDS) gives bitwise the same state
+    and observables as single-step launches, in every storage."""
+    nx, ny = size
+    if (nx, ny) == (192, 96):
+        p, mask, walls, geo = A.config0()
+    else:
+        p, mask, walls, geo = A.sweep_instance(4, nx, ny, tau_f="draw", phi_deg="draw")
+    p = A.Params(**{**p.asdict(), "storage": storage})
+    out = []
+    for fuse in (False, True):
+        s = aq.Solver(p, mask, walls)
+        s.set_fusion(fuse)
+        s.step(537)
+        out.append(([s.read_field(f) for f in ("p", "ux", "uy", "T")], s.observe()))
+        s.close()
+    for x, y in zip(out[0][0], out[1][0]):
+        assert np.array_equal(np.nan_to_num(x, nan=7.0), np.nan_to_num(y, nan=7.0))
+    assert out[0][1] == out[1][1]
