@@ -129,12 +129,15 @@ struct aq_batch {
 
     InstDesc* d_inst = nullptr;
     int2* d_work[3] = {nullptr, nullptr, nullptr};
-    int* d_nwork = nullptr;
+    int2* d_work2[3] = {nullptr, nullptr, nullptr};
+    int* d_nwork = nullptr;         // [0..2] single-step items, [3..5] two-step items
+    int fuse[3] = {1, 1, 0};        // two steps per launch: F64 and F32 yes, F16S no
     double* d_partials[3] = {nullptr, nullptr, nullptr};
     double* d_latest = nullptr;
     double* h_latest = nullptr;     // pinned
     std::vector<InstDesc> h_inst;
     int n_work[3] = {0, 0, 0};
+    int n_work2[3] = {0, 0, 0};
 
     int nt_store = 0;               // non-temporal stores for the current working set
     int graph_mask = -1;
@@ -150,6 +153,8 @@ BatchArgs batch_args(const aq_batch* b, int mode, int parity)
     a.inst = b->d_inst;
     a.work = b->d_work[mode];
     a.n_work = b->d_nwork + mode;
+    a.work2 = b->d_work2[mode];
+    a.n_work2 = b->d_nwork + 3 + mode;
     a.partials = b->d_partials[mode];
     a.latest = b->d_latest;
     a.parity = parity;
@@ -185,10 +190,19 @@ int ensure_graph(aq_batch* b)
     drop_graph(b);
     HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
-    for (int t = 0; t < b->interval && err == hipSuccess; t++) {
-        const bool reduce = t == b->interval - 1;
-        for (int m = 0; m < 3 && err == hipSuccess; m++)
-            if (mask & (1 << m)) err = launch_batch_step(m, reduce, batch_args(b, m, t & 1), b->grid, b->stream);
+    for (int m = 0; m < 3 && err == hipSuccess; m++) {
+        if (!(mask & (1 << m))) continue;
+        // interval - 1 plain steps then the reducing one; with fusion, an even number F of
+        // two-step launches so every interval swaps the buffers an even number of times
+        // and the batch is back at parity 0 (instances are admitted at parity 0)
+        const int plain = b->interval - 1;
+        const int F = b->fuse[m] ? (plain / 2) & ~1 : 0;
+        int parity = 0;
+        for (int j = 0; j < F && err == hipSuccess; j++, parity ^= 1)
+            err = launch_batch_step2(m, batch_args(b, m, parity), b->grid, b->stream);
+        for (int j = 2 * F; j < plain && err == hipSuccess; j++, parity ^= 1)
+            err = launch_batch_step(m, false, batch_args(b, m, parity), b->grid, b->stream);
+        if (err == hipSuccess) err = launch_batch_step(m, true, batch_args(b, m, parity), b->grid, b->stream);
     }
     for (int m = 0; m < 3 && err == hipSuccess; m++)
         if (mask & (1 << m)) err = launch_batch_finish(batch_args(b, m, 0), b->stream);
@@ -214,7 +228,7 @@ int ensure_graph(aq_batch* b)
 // copy them to the device (ordered on the batch stream, then synchronised).
 int upload_tables(aq_batch* b)
 {
-    std::vector<int2> work[3];
+    std::vector<int2> work[3], work2[3];
     double bytes = 0;
     for (const Slot& sl : b->slots)
         if (sl.used && sl.running) bytes += (double)sl.s->n_active * bytes_per_update(sl.s->mode);
@@ -231,19 +245,27 @@ int upload_tables(aq_batch* b)
         const int m = sl.s->mode;
         d.a = make_args(sl.s, true);
         d.a.nt_store = nt;
+        d.a2 = make_args2(sl.s, true);
+        d.a2.nt_store = nt;
         d.work_start = (int)work[m].size();
         d.work_count = sl.s->n_tiles;
         d.running = 1;
         d.mode = m;
         for (int t : sl.s->htiles) work[m].push_back(make_int2(i, t));
+        for (int t : sl.s->htiles2) work2[m].push_back(make_int2(i, t));
     }
     for (int m = 0; m < 3; m++) {
-        if ((int)work[m].size() > b->max_tiles) return fail(AQ_EBUSY, "work list capacity exceeded");
+        if ((int)work[m].size() > b->max_tiles || (int)work2[m].size() > b->max_tiles)
+            return fail(AQ_EBUSY, "work list capacity exceeded");
         b->n_work[m] = (int)work[m].size();
+        b->n_work2[m] = (int)work2[m].size();
         if (!work[m].empty())
             HIPCHK(hipMemcpyAsync(b->d_work[m], work[m].data(), work[m].size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
+        if (!work2[m].empty())
+            HIPCHK(hipMemcpyAsync(b->d_work2[m], work2[m].data(), work2[m].size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
     }
-    HIPCHK(hipMemcpyAsync(b->d_nwork, b->n_work, 3 * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    int counts[6] = {b->n_work[0], b->n_work[1], b->n_work[2], b->n_work2[0], b->n_work2[1], b->n_work2[2]};
+    HIPCHK(hipMemcpyAsync(b->d_nwork, counts, sizeof(counts), hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipMemcpyAsync(b->d_inst, b->h_inst.data(), b->h_inst.size() * sizeof(InstDesc), hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     return AQ_OK;
@@ -362,6 +384,7 @@ int aq_batch_create(size_t budget_bytes, int32_t max_slots, int64_t max_active_n
               hipHostMalloc((void**)&b->h_latest, (size_t)max_slots * NRED * 8, hipHostMallocDefault) == hipSuccess;
     for (int m = 0; m < 3 && ok; m++)
         ok = hipMalloc((void**)&b->d_work[m], (size_t)max_tiles * sizeof(int2)) == hipSuccess &&
+             hipMalloc((void**)&b->d_work2[m], (size_t)max_tiles * sizeof(int2)) == hipSuccess &&
              hipMalloc((void**)&b->d_partials[m], (size_t)max_tiles * NRED * 8) == hipSuccess;
     if (!ok) return cleanup(fail(AQ_ENOMEM, "cannot allocate the batch tables"));
     int rc = upload_tables(b);
@@ -383,6 +406,7 @@ int aq_batch_destroy(aq_batch* b)
     if (b->h_latest) (void)hipHostFree(b->h_latest);
     for (int m = 0; m < 3; m++) {
         (void)hipFree(b->d_work[m]);
+        (void)hipFree(b->d_work2[m]);
         (void)hipFree(b->d_partials[m]);
     }
     (void)hipFree(b->arena);

@@ -62,6 +62,7 @@ struct StepArgs {
 // One instance of a batch (device table entry).  `a` has buffer A as src (even parity).
 struct InstDesc {
     StepArgs a;
+    StepArgs a2;                  // the same instance with its fused (two-step) tile list
     int work_start, work_count;   // this instance's run in its storage mode's work list
     int running, mode;
 };
@@ -71,6 +72,8 @@ struct BatchArgs {
     const InstDesc* inst;
     const int2* work;          // (slot, tile) items, grouped by slot
     const int* n_work;         // number of items (device memory, read at run time)
+    const int2* work2;         // (slot, fused tile) items for two-step launches
+    const int* n_work2;
     double* partials;          // [work capacity][NRED]
     double* latest;            // [max_slots][NRED]: latest raw sums of every instance
     int parity;                // 0: buffer A is src
@@ -84,6 +87,7 @@ hipError_t launch_step(int mode, bool reduce, const StepArgs& a, hipStream_t s);
 hipError_t launch_batch_step(int mode, bool reduce, const BatchArgs& b, int grid, hipStream_t s);
 // Two plain time steps in one launch (tiles 64 x fused_tile_rows(mode) from a.tiles).
 hipError_t launch_step2(int mode, const StepArgs& a, hipStream_t s);
+hipError_t launch_batch_step2(int mode, const BatchArgs& b, int grid, hipStream_t s);
 int fused_tile_rows(int mode);
 hipError_t launch_batch_finish(const BatchArgs& b, hipStream_t s);
 // Write into a.dst the buffer whose pull gives the pre-collision populations `pops`

@@ -113,6 +113,7 @@ struct aq_solver {
 namespace aq {
 
 StepArgs make_args(const aq_solver* s, bool a_is_src);
+StepArgs make_args2(const aq_solver* s, bool a_is_src);
 int set_state(aq_solver* s, const double* pops);
 void raw_to_obs(const aq_solver* s, const double* raw, int64_t step, aq_observables* o);
 int create_common(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls,

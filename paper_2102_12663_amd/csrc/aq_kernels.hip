@@ -534,6 +534,16 @@ __device__ __forceinline__ StepArgs load_desc(const InstDesc* table, int i)
 #endif
 }
 
+__device__ __forceinline__ StepArgs load_desc2(const InstDesc* table, int i)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) InstDesc ConstDesc;
+    return ((ConstDesc*)table)[i].a2;
+#else
+    return table[i].a2;
+#endif
+}
+
 __device__ __forceinline__ int2 load_item(const int2* work, int w)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -759,6 +769,56 @@ hipError_t launch_step2(int mode, const StepArgs& a, hipStream_t s)
 }
 
 int fused_tile_rows(int mode) { return mode == 0 ? Fuse<0>::TY : Fuse<1>::TY; }
+
+// Two time steps of every running instance of a batch whose storage is MODE (fused tile
+// work list; same walk, prefetch and descriptor caching as batch_step_kernel).
+template <int MODE, bool NT>
+__global__ __launch_bounds__(256) void batch_step2_kernel(BatchArgs b)
+{
+    __shared__ typename Traits<MODE>::R lds[NPOP * Fuse<MODE>::EN];
+    const int n = *b.n_work2;
+    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int w0 = blockIdx.x * per, w1 = min(n, w0 + per);
+    if (w0 >= w1) return;
+    int2 nxt = load_item(b.work2, w0);
+    int cur_slot = -1;
+    StepArgs a;
+    for (int w = w0; w < w1; w++) {
+        const int2 it = nxt;
+        if (w + 1 < w1) nxt = load_item(b.work2, w + 1);
+        if (it.x != cur_slot) {
+            a = load_desc2(b.inst, it.x);
+            if (b.parity) {
+                void* t = (void*)a.src;
+                a.src = a.dst;
+                a.dst = t;
+            }
+            cur_slot = it.x;
+        }
+        process_tile2<MODE, NT>(a, it.y, lds);
+        __syncthreads();   // the next tile overwrites the LDS image
+    }
+}
+
+template <int MODE, bool NT>
+static hipError_t launch_batch2_t(const BatchArgs& b, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_step2_kernel<MODE, NT>), dim3(grid), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step2(int mode, const BatchArgs& b, int grid, hipStream_t s)
+{
+    switch (mode * 2 + (b.nt_store ? 1 : 0)) {
+    case 0: return launch_batch2_t<0, false>(b, grid, s);
+    case 1: return launch_batch2_t<0, true>(b, grid, s);
+    case 2: return launch_batch2_t<1, false>(b, grid, s);
+    case 3: return launch_batch2_t<1, true>(b, grid, s);
+    case 4: return launch_batch2_t<2, false>(b, grid, s);
+    case 5: return launch_batch2_t<2, true>(b, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
 
 // ------------------------------------------------------------------------------ scatter / unpack
 // The state after step N is kept as two buffers: `cur` holds the post-collision
