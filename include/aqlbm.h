@@ -147,6 +147,10 @@ typedef struct aq_info {
     int32_t nx, ny, pitch, storage;
     int32_t tile_x, tile_y, n_tiles, check_interval;
     int32_t fp16_exp_flow, fp16_exp_thermal;
+    int32_t fusion;                 /* 1: the plain steps run two per launch */
+    int32_t graph_launches;         /* launches replayed from a graph per check interval */
+    int32_t nt_store;               /* 1: population stores bypass the caches (non-temporal) */
+    int32_t reserved0;
     int64_t step;
     size_t device_bytes;
     double bytes_per_node_update;   /* algorithmic HBM bytes per active-node update */
@@ -226,10 +230,13 @@ int aq_set_fusion(aq_solver* s, int32_t enable);
  * follows, untimed.  The state advances by 2 * n_launch + 1 steps without reductions. */
 int aq_time_fused_kernel(aq_solver* s, int32_t n_launch, double* ms_per_launch);
 
-/* Whole-interval graph replays with HIP events around the non-reducing part of each
- * interval: runs n_intervals * check_interval steps (the current step must be a multiple
- * of check_interval) and returns the total elapsed milliseconds and the milliseconds
- * spent in the check_interval - 1 plain launches of every interval. */
+/* Whole-interval graph replays with HIP events around the graph part of each interval:
+ * runs n_intervals * check_interval steps (the current step must be a multiple of
+ * check_interval) and returns the total elapsed milliseconds and the milliseconds spent
+ * in the graph part of every interval, i.e. aq_info.graph_launches launches per interval:
+ * (check_interval - 2) / 2 two-step launches when fusion is on, else check_interval - 1
+ * single steps.  The remaining single step (fusion on) and the reducing step are outside
+ * the graph part. */
 int aq_run_intervals_timed(aq_solver* s, int32_t n_intervals, double* total_ms,
                            double* plain_ms);
 

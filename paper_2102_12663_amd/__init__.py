@@ -60,7 +60,9 @@ class AqInfo(C.Structure):
                 ("nx", C.c_int32), ("ny", C.c_int32), ("pitch", C.c_int32), ("storage", C.c_int32),
                 ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("n_tiles", C.c_int32),
                 ("check_interval", C.c_int32), ("fp16_exp_flow", C.c_int32),
-                ("fp16_exp_thermal", C.c_int32), ("step", C.c_int64), ("device_bytes", C.c_size_t),
+                ("fp16_exp_thermal", C.c_int32), ("fusion", C.c_int32), ("graph_launches", C.c_int32),
+                ("nt_store", C.c_int32), ("reserved0", C.c_int32),
+                ("step", C.c_int64), ("device_bytes", C.c_size_t),
                 ("bytes_per_node_update", C.c_double)]
 
     def asdict(self):

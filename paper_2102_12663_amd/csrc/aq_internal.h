@@ -69,7 +69,9 @@ constexpr double kMallBytes = 192.0 * 1024 * 1024;
 
 }  // namespace aq
 
-
+struct PlainPlan {
+    int graph_launches, graph_steps, tail;
+};
 
 struct aq_solver {
     aq_params P;

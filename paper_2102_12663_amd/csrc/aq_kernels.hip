@@ -36,29 +36,32 @@ template <int MODE> struct Traits;
 template <> struct Traits<0> {   // AQ_F64
     using S = double;
     using R = double;
+    using Acc = double;      // exact-enough sums of a node's stored values
     __device__ static R ld(const S* p, R) { return *p; }
     __device__ static R ldv(S v, R) { return v; }
     __device__ static void st(S* p, R v, R) { *p = v; }
-    __device__ static S enc(double v, R) { return v; }
-    __device__ static double dec(S s, R) { return s; }
+    __device__ static S enc(Acc v, R) { return v; }
+    __device__ static Acc dec(S s, R) { return s; }
 };
 template <> struct Traits<1> {   // AQ_F32
     using S = float;
     using R = float;
+    using Acc = double;
     __device__ static R ld(const S* p, R) { return *p; }
     __device__ static R ldv(S v, R) { return v; }
     __device__ static void st(S* p, R v, R) { *p = v; }
-    __device__ static S enc(double v, R) { return (S)v; }
-    __device__ static double dec(S s, R) { return s; }
+    __device__ static S enc(Acc v, R) { return (S)v; }
+    __device__ static Acc dec(S s, R) { return s; }
 };
 template <> struct Traits<2> {   // AQ_F16S: binary16 of (deviation * 2^s)
     using S = _Float16;
     using R = float;
+    using Acc = float;       // float sums of binary16 values are far finer than their ulp
     __device__ static R ld(const S* p, R inv) { return (R)(*p) * inv; }
     __device__ static R ldv(S v, R inv) { return (R)v * inv; }
     __device__ static void st(S* p, R v, R sc) { *p = (S)(v * sc); }
-    __device__ static S enc(double v, R sc) { return (S)((R)v * sc); }
-    __device__ static double dec(S s, R inv) { return (double)((R)s * inv); }
+    __device__ static S enc(Acc v, R sc) { return (S)(v * sc); }
+    __device__ static Acc dec(S s, R inv) { return (R)s * inv; }
 };
 
 template <typename R> struct Node {
@@ -262,9 +265,9 @@ __device__ __forceinline__ void store_all(const StepArgs& a, typename Traits<MOD
     const R sf = R(a.sf), st = R(a.st);
     typename T::S e[NPOP];
 #pragma unroll
-    for (int i = 1; i <= 8; i++) e[i - 1] = T::enc((double)hs[i], sf);
+    for (int i = 1; i <= 8; i++) e[i - 1] = T::enc((typename T::Acc)hs[i], sf);
 #pragma unroll
-    for (int i = 0; i <= 4; i++) e[8 + i] = T::enc((double)gs[i], st);
+    for (int i = 0; i <= 4; i++) e[8 + i] = T::enc((typename T::Acc)gs[i], st);
     put_all<MODE, NT>(a, dst, k, e);
 }
 
@@ -282,20 +285,21 @@ __device__ __forceinline__ void conserve_encode(const typename Traits<MODE>::R* 
                                                 typename Traits<MODE>::R inv)
 {
     using T = Traits<MODE>;
-    double target = 0.0, sum = 0.0, amin = 0.0;
+    using Acc = typename T::Acc;
+    Acc target = 0, sum = 0, amin = 0;
     int kmin = 0;
 #pragma unroll
     for (int i = 0; i < N; i++) {
-        target += (double)in[i];
-        enc[i] = T::enc((double)out[i], sc);
-        const double d = T::dec(enc[i], inv);
+        target += (Acc)in[i];
+        enc[i] = T::enc((Acc)out[i], sc);
+        const Acc d = T::dec(enc[i], inv);
         sum += d;
         if (i == 0 || fabs(d) < amin) {
             amin = fabs(d);
             kmin = i;
         }
     }
-    const double r = target - sum;
+    const Acc r = target - sum;
 #pragma unroll
     for (int i = 0; i < N; i++)
         if (i == kmin) enc[i] = T::enc(T::dec(enc[i], inv) + r, sc);
@@ -680,9 +684,9 @@ __device__ __forceinline__ void encode_decoded(const StepArgs& a, const Node<typ
     using R = typename T::R;
     if (MODE == 0) {
 #pragma unroll
-        for (int i = 1; i <= 8; i++) e[i - 1] = T::enc((double)hs[i], R(a.sf));
+        for (int i = 1; i <= 8; i++) e[i - 1] = T::enc((typename T::Acc)hs[i], R(a.sf));
 #pragma unroll
-        for (int i = 0; i <= 4; i++) e[8 + i] = T::enc((double)gs[i], R(a.st));
+        for (int i = 0; i <= 4; i++) e[8 + i] = T::enc((typename T::Acc)gs[i], R(a.st));
     } else {
         conserve_encode<MODE, 8>(n.h + 1, hs + 1, e, R(a.sf), R(a.inv_sf));
         conserve_encode<MODE, 5>(n.g, gs, e + 8, R(a.st), R(a.inv_st));

@@ -210,38 +210,37 @@ void drop_graph(aq_solver* s)
 // (check_interval - 2)/2 two-step launches and one single step when fusion is on (the
 // interval must end with a single step so the previous buffer pulls back to the current
 // state), else as single steps.  Returns the number of buffer swaps.
-int plain_part_swaps(const aq_solver* s)
+// The check_interval - 1 plain steps of an interval: `graph_launches` launches replayed
+// from a graph (two-step launches when fusion is on, else single steps) covering
+// `graph_steps` steps, then `tail` single steps launched directly.  The reducing step that
+// closes the interval is always a single step, so the previous buffer pulls back to the
+// state at every check step.
+static PlainPlan plain_plan(const aq_solver* s)
 {
     const int n = s->P.check_interval - 1;
-    return s->fuse ? (n - 1) / 2 + 1 : n;
+    if (s->fuse) return {n / 2, 2 * (n / 2), n % 2};
+    return {n, n, 0};
 }
 
-int enqueue_plain_part(aq_solver* s, int cur, hipError_t* err)
+static void enqueue_graph_part(aq_solver* s, int cur, hipError_t* err)
 {
-    const int n = s->P.check_interval - 1;
+    const PlainPlan pp = plain_plan(s);
     bool a_src = cur == 0;
     *err = hipSuccess;
-    int left = n;
-    if (s->fuse) {
-        for (; left >= 3 && *err == hipSuccess; left -= 2) {
-            *err = launch_step2(s->mode, make_args2(s, a_src), s->stream);
-            a_src = !a_src;
-        }
-    }
-    for (; left > 0 && *err == hipSuccess; left--) {
-        *err = launch_step(s->mode, false, make_args(s, a_src), s->stream);
+    for (int i = 0; i < pp.graph_launches && *err == hipSuccess; i++) {
+        *err = s->fuse ? launch_step2(s->mode, make_args2(s, a_src), s->stream)
+                       : launch_step(s->mode, false, make_args(s, a_src), s->stream);
         a_src = !a_src;
     }
-    return AQ_OK;
 }
 
-// Capture the plain part of an interval starting from buffer `cur` as one graph.
+// Capture the graph part of an interval starting from buffer `cur` as one graph.
 int ensure_graph(aq_solver* s, int cur)
 {
-    if (s->plain_graph[cur]) return AQ_OK;
+    if (s->plain_graph[cur] || plain_plan(s).graph_launches == 0) return AQ_OK;
     HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
-    enqueue_plain_part(s, cur, &err);
+    enqueue_graph_part(s, cur, &err);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s->stream, &g);
     if (err != hipSuccess) {
@@ -272,6 +271,29 @@ int launch_one(aq_solver* s)
         s->last_check_step = s->step;
     }
     return AQ_OK;
+}
+
+// Replay the graph part of an interval (the state is at a check step).
+static int launch_graph_part(aq_solver* s)
+{
+    const PlainPlan pp = plain_plan(s);
+    if (pp.graph_launches == 0) return AQ_OK;
+    int rc = ensure_graph(s, s->cur);
+    if (rc) return rc;
+    HIPCHK(hipGraphLaunch(s->plain_graph[s->cur], s->stream));
+    s->cur ^= pp.graph_launches & 1;
+    s->step += pp.graph_steps;
+    return AQ_OK;
+}
+
+// The tail single steps and the reducing step that close an interval.
+static int launch_interval_end(aq_solver* s)
+{
+    for (int i = 0; i < plain_plan(s).tail; i++) {
+        int rc = launch_one(s);
+        if (rc) return rc;
+    }
+    return launch_one(s);
 }
 
 void raw_to_obs(const aq_solver* s, const double* r, int64_t step, aq_observables* o)
@@ -494,12 +516,8 @@ int aq_step(aq_solver* s, int64_t nsteps)
     const int D = s->P.check_interval;
     while (nsteps > 0) {
         if (s->step % D == 0 && nsteps >= D && s->n_tiles > 0) {
-            int rc = ensure_graph(s, s->cur);
-            if (rc) return rc;
-            HIPCHK(hipGraphLaunch(s->plain_graph[s->cur], s->stream));
-            s->cur ^= plain_part_swaps(s) & 1;
-            s->step += D - 1;
-            rc = launch_one(s);       // the reducing step
+            int rc = launch_graph_part(s);
+            if (rc == AQ_OK) rc = launch_interval_end(s);
             if (rc) return rc;
             nsteps -= D;
         } else {
@@ -628,6 +646,9 @@ int aq_get_info(aq_solver* s, aq_info* o)
     o->check_interval = s->P.check_interval;
     o->fp16_exp_flow = s->exp_f;
     o->fp16_exp_thermal = s->exp_t;
+    o->fusion = s->fuse ? 1 : 0;
+    o->graph_launches = plain_plan(s).graph_launches;
+    o->nt_store = s->nt_store ? 1 : 0;
     o->step = s->step;
     o->device_bytes = s->L.total;
     o->bytes_per_node_update = bytes_per_update(s->mode);
@@ -739,11 +760,10 @@ int aq_run_intervals_timed(aq_solver* s, int32_t n, double* total_ms, double* pl
     for (auto& e : evs) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipEventRecord(evs[0], s->stream));
     for (int i = 0; i < n; i++) {
-        HIPCHK(hipGraphLaunch(s->plain_graph[s->cur], s->stream));
-        s->cur ^= plain_part_swaps(s) & 1;
-        s->step += D - 1;
+        rc = launch_graph_part(s);
+        if (rc) return rc;
         HIPCHK(hipEventRecord(evs[2 * i + 1], s->stream));
-        rc = launch_one(s);
+        rc = launch_interval_end(s);
         if (rc) return rc;
         HIPCHK(hipEventRecord(evs[2 * i + 2], s->stream));
     }
