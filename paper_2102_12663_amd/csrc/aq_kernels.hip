@@ -85,14 +85,11 @@ __device__ __forceinline__ bool is_active(uint8_t t)
 // 8 neighbours' type bytes, each load address is then selected (upstream slot, or the
 // node's own opposite slot for a link into a non-active node), and the link rules are
 // applied to the loaded values afterwards.  Interior nodes skip the type reads.
-template <int MODE>
-__device__ __forceinline__ void pull_all(const StepArgs& a, const typename Traits<MODE>::S* src, int k,
-                                         bool boundary, Node<typename Traits<MODE>::R>& n)
+// The three phases of the pull, separable so that a thread owning several nodes can issue
+// the loads of all of them before waiting on any.
+// (1) Types of the 8 neighbours (boundary nodes only; interior nodes see all FLUID).
+__device__ __forceinline__ void pull_types(const StepArgs& a, int k, bool boundary, uint8_t* nt)
 {
-    using T = Traits<MODE>;
-    using R = typename T::R;
-    const R inv_f = R(a.inv_sf), inv_t = R(a.inv_st);
-    uint8_t nt[9];
     if (boundary) {
 #pragma unroll
         for (int i = 1; i <= 8; i++) nt[i] = a.type[k - EY[i] * a.pitch - EX[i]];
@@ -100,29 +97,42 @@ __device__ __forceinline__ void pull_all(const StepArgs& a, const typename Trait
 #pragma unroll
         for (int i = 1; i <= 8; i++) nt[i] = FLUID;
     }
-    bool up[9];
-#pragma unroll
-    for (int i = 1; i <= 8; i++) up[i] = is_active(nt[i]);
+}
+
+// (2) The 13 loads: upstream slot, or the own opposite slot for a link into a non-active node.
+template <int MODE>
+__device__ __forceinline__ void pull_loads(const StepArgs& a, const typename Traits<MODE>::S* src, int k,
+                                           const uint8_t* nt, Node<typename Traits<MODE>::R>& n)
+{
+    using T = Traits<MODE>;
+    using R = typename T::R;
+    const R inv_f = R(a.inv_sf), inv_t = R(a.inv_st);
 #pragma unroll
     for (int i = 1; i <= 8; i++) {
-        const long long off = up[i] ? (long long)(i - 1) * a.qs + (k - EY[i] * a.pitch - EX[i])
-                                    : (long long)(OPP[i] - 1) * a.qs + k;
+        const long long off = is_active(nt[i]) ? (long long)(i - 1) * a.qs + (k - EY[i] * a.pitch - EX[i])
+                                               : (long long)(OPP[i] - 1) * a.qs + k;
         n.h[i] = T::ld(src + off, inv_f);
     }
     const typename T::S* tsrc = src + 8LL * a.qs;
     n.g[0] = T::ld(tsrc + k, inv_t);
 #pragma unroll
     for (int i = 1; i <= 4; i++) {
-        const long long off = up[i] ? (long long)i * a.qs + (k - EY[i] * a.pitch - EX[i])
-                                    : (long long)OPP[i] * a.qs + k;
+        const long long off = is_active(nt[i]) ? (long long)i * a.qs + (k - EY[i] * a.pitch - EX[i])
+                                               : (long long)OPP[i] * a.qs + k;
         n.g[i] = T::ld(tsrc + off, inv_t);
     }
+}
+
+// (3) The link rules on the loaded values of links into non-active nodes.
+template <typename R>
+__device__ __forceinline__ void pull_rules(const StepArgs& a, const uint8_t* nt, bool boundary, Node<R>& n)
+{
     n.qin = R(0);
     n.qout = R(0);
     if (!boundary) return;
 #pragma unroll
     for (int i = 1; i <= 8; i++) {
-        if (up[i]) continue;
+        if (is_active(nt[i])) continue;
         const uint8_t c = nt[i] & CLS_MASK;
         const R v = n.h[i];
         if (c == INLET) {                                      // moving wall at u_in
@@ -137,7 +147,7 @@ __device__ __forceinline__ void pull_all(const StepArgs& a, const typename Trait
     }
 #pragma unroll
     for (int i = 1; i <= 4; i++) {
-        if (up[i]) continue;
+        if (is_active(nt[i])) continue;
         const uint8_t c = nt[i] & CLS_MASK;
         const uint8_t wall = (nt[i] >> WALL_SHIFT) & 3;
         if (c == INLET || (c == SOLID && wall != WALL_BOX)) {  // Dirichlet anti-bounce-back
@@ -145,6 +155,16 @@ __device__ __forceinline__ void pull_all(const StepArgs& a, const typename Trait
             n.g[i] = -n.g[i] + R(2.0) * R(a.wT) * R(tw);
         }                                                      // else adiabatic bounce-back
     }
+}
+
+template <int MODE>
+__device__ __forceinline__ void pull_all(const StepArgs& a, const typename Traits<MODE>::S* src, int k,
+                                         bool boundary, Node<typename Traits<MODE>::R>& n)
+{
+    uint8_t nt[9];
+    pull_types(a, k, boundary, nt);
+    pull_loads<MODE>(a, src, k, nt, n);
+    pull_rules(a, nt, boundary, n);
 }
 
 // ------------------------------------------------------------------------------ moments
@@ -611,15 +631,33 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(BatchArgs b)
 // are bitwise identical to two single-step launches while the intermediate state never
 // travels to HBM.
 template <int MODE> struct Fuse {
-    static constexpr int TY = (MODE == 0) ? 4 : 8;   // output rows per tile
+    static constexpr int TY = 8;                              // output rows per tile
+    static constexpr int THREADS = (MODE == 0) ? 512 : 256;   // threads per block
+    // the batched kernel keeps its instance descriptor in registers; there the FP32 and
+    // F16S forms run faster one step-A node at a time
+    static constexpr bool BATCH_PF = MODE == 0;
     static constexpr int EW = 66, EH = TY + 2;        // tile plus a one-node halo
-    static constexpr int EN = EW * EH;
+    static constexpr int EN = EW * EH;                // step-A nodes
+    static constexpr int NA = (EN + THREADS - 1) / THREADS;   // step-A nodes per thread
+    // LDS image: h_1..h_8 and g_1..g_4 over tile + halo (planes 0..11); g_0 is only read
+    // by its own node, so it is kept for the tile nodes alone.  FP64 at TY = 4 then fits
+    // four blocks per CU.
+    static constexpr int PLANES = 12;
+    static constexpr int WORDS = PLANES * EN + 64 * TY;
+    static_assert((TY * 64) % THREADS == 0, "step B covers the tile in whole passes");
 };
 
 template <int MODE>
 __device__ __forceinline__ int lds_at(int q, int ly, int lx)
 {
     return (q * Fuse<MODE>::EH + ly) * Fuse<MODE>::EW + lx;
+}
+
+// g_0 of tile node (lx, ly) in E coordinates (1 <= lx <= 64, 1 <= ly <= TY)
+template <int MODE>
+__device__ __forceinline__ int lds_g0(int ly, int lx)
+{
+    return Fuse<MODE>::PLANES * Fuse<MODE>::EN + (ly - 1) * 64 + (lx - 1);
 }
 
 // Pull from the LDS image of step n+1 (E coordinates: the tile node is (ex, ey)).
@@ -642,10 +680,10 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
 #pragma unroll
     for (int i = 1; i <= 8; i++)
         n.h[i] = up[i] ? lds[lds_at<MODE>(i - 1, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE>(OPP[i] - 1, ey, ex)];
-    n.g[0] = lds[lds_at<MODE>(8, ey, ex)];
+    n.g[0] = lds[lds_g0<MODE>(ey, ex)];
 #pragma unroll
     for (int i = 1; i <= 4; i++)
-        n.g[i] = up[i] ? lds[lds_at<MODE>(8 + i, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE>(8 + OPP[i], ey, ex)];
+        n.g[i] = up[i] ? lds[lds_at<MODE>(7 + i, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE>(7 + OPP[i], ey, ex)];
     n.qin = R(0);
     n.qout = R(0);
     if (!boundary) return;
@@ -693,7 +731,30 @@ __device__ __forceinline__ void encode_decoded(const StepArgs& a, const Node<typ
     }
 }
 
-template <int MODE, bool NT>
+// Step A of one node (E coordinates ex, ey): collide, round as a store would, and keep the
+// decoded values in LDS.
+template <int MODE>
+__device__ __forceinline__ void step_a_store(const StepArgs& a, const Node<typename Traits<MODE>::R>& n, bool porous,
+                                             int ex, int ey, typename Traits<MODE>::R* lds)
+{
+    using T = Traits<MODE>;
+    using R = typename T::R;
+    using F = Fuse<MODE>;
+    const Moments<R> m = moments(n);
+    R hs[9], gs[5];
+    collide(a, porous, n, m, hs, gs);
+    typename T::S enc[NPOP];
+    encode_decoded<MODE>(a, n, hs, gs, enc);
+#pragma unroll
+    for (int q = 0; q < 8; q++) lds[lds_at<MODE>(q, ey, ex)] = T::ldv(enc[q], R(a.inv_sf));
+#pragma unroll
+    for (int i = 1; i <= 4; i++) lds[lds_at<MODE>(7 + i, ey, ex)] = T::ldv(enc[8 + i], R(a.inv_st));
+    if (ex >= 1 && ex <= 64 && ey >= 1 && ey <= F::TY) lds[lds_g0<MODE>(ey, ex)] = T::ldv(enc[8], R(a.inv_st));
+}
+
+// PF: step A issues the loads of all of a thread's nodes before computing any (more bytes
+// in flight, more registers).
+template <int MODE, bool NT, bool PF>
 __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typename Traits<MODE>::R* lds)
 {
     using T = Traits<MODE>;
@@ -704,30 +765,52 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
     const typename T::S* src = (const typename T::S*)a.src;
     typename T::S* dst = (typename T::S*)a.dst;
     // step A: step n+1 on the tile and its halo, into LDS
-    for (int e = threadIdx.x; e < F::EN; e += 256) {
-        const int ex = e % F::EW, ey = e / F::EW;
-        const int x = x0 - 1 + ex, y = y0 - 1 + ey;
-        if (x < 0 || y < 0 || x >= a.nx || y >= a.ny) continue;
-        const int k = y * a.pitch + x;
-        const uint8_t t = a.type[k];
-        if (!is_active(t)) continue;
-        Node<R> n;
-        pull_all<MODE>(a, src, k, (t & F_BOUNDARY) != 0, n);
-        const Moments<R> m = moments(n);
-        R hs[9], gs[5];
-        collide(a, (t & CLS_MASK) == POROUS, n, m, hs, gs);
-        typename T::S enc[NPOP];
-        encode_decoded<MODE>(a, n, hs, gs, enc);
+    if constexpr (PF) {
+        // each thread owns NA nodes and issues the loads of all of them before computing
+        int kA[F::NA];
+        uint8_t tA[F::NA];
 #pragma unroll
-        for (int q = 0; q < 8; q++) lds[lds_at<MODE>(q, ey, ex)] = T::ldv(enc[q], R(a.inv_sf));
+        for (int j = 0; j < F::NA; j++) {
+            const int e = threadIdx.x + F::THREADS * j;
+            const int ex = e % F::EW, ey = e / F::EW;
+            const int x = x0 - 1 + ex, y = y0 - 1 + ey;
+            const bool in = e < F::EN && x >= 0 && y >= 0 && x < a.nx && y < a.ny;
+            kA[j] = in ? y * a.pitch + x : 0;
+            tA[j] = in ? a.type[kA[j]] : (uint8_t)0;   // 0 = SOLID: not active
+        }
+        Node<R> nA[F::NA];
+        uint8_t ntA[F::NA][9];
 #pragma unroll
-        for (int q = 8; q < NPOP; q++) lds[lds_at<MODE>(q, ey, ex)] = T::ldv(enc[q], R(a.inv_st));
+        for (int j = 0; j < F::NA; j++) pull_types(a, kA[j], is_active(tA[j]) && (tA[j] & F_BOUNDARY), ntA[j]);
+#pragma unroll
+        for (int j = 0; j < F::NA; j++)
+            if (is_active(tA[j])) pull_loads<MODE>(a, src, kA[j], ntA[j], nA[j]);
+#pragma unroll
+        for (int j = 0; j < F::NA; j++) pull_rules(a, ntA[j], (tA[j] & F_BOUNDARY) != 0, nA[j]);
+#pragma unroll
+        for (int j = 0; j < F::NA; j++) {
+            const int e = threadIdx.x + F::THREADS * j;
+            if (is_active(tA[j])) step_a_store<MODE>(a, nA[j], (tA[j] & CLS_MASK) == POROUS, e % F::EW, e / F::EW, lds);
+        }
+    } else {
+        // one node at a time (fewer registers)
+        for (int e = threadIdx.x; e < F::EN; e += F::THREADS) {
+            const int ex = e % F::EW, ey = e / F::EW;
+            const int x = x0 - 1 + ex, y = y0 - 1 + ey;
+            if (x < 0 || y < 0 || x >= a.nx || y >= a.ny) continue;
+            const int k = y * a.pitch + x;
+            const uint8_t t = a.type[k];
+            if (!is_active(t)) continue;
+            Node<R> n;
+            pull_all<MODE>(a, src, k, (t & F_BOUNDARY) != 0, n);
+            step_a_store<MODE>(a, n, (t & CLS_MASK) == POROUS, ex, ey, lds);
+        }
     }
     __syncthreads();
     // step B: step n+2 on the tile, from LDS, to global memory
 #pragma unroll
-    for (int r = 0; r < F::TY / 4; r++) {
-        const int lx = threadIdx.x & 63, ly = (threadIdx.x >> 6) + 4 * r;
+    for (int r = 0; r < F::TY * 64 / F::THREADS; r++) {
+        const int lx = threadIdx.x & 63, ly = (threadIdx.x >> 6) + (F::THREADS / 64) * r;
         const int x = x0 + lx, y = y0 + ly;
         if (x >= a.nx || y >= a.ny) continue;
         const int k = y * a.pitch + x;
@@ -745,17 +828,17 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
 // Two time steps of one lattice; one block per active 64 x TY tile (tile list in
 // a.tiles, laid out with a.tiles_x = ceil(nx / 64) tiles per row).
 template <int MODE, bool NT>
-__global__ __launch_bounds__(256) void step2_kernel(StepArgs a)
+__global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void step2_kernel(StepArgs a)
 {
-    __shared__ typename Traits<MODE>::R lds[NPOP * Fuse<MODE>::EN];
-    process_tile2<MODE, NT>(a, a.tiles[tile_of_block(a)], lds);
+    __shared__ typename Traits<MODE>::R lds[Fuse<MODE>::WORDS];
+    process_tile2<MODE, NT, true>(a, a.tiles[tile_of_block(a)], lds);
 }
 
 template <int MODE, bool NT>
 static hipError_t launch_step2_t(const StepArgs& a, hipStream_t s)
 {
     if (a.n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((step2_kernel<MODE, NT>), dim3(a.n_tiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((step2_kernel<MODE, NT>), dim3(a.n_tiles), dim3(Fuse<MODE>::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
@@ -772,14 +855,14 @@ hipError_t launch_step2(int mode, const StepArgs& a, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
-int fused_tile_rows(int mode) { return mode == 0 ? Fuse<0>::TY : Fuse<1>::TY; }
+int fused_tile_rows(int mode) { return mode == 0 ? Fuse<0>::TY : mode == 1 ? Fuse<1>::TY : Fuse<2>::TY; }
 
 // Two time steps of every running instance of a batch whose storage is MODE (fused tile
 // work list; same walk, prefetch and descriptor caching as batch_step_kernel).
 template <int MODE, bool NT>
-__global__ __launch_bounds__(256) void batch_step2_kernel(BatchArgs b)
+__global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void batch_step2_kernel(BatchArgs b)
 {
-    __shared__ typename Traits<MODE>::R lds[NPOP * Fuse<MODE>::EN];
+    __shared__ typename Traits<MODE>::R lds[Fuse<MODE>::WORDS];
     const int n = *b.n_work2;
     const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
     const int w0 = blockIdx.x * per, w1 = min(n, w0 + per);
@@ -799,7 +882,7 @@ __global__ __launch_bounds__(256) void batch_step2_kernel(BatchArgs b)
             }
             cur_slot = it.x;
         }
-        process_tile2<MODE, NT>(a, it.y, lds);
+        process_tile2<MODE, NT, Fuse<MODE>::BATCH_PF>(a, it.y, lds);
         __syncthreads();   // the next tile overwrites the LDS image
     }
 }
@@ -807,7 +890,7 @@ __global__ __launch_bounds__(256) void batch_step2_kernel(BatchArgs b)
 template <int MODE, bool NT>
 static hipError_t launch_batch2_t(const BatchArgs& b, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((batch_step2_kernel<MODE, NT>), dim3(grid), dim3(256), 0, s, b);
+    hipLaunchKernelGGL((batch_step2_kernel<MODE, NT>), dim3(grid), dim3(Fuse<MODE>::THREADS), 0, s, b);
     return hipGetLastError();
 }
 
