@@ -17,7 +17,9 @@ inputs.
 
 Mask byte encoding (an input format, read independently by both implementations):
   bits 0-2  node class: SOLID=0, FLUID=1, POROUS=2, INLET=3, OUTLET=4
-  bits 3-4  wall id of a SOLID node: BOX=0 (adiabatic), CORNEA=1, IRIS=2
+  bits 3-4  wall id of a SOLID node: BOX=0 (adiabatic), CORNEA=1, IRIS=2; for an OUTLET
+            node of a lumped-meshwork outlet, the outward seepage direction
+            (+x=0, +y=1, -x=2, -y=3)
 FLUID and POROUS nodes are "active" (they carry populations).  The outer one-node frame
 of a non-periodic lattice is never active.
 
@@ -34,6 +36,10 @@ import numpy as np
 
 SOLID, FLUID, POROUS, INLET, OUTLET = 0, 1, 2, 3, 4
 WALL_BOX, WALL_CORNEA, WALL_IRIS = 0, 1, 2
+# For OUTLET nodes of a lumped-meshwork outlet the wall bits hold the outward direction
+# of the seepage flow (the axis link it points along).
+DIR_PX, DIR_PY, DIR_MX, DIR_MY = 0, 1, 2, 3
+OUTLET_PRESSURE, OUTLET_LUMPED = 0, 1
 
 WALL_DTYPE = np.dtype([("node", "<i4"), ("wall", "<i4"), ("nx", "<f8"), ("ny", "<f8")])
 
@@ -112,7 +118,7 @@ D0_DEPTH = 80.0 * (1.0 - math.cos(math.radians(45.0)))   # chamber depth of the 
 
 
 def eye_mask(nx: int, ny: int, alpha_deg: float = 45.0, R: float | None = None,
-             jf: int = 2, pupil_gap: int | None = None):
+             jf: int = 2, pupil_gap: int | None = None, tm: str = "resolved"):
     """Synthetic anterior-chamber section.
 
     Rows j < jf are the iris/lens floor (SOLID, wall IRIS).  A pupil gap of `pupil_gap`
@@ -122,6 +128,10 @@ def eye_mask(nx: int, ny: int, alpha_deg: float = 45.0, R: float | None = None,
     R(1 - cos alpha).  At each chamber angle a POROUS trabecular-meshwork block 4s wide and
     8s tall is centred on the corner, with a one-column OUTLET strip on its outer side.
     Every other node is SOLID: CORNEA above the floor, IRIS in it.
+
+    tm="lumped" instead makes each meshwork block and its strip OUTLET nodes whose
+    seepage direction points away from the chamber along x (-x on the left, +x on the
+    right): the lumped-meshwork outlet, where the flow leaves at the Darcy seepage speed.
 
     Returns (mask[ny, nx] uint8, walls (WALL_DTYPE), EyeGeometry).
     """
@@ -158,9 +168,14 @@ def eye_mask(nx: int, ny: int, alpha_deg: float = 45.0, R: float | None = None,
     # left block centred on the left corner; the right block is its exact mirror image
     c0 = int(math.floor(xc - half - w / 2.0 + 0.5))
     c1 = c0 + w - 1
-    for lo, hi, oc in ((c0, c1, c0 - 1), (nx - 1 - c1, nx - 1 - c0, nx - c0)):
-        mask[jf:jf + h, lo:hi + 1] = encode(POROUS)
-        mask[jf:jf + h, oc] = encode(OUTLET)
+    if tm not in ("resolved", "lumped"):
+        raise ValueError("tm is 'resolved' or 'lumped'")
+    for lo, hi, oc, d in ((c0, c1, c0 - 1, DIR_MX), (nx - 1 - c1, nx - 1 - c0, nx - c0, DIR_PX)):
+        if tm == "lumped":
+            mask[jf:jf + h, min(lo, oc):max(hi, oc) + 1] = encode(OUTLET, d)
+        else:
+            mask[jf:jf + h, lo:hi + 1] = encode(POROUS)
+            mask[jf:jf + h, oc] = encode(OUTLET)
         geo.tm_cols.append((lo, hi))
         geo.outlet_cols.append(oc)
 
@@ -314,6 +329,12 @@ class Params:
     fp16_exp_thermal: int = -1
     periodic_x: int = 0
     periodic_y: int = 0
+    # lumped meshwork outlet (outlet_mode = OUTLET_LUMPED): permeability, thickness and
+    # Schlemm's-canal pressure, lattice units
+    outlet_mode: int = OUTLET_PRESSURE
+    K_tm: float = 1.0
+    h_tm: float = 1.0
+    p_sc: float = 1.0 / 3.0
 
     def asdict(self):
         return asdict(self)
@@ -330,15 +351,24 @@ def diffusivity_of(tau_t: float, w0: float) -> float:
 
 
 def eye_params(nx, ny, geo: EyeGeometry, *, u_in=1e-4, Da=1e-4, Ra=1e3, tau_f=0.8,
-               tau_t=0.7, w0=1.0 / 3.0, phi_deg=0.0, storage=F64, check_interval=100):
+               tau_t=0.7, w0=1.0 / 3.0, phi_deg=0.0, storage=F64, check_interval=100,
+               tm="resolved", h_tm=None, p_sc=1.0 / 3.0):
     """Workload parameters for the eye geometry.  Ra = g beta dT H^3 / (nu theta) and
-    Da = K / H^2 with H the chamber depth and dT = T_iris - T_cornea = 1."""
+    Da = K / H^2 with H the chamber depth and dT = T_iris - T_cornea = 1.  With
+    tm="lumped" the meshwork has permeability K_tm = Da H^2 and thickness h_tm (default:
+    the block width 4s) and drains to the Schlemm's-canal pressure p_sc."""
     H = geo.depth
     nu = viscosity_of(tau_f)
     th = diffusivity_of(tau_t, w0)
-    return Params(nx=nx, ny=ny, tau_f=tau_f, tau_t=tau_t, w0=w0, u_in_x=0.0, u_in_y=u_in,
-                  gbeta=Ra * nu * th / H ** 3, gravity_angle=math.radians(phi_deg),
-                  K=Da * H * H, storage=storage, check_interval=check_interval)
+    p = Params(nx=nx, ny=ny, tau_f=tau_f, tau_t=tau_t, w0=w0, u_in_x=0.0, u_in_y=u_in,
+               gbeta=Ra * nu * th / H ** 3, gravity_angle=math.radians(phi_deg),
+               K=Da * H * H, storage=storage, check_interval=check_interval)
+    if tm == "lumped":
+        p.outlet_mode = OUTLET_LUMPED
+        p.K_tm = Da * H * H
+        p.h_tm = float(4 * geo.s) if h_tm is None else float(h_tm)
+        p.p_sc = p_sc
+    return p
 
 
 def config0():

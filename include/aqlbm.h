@@ -65,9 +65,15 @@ enum {
     AQ_FIELD_POP_HEAT = 5  /* pre-collision thermal population q = 0..4, deviation form */
 };
 
-/* Mask byte (input): bits 0-2 node class, bits 3-4 wall id of a SOLID node. */
+/* Mask byte (input): bits 0-2 node class, bits 3-4 wall id of a SOLID node; for an OUTLET
+ * node under AQ_OUTLET_LUMPED, bits 3-4 are the outward seepage direction (AQ_DIR_*). */
 enum { AQ_SOLID = 0, AQ_FLUID = 1, AQ_POROUS = 2, AQ_INLET = 3, AQ_OUTLET = 4 };
 enum { AQ_WALL_BOX = 0, AQ_WALL_CORNEA = 1, AQ_WALL_IRIS = 2 };
+enum { AQ_DIR_PX = 0, AQ_DIR_PY = 1, AQ_DIR_MX = 2, AQ_DIR_MY = 3 };
+
+/* Outlet models: a pressure outlet at p_out, or the lumped trabecular meshwork of
+ * section 2.2.4 (Darcy seepage driven by the IOP, applied as a velocity condition). */
+enum { AQ_OUTLET_PRESSURE = 0, AQ_OUTLET_LUMPED = 1 };
 
 /*
  * Solver parameters (lattice units).  struct_size must be sizeof(aq_params).
@@ -80,7 +86,8 @@ enum { AQ_WALL_BOX = 0, AQ_WALL_CORNEA = 1, AQ_WALL_IRIS = 2 };
  *   p_ref             pressure about which flow populations are stored:
  *                     h_i = f_i - lambda_i p_ref (lambda_{1-4} = 1/3, lambda_{5-8} = 1/12,
  *                     the reading sigma = 5/12 of the constraints under eq. 7)
- *   p_out             absolute pressure at OUTLET nodes (anti-bounce-back)
+ *   p_out             absolute pressure at OUTLET nodes (anti-bounce-back), and the
+ *                     reference of iop_gauge
  *   p_init, T_init    initial equilibrium state, at rest
  *   T_ref             temperature about which thermal populations are stored:
  *                     g_i = T_i - w^T_i T_ref
@@ -94,6 +101,16 @@ enum { AQ_WALL_BOX = 0, AQ_WALL_CORNEA = 1, AQ_WALL_IRIS = 2 };
  *   fp16_exp_flow, fp16_exp_thermal
  *                     F16S scale exponents s (values stored as deviation * 2^s);
  *                     -1 picks them from the parameters
+ *   outlet_mode       AQ_OUTLET_PRESSURE, or AQ_OUTLET_LUMPED: the meshwork is not
+ *                     resolved; its pressure falls linearly over the thickness h_tm from
+ *                     the IOP (mean pressure over FLUID nodes) to p_sc, so Darcy's law
+ *                     (eq. 4, viscosity nu at unit density) gives the seepage speed
+ *                     u_s = K_tm (IOP - p_sc) / (nu h_tm).  u_s is re-evaluated at every
+ *                     check step and holds for the next check_interval steps (the first
+ *                     interval uses p_init); every OUTLET node is a wall moving at u_s
+ *                     along its outward direction (moving-wall bounce-back).
+ *   K_tm, h_tm, p_sc  lumped meshwork permeability and thickness (> 0) and Schlemm's-
+ *                     canal pressure (absolute)
  */
 typedef struct aq_params {
     uint32_t struct_size;
@@ -101,13 +118,14 @@ typedef struct aq_params {
     int32_t storage;
     int32_t check_interval;
     int32_t fp16_exp_flow, fp16_exp_thermal;
-    int32_t reserved0;
+    int32_t outlet_mode;
     double tau_f, tau_t, w0;
     double u_in_x, u_in_y;
     double p_ref, p_out, p_init;
     double T_ref, T_init, T0;
     double T_cornea, T_iris, T_inlet;
     double gbeta, gravity_angle, K;
+    double K_tm, h_tm, p_sc;
 } aq_params;
 
 /* Wall-shear-stress node: an active FLUID node next to a CORNEA or IRIS solid, with the
@@ -132,6 +150,8 @@ typedef struct aq_wall_node {
  *                   absolute form when ||u|| = 0); resid_T the same with T - T_ref
  *   u_max           max |u|; mass_flow = sum h, mass_thermal = sum g over active nodes
  *   n_nonfinite     number of active nodes with a non-finite moment
+ *   u_seep          AQ_OUTLET_LUMPED: the seepage speed evaluated at this check step
+ *                   (in effect for the next check_interval steps); 0 otherwise
  */
 typedef struct aq_observables {
     int64_t step;
@@ -139,6 +159,7 @@ typedef struct aq_observables {
     double wss_cornea_mean, wss_cornea_max, wss_iris_mean, wss_iris_max;
     double resid_u, resid_T, u_max, mass_flow, mass_thermal;
     int64_t n_nonfinite;
+    double u_seep;
 } aq_observables;
 
 /* Read-only facts about a solver. */

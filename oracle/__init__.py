@@ -37,20 +37,21 @@ def build(force: bool = True) -> str:
 
 class OrParams(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("periodic_x", C.c_int32),
-                ("periodic_y", C.c_int32), ("check_interval", C.c_int32), ("pad_", C.c_int32),
+                ("periodic_y", C.c_int32), ("check_interval", C.c_int32), ("outlet_mode", C.c_int32),
                 ("tau_f", C.c_double), ("tau_t", C.c_double), ("w0", C.c_double),
                 ("u_in_x", C.c_double), ("u_in_y", C.c_double),
                 ("p_ref", C.c_double), ("p_out", C.c_double), ("p_init", C.c_double),
                 ("T_ref", C.c_double), ("T_init", C.c_double), ("T0", C.c_double),
                 ("T_cornea", C.c_double), ("T_iris", C.c_double), ("T_inlet", C.c_double),
-                ("gbeta", C.c_double), ("gravity_angle", C.c_double), ("K", C.c_double)]
+                ("gbeta", C.c_double), ("gravity_angle", C.c_double), ("K", C.c_double),
+                ("K_tm", C.c_double), ("h_tm", C.c_double), ("p_sc", C.c_double)]
 
 
 class OrObservables(C.Structure):
     _fields_ = [("step", C.c_int64)] + [(n, C.c_double) for n in (
         "iop_gauge", "p_mean_fluid", "q_in", "q_out", "wss_cornea_mean", "wss_cornea_max",
         "wss_iris_mean", "wss_iris_max", "resid_u", "resid_T", "u_max", "mass_flow",
-        "mass_thermal")] + [("n_nonfinite", C.c_int64)]
+        "mass_thermal")] + [("n_nonfinite", C.c_int64), ("u_seep", C.c_double)]
 
     def asdict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -94,8 +95,6 @@ def make_params(p) -> OrParams:
     d = p if isinstance(p, dict) else p.asdict()
     op = OrParams()
     for name, _ in OrParams._fields_:
-        if name == "pad_":
-            continue
         setattr(op, name, d[name])
     return op
 

@@ -45,6 +45,14 @@
  *     at INLET (wall velocity u_in), anti-bounce-back pressure at OUTLET (p_out, the
  *     O(u^2) term dropped).  Thermal: anti-bounce-back Dirichlet at CORNEA, IRIS and
  *     INLET (T_cornea, T_iris, T_inlet), adiabatic bounce-back at BOX and OUTLET.
+ *   - Lumped meshwork outlet (the coupling of section 2.2.4 with eq. 2 and eq. 4): the
+ *     pressure in the meshwork falls linearly over its thickness h_TM from the IOP to the
+ *     Schlemm's-canal pressure p_sc, so Darcy's law gives the seepage speed
+ *     u_s = (K_TM / mu) (IOP - p_sc) / h_TM, with mu = nu (unit density) and IOP the mean
+ *     pressure over FLUID nodes.  u_s is re-evaluated at every check step and holds for
+ *     the next check interval; the first interval uses the initial pressure p_init.  OUTLET
+ *     nodes then act as a wall moving at u_s along their outward direction n (stored in
+ *     the wall bits: 0 +x, 1 +y, 2 -x, 3 -y): moving-wall bounce-back with that velocity.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, so rounding follows
  * the written order).
@@ -102,6 +110,7 @@ struct or_state {
     double* wall_nx;
     double* wall_ny;
     double q_out_last, q_in_last;
+    double u_seep;           /* lumped meshwork seepage speed in effect */
     double gx_hat, gy_hat;   /* (sin phi, cos phi): direction of the buoyant force for T > T0 */
     int64_t step;
     or_observables obs;
@@ -194,6 +203,12 @@ static void collide_node(const or_state* s, int porous, const double* h8, const 
 }
 
 /* ---------------------------------------------------------------- boundaries */
+/* eq. 4 over the meshwork thickness: u = (K/mu) (p_IOP - p_sc) / h_TM, mu = nu at unit density */
+static double seepage_speed(const or_params* P, double p_iop)
+{
+    return P->K_tm / nu_of(P) * ((p_iop - P->p_sc) / P->h_tm);
+}
+
 static double wall_temperature(const or_state* s, int wall)
 {
     return wall == OR_WALL_CORNEA ? s->P.T_cornea : s->P.T_iris;
@@ -241,6 +256,11 @@ static void step_once(or_state* s)
                     double eu = ex[i] * P->u_in_x + ey[i] * P->u_in_y;
                     *back = hout - 6.0 * w_flow(i) * eu;                /* moving wall u_in */
                     q_in += *back - hout;
+                } else if (P->outlet_mode == OR_OUTLET_LUMPED) { /* OR_OUTLET, lumped meshwork */
+                    int d = s->wall[kk] + 1;                            /* outward axis link */
+                    double eu = (ex[i] * ex[d] + ey[i] * ey[d]) * s->u_seep;
+                    *back = hout - 6.0 * w_flow(i) * eu;                /* moving wall u_s n */
+                    q_out += hout - *back;
                 } else { /* OR_OUTLET */
                     *back = -hout + 2.0 * lambda_i(i) * (P->p_out - P->p_ref); /* pressure ABB */
                     q_out += hout - *back;
@@ -347,6 +367,10 @@ static void observe(or_state* s)
     o->mass_flow = mf;
     o->mass_thermal = mt;
     o->n_nonfinite = bad;
+    /* lumped meshwork: Darcy seepage from the pressure drop across it, for the next interval */
+    if (P->outlet_mode == OR_OUTLET_LUMPED)
+        s->u_seep = seepage_speed(P, o->p_mean_fluid);
+    o->u_seep = s->u_seep;
 }
 
 static void set_prev_from_state(or_state* s)
@@ -367,6 +391,7 @@ or_state* or_create(const or_params* P, const uint8_t* mask, int n_walls, const 
                     const int32_t* wall_id, const double* wall_nx, const double* wall_ny)
 {
     if (P->nx < 3 || P->ny < 3 || P->tau_f <= 0.5 || P->tau_t <= 0.5 || P->check_interval < 1) return NULL;
+    if (P->outlet_mode == OR_OUTLET_LUMPED && !(P->K_tm > 0 && P->h_tm > 0)) return NULL;
     or_state* s = (or_state*)calloc(1, sizeof(or_state));
     s->P = *P;
     s->gx_hat = sin(P->gravity_angle);
@@ -412,6 +437,7 @@ or_state* or_create(const or_params* P, const uint8_t* mask, int n_walls, const 
     }
     set_prev_from_state(s);
     memset(&s->obs, 0, sizeof(s->obs));
+    s->u_seep = P->outlet_mode == OR_OUTLET_LUMPED ? seepage_speed(P, P->p_init) : 0.0;
     return s;
 }
 

@@ -7,14 +7,19 @@
 enum { OR_SOLID = 0, OR_FLUID = 1, OR_POROUS = 2, OR_INLET = 3, OR_OUTLET = 4 };
 enum { OR_WALL_BOX = 0, OR_WALL_CORNEA = 1, OR_WALL_IRIS = 2 };
 
+/* outlet_mode: 0 = pressure outlet at p_out; 1 = lumped trabecular meshwork (Darcy
+ * seepage velocity from the IOP, applied as a velocity boundary condition) */
+enum { OR_OUTLET_PRESSURE = 0, OR_OUTLET_LUMPED = 1 };
+
 typedef struct {
-    int32_t nx, ny, periodic_x, periodic_y, check_interval, pad_;
+    int32_t nx, ny, periodic_x, periodic_y, check_interval, outlet_mode;
     double tau_f, tau_t, w0;
     double u_in_x, u_in_y;
     double p_ref, p_out, p_init;
     double T_ref, T_init, T0;
     double T_cornea, T_iris, T_inlet;
     double gbeta, gravity_angle, K;
+    double K_tm, h_tm, p_sc;   /* lumped meshwork: permeability, thickness, Schlemm's-canal pressure */
 } or_params;
 
 typedef struct {
@@ -23,6 +28,7 @@ typedef struct {
     double wss_cornea_mean, wss_cornea_max, wss_iris_mean, wss_iris_max;
     double resid_u, resid_T, u_max, mass_flow, mass_thermal;
     int64_t n_nonfinite;
+    double u_seep;             /* lumped meshwork: seepage velocity for the next interval */
 } or_observables;
 
 typedef struct or_state or_state;

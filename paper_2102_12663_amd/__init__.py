@@ -35,10 +35,10 @@ class AqParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32),
                 ("storage", C.c_int32), ("check_interval", C.c_int32),
                 ("fp16_exp_flow", C.c_int32), ("fp16_exp_thermal", C.c_int32),
-                ("reserved0", C.c_int32)] + [(n, C.c_double) for n in (
+                ("outlet_mode", C.c_int32)] + [(n, C.c_double) for n in (
                     "tau_f", "tau_t", "w0", "u_in_x", "u_in_y", "p_ref", "p_out", "p_init",
                     "T_ref", "T_init", "T0", "T_cornea", "T_iris", "T_inlet", "gbeta",
-                    "gravity_angle", "K")]
+                    "gravity_angle", "K", "K_tm", "h_tm", "p_sc")]
 
 
 class AqWallNode(C.Structure):
@@ -49,7 +49,7 @@ class AqObservables(C.Structure):
     _fields_ = [("step", C.c_int64)] + [(n, C.c_double) for n in (
         "iop_gauge", "p_mean_fluid", "q_in", "q_out", "wss_cornea_mean", "wss_cornea_max",
         "wss_iris_mean", "wss_iris_max", "resid_u", "resid_T", "u_max", "mass_flow",
-        "mass_thermal")] + [("n_nonfinite", C.c_int64)]
+        "mass_thermal")] + [("n_nonfinite", C.c_int64), ("u_seep", C.c_double)]
 
     def asdict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

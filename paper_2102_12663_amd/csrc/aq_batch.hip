@@ -316,13 +316,20 @@ int convert_to_f32(aq_batch* b, int i)
         b->pool.release(off, L32.total);
         return fail(AQ_ENOMEM, "no device memory for the state conversion");
     }
-    StepArgs a = make_args(s16, s16->cur != 0);   // src = prev: pulls to the current state
+    StepArgs a = make_readout_args(s16);   // src = prev: pulls to the current state
     e = launch_unpack(s16->mode, a, 7, 0, P.p_ref, dense, b->stream);
     aq_solver* s32 = nullptr;
     int rc = AQ_OK;
     if (e == hipSuccess) {
         rc = create_common(&P, mask.data(), walls.data(), s16->n_walls, b->arena + off, L32.total, b->stream, false, &s32);
         if (rc == AQ_OK) rc = aq_set_tile(s32, s16->tile_x, s16->tile_y);
+        if (rc == AQ_OK) {
+            // lumped outlet: the seepage speeds carry over with the state
+            const size_t uo = s32->L.off_counters + kUseepOffset;
+            e = hipMemcpyAsync(s32->base + uo, s16->base + s16->L.off_counters + kUseepOffset, 16,
+                               hipMemcpyDeviceToDevice, b->stream);
+            if (e != hipSuccess) rc = fail(AQ_EDEVICE, std::string("seepage speed copy: ") + hipGetErrorString(e));
+        }
         if (rc == AQ_OK) rc = set_state(s32, dense);
         if (rc == AQ_OK) {
             s32->step = s16->step;
@@ -489,6 +496,7 @@ int aq_batch_run(aq_batch* b, int32_t n_intervals)
         if (!sl.used || !sl.running) continue;
         aq_solver* s = sl.s;
         s->step += dn;
+        s->ro_slot = 1;   // every interval ends with a reducing step and its finish kernel
         s->checks += n_intervals;
         s->last_check_step = s->step;
         sl.steps += dn;

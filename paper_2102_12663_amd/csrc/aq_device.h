@@ -48,6 +48,15 @@ struct StepArgs {
     double tw_cornea, tw_iris, tw_inlet;   // T_w - T_ref
     double sf, inv_sf, st, inv_st;         // F16S scales (flow, thermal)
 
+    // lumped meshwork outlet: OUTLET links are walls moving at the seepage speed *useep
+    // along the node's outward direction; the finish kernel re-evaluates it at check steps
+    int lumped;
+    const double* useep;      // seepage speed the pull uses
+    double* useep_state;      // [0] in effect for the next steps, [1] the one before it
+    double k_mu, h_tm;        // K_tm / mu (mu = nu at unit density) and the thickness
+    double p_ref, p_sc;
+    double n_fluid;           // FLUID nodes (IOP mean)
+
     // reductions (check steps only)
     double* partials;         // [gridDim][NRED]
     double* obs;              // [OBS_RING][NRED]

@@ -63,6 +63,9 @@ inline Layout make_layout(const aq_params& P, int n_walls)
 
 inline double bytes_per_update(int mode) { return 2.0 * NPOP * storage_size(mode) + 1.0; }
 
+// Lumped-outlet seepage speeds: two doubles in the counters block.
+constexpr size_t kUseepOffset = 128;
+
 // Working sets (bytes moved per step) above this use non-temporal population stores; the
 // MI355X last-level cache (MALL) holds 256 MB.
 constexpr double kMallBytes = 192.0 * 1024 * 1024;
@@ -95,6 +98,7 @@ struct aq_solver {
     int tiles_x2 = 0, n_tiles2 = 0;
     std::vector<int> htiles;      // active tile indices (host copy of the device list)
     int cur = 0;                  // 0: buffer A holds the state
+    int ro_slot = 0;              // lumped outlet: seepage-speed slot the last pull used
     int64_t step = 0;
     unsigned int checks = 0;      // reducing launches enqueued
     int64_t last_check_step = 0;
@@ -106,6 +110,7 @@ struct aq_solver {
     hipGraph_t plain_graph_src[2] = {nullptr, nullptr};
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     double* obs_pinned = nullptr; // host pinned, 2 * NRED
+    double useep_host[2] = {0.0, 0.0};   // lumped outlet: last seepage speeds set from the host
 
     void* popA() const { return base + L.off_a; }
     void* popB() const { return base + L.off_b; }
@@ -117,6 +122,9 @@ namespace aq {
 StepArgs make_args(const aq_solver* s, bool a_is_src);
 StepArgs make_args2(const aq_solver* s, bool a_is_src);
 int set_state(aq_solver* s, const double* pops);
+int set_useep(aq_solver* s, double now, double before);
+StepArgs make_readout_args(const aq_solver* s);
+double seepage_speed(const aq_params& P, double p_iop);
 void raw_to_obs(const aq_solver* s, const double* raw, int64_t step, aq_observables* o);
 int create_common(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls,
                   void* arena, size_t arena_bytes, void* stream, bool own, aq_solver** out);

@@ -139,10 +139,17 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const uint8_t* nt,
             const R corr = R(6.0) * wflow<R>(i) * (R(EX[i]) * R(a.uin_x) + R(EY[i]) * R(a.uin_y));
             n.h[i] = v + corr;
             n.qin += corr;
-        } else if (c == OUTLET) {                              // pressure anti-bounce-back
-            const R out = -v + R(2.0) * lam<R>(i) * R(a.dp_out);
-            n.qout += v - out;
-            n.h[i] = out;
+        } else if (c == OUTLET) {
+            if (a.lumped) {                                    // wall moving at u_s n (meshwork)
+                const int d = ((nt[i] >> WALL_SHIFT) & 3) + 1;
+                const R corr = R(6.0) * wflow<R>(i) * (R(EX[i] * EX[d] + EY[i] * EY[d]) * R(*a.useep));
+                n.h[i] = v + corr;
+                n.qout -= corr;
+            } else {                                           // pressure anti-bounce-back
+                const R out = -v + R(2.0) * lam<R>(i) * R(a.dp_out);
+                n.qout += v - out;
+                n.h[i] = out;
+            }
         }                                                      // SOLID: half-way bounce-back
     }
 #pragma unroll
@@ -380,14 +387,32 @@ __device__ void block_reduce_store(double* r, double* out)
 // the 4 waves in order) and append the result to an observables ring.  Called by one
 // block of 256 threads.  Single-lattice and batched runs use this same function, so an
 // instance gives bitwise the same observables alone or in a batch.
-__device__ void finish_sum(const double* partials, int n, double* obs, unsigned int* obs_count, double* latest)
+__device__ void finish_sum(const StepArgs& a, const double* partials, int n, double* latest)
 {
+    double* obs = a.obs;
+    unsigned int* obs_count = a.obs_count;
     __shared__ double sm[4][NRED];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double acc[NRED];
 #pragma unroll
     for (int j = 0; j < NRED; j++) acc[j] = 0.0;
-    for (int b = threadIdx.x; b < n; b += 256) {
+    // four partials per pass, loaded before any is added (same order of additions)
+    int b = threadIdx.x;
+    for (; b + 3 * 256 < n; b += 4 * 256) {
+        double v[4][NRED];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const double* pb = partials + (long long)(b + u * 256) * NRED;
+#pragma unroll
+            for (int j = 0; j < NRED; j++) v[u][j] = pb[j];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+#pragma unroll
+            for (int j = 0; j < NRED; j++) acc[j] = red_is_max(j) ? fmax(acc[j], v[u][j]) : acc[j] + v[u][j];
+        }
+    }
+    for (; b < n; b += 256) {
         const double* pb = partials + (long long)b * NRED;
 #pragma unroll
         for (int j = 0; j < NRED; j++) acc[j] = red_is_max(j) ? fmax(acc[j], pb[j]) : acc[j] + pb[j];
@@ -417,13 +442,20 @@ __device__ void finish_sum(const double* partials, int n, double* obs, unsigned 
             if (latest) latest[j] = v;
         }
         *obs_count = c + 1;
+        if (a.lumped) {
+            // Darcy seepage across the meshwork from this check step's IOP, in effect from
+            // the next step on; the previous value stays readable for the read-out pull
+            const double p_iop = a.p_ref + (a.n_fluid > 0 ? o[R_DP_FLUID] / a.n_fluid : 0.0);
+            a.useep_state[1] = a.useep_state[0];
+            a.useep_state[0] = a.k_mu * ((p_iop - a.p_sc) / a.h_tm);   // eq. 4 across h_TM
+        }
     }
     __syncthreads();
 }
 
 __global__ __launch_bounds__(256) void finish_kernel(StepArgs a)
 {
-    finish_sum(a.partials, a.n_tiles, a.obs, a.obs_count, nullptr);
+    finish_sum(a, a.partials, a.n_tiles, nullptr);
 }
 
 // Wall-shear stress |t - (t.n) n| with t = sigma n, sigma = -(1 - omega/2) Pi^neq.
@@ -617,8 +649,7 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(BatchArgs b)
     for (int sl = blockIdx.x; sl < b.max_slots; sl += gridDim.x) {
         const InstDesc* d = b.inst + sl;
         if (!d->running || d->mode != b.mode) continue;
-        finish_sum(b.partials + (long long)d->work_start * NRED, d->work_count, d->a.obs, d->a.obs_count,
-                   b.latest + (long long)sl * NRED);
+        finish_sum(d->a, b.partials + (long long)d->work_start * NRED, d->work_count, b.latest + (long long)sl * NRED);
     }
 }
 
@@ -696,7 +727,12 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
             const R corr = R(6.0) * wflow<R>(i) * (R(EX[i]) * R(a.uin_x) + R(EY[i]) * R(a.uin_y));
             n.h[i] = v + corr;
         } else if (c == OUTLET) {
-            n.h[i] = -v + R(2.0) * lam<R>(i) * R(a.dp_out);
+            if (a.lumped) {
+                const int d = ((nt[i] >> WALL_SHIFT) & 3) + 1;
+                n.h[i] = v + R(6.0) * wflow<R>(i) * (R(EX[i] * EX[d] + EY[i] * EY[d]) * R(*a.useep));
+            } else {
+                n.h[i] = -v + R(2.0) * lam<R>(i) * R(a.dp_out);
+            }
         }
     }
 #pragma unroll
@@ -940,7 +976,10 @@ __global__ __launch_bounds__(256) void scatter_kernel(StepArgs a, const double* 
             R v;
             if (c == SOLID) v = f;
             else if (c == INLET) v = f - R(6.0) * wflow<R>(i) * (R(EX[i]) * R(a.uin_x) + R(EY[i]) * R(a.uin_y));
-            else v = R(2.0) * lam<R>(i) * R(a.dp_out) - f;
+            else if (a.lumped) {
+                const int dd = ((a.type[ks] >> WALL_SHIFT) & 3) + 1;
+                v = f - R(6.0) * wflow<R>(i) * (R(EX[i] * EX[dd] + EY[i] * EY[dd]) * R(*a.useep));
+            } else v = R(2.0) * lam<R>(i) * R(a.dp_out) - f;
             T::st(X + (long long)(OPP[i] - 1) * a.qs + k, v, sf);
         }
     }

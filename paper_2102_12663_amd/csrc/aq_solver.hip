@@ -71,7 +71,31 @@ StepArgs make_args(const aq_solver* s, bool a_is_src)
     a.wall_id = (const int*)(b + s->L.off_walls + 4 * (size_t)std::max(s->n_walls, 1));
     a.wall_n = (const double*)(b + s->L.off_walls + 8 * (size_t)std::max(s->n_walls, 1));
     a.n_walls = s->n_walls;
+    a.lumped = P.outlet_mode == AQ_OUTLET_LUMPED ? 1 : 0;
+    a.useep_state = (double*)(b + s->L.off_counters + kUseepOffset);
+    a.useep = a.useep_state;          // a step pulls with the speed in effect
+    a.k_mu = a.lumped ? P.K_tm / nu : 0.0;
+    a.h_tm = a.lumped ? P.h_tm : 1.0;
+    a.p_ref = P.p_ref;
+    a.p_sc = P.p_sc;
+    a.n_fluid = (double)s->n_fluid;
     return a;
+}
+
+// Arguments of a read-out pull of the current state: the lumped outlet's links must use
+// the seepage speed the last step's pull used (a check step replaces the speed in effect).
+StepArgs make_readout_args(const aq_solver* s)
+{
+    StepArgs a = make_args(s, s->cur != 0);
+    a.useep = a.useep_state + s->ro_slot;
+    return a;
+}
+
+// Seepage speed of the lumped meshwork at pressure p_iop (eq. 4 across the thickness).
+double seepage_speed(const aq_params& P, double p_iop)
+{
+    const double nu = (2.0 * P.tau_f - 1.0) / 6.0;
+    return P.K_tm / nu * ((p_iop - P.p_sc) / P.h_tm);
 }
 
 // Arguments of the two-steps-per-launch kernel: the same lattice with the fused tile list.
@@ -99,6 +123,11 @@ int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls,
     if (P->check_interval < 2 || (P->check_interval & 1)) return fail(AQ_EINVAL, "check_interval must be even and >= 2");
     if (P->fp16_exp_flow < -1 || P->fp16_exp_flow > 40 || P->fp16_exp_thermal < -1 || P->fp16_exp_thermal > 40)
         return fail(AQ_EINVAL, "fp16 exponents must be in [-1, 40]");
+    if (P->outlet_mode != AQ_OUTLET_PRESSURE && P->outlet_mode != AQ_OUTLET_LUMPED)
+        return fail(AQ_EINVAL, "unknown outlet_mode");
+    if (P->outlet_mode == AQ_OUTLET_LUMPED &&
+        !(P->K_tm > 0.0 && P->h_tm > 0.0 && std::isfinite(P->K_tm) && std::isfinite(P->h_tm) && std::isfinite(P->p_sc)))
+        return fail(AQ_EINVAL, "lumped outlet needs finite K_tm > 0, h_tm > 0 and p_sc");
     const int nx = P->nx, ny = P->ny;
     for (int y = 0; y < ny; y++)
         for (int x = 0; x < nx; x++) {
@@ -109,6 +138,33 @@ int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls,
             if (act && (x == 0 || y == 0 || x == nx - 1 || y == ny - 1))
                 return fail(AQ_EINVAL, "active node on the outer frame");
         }
+    if (P->outlet_mode == AQ_OUTLET_LUMPED) {
+        // The seepage speed is explicit over a check interval.  The flow mass of the
+        // chamber, (5/3) N dp, then relaxes toward its steady level by the factor
+        // 1 - D r per interval, r = 3 A K_tm / (5 N nu h_tm), where A = sum over links
+        // into OUTLET nodes of 6 w_i e_i.n is the outflow area.  Accept D r <= 1
+        // (monotone approach; the coupling oscillates beyond and diverges past 2).
+        static const int lx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, ly[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+        double area = 0.0, n_act = 0.0;
+        for (int y = 1; y < ny - 1; y++)
+            for (int x = 1; x < nx - 1; x++) {
+                const int c = mask[(size_t)y * nx + x] & 7;
+                if (c != AQ_FLUID && c != AQ_POROUS) continue;
+                n_act += 1.0;
+                for (int i = 1; i <= 8; i++) {
+                    const uint8_t m = mask[(size_t)(y + ly[i]) * nx + x + lx[i]];
+                    if ((m & 7) != AQ_OUTLET) continue;
+                    const int d = ((m >> 3) & 3) + 1;
+                    area += 6.0 * (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0) * (lx[i] * lx[d] + ly[i] * ly[d]);
+                }
+            }
+        if (!(area > 0.0)) return fail(AQ_EINVAL, "lumped outlet: no outflow area (no link into an OUTLET node along its direction)");
+        const double nu = (2.0 * P->tau_f - 1.0) / 6.0;
+        const double dr = P->check_interval * 3.0 * area * P->K_tm / (5.0 * n_act * nu * P->h_tm);
+        if (dr > 1.0)
+            return fail(AQ_EINVAL, "lumped outlet: check_interval * 3 A K_tm / (5 N nu h_tm) = " + std::to_string(dr) +
+                                       " > 1 (the explicit coupling would overshoot); lower check_interval or K_tm");
+    }
     if (n_walls < 0 || (n_walls > 0 && !walls)) return fail(AQ_EINVAL, "invalid wall list");
     for (int w = 0; w < n_walls; w++) {
         const int k = walls[w].node;
@@ -266,6 +322,7 @@ int launch_one(aq_solver* s)
     HIPCHK(launch_step(s->mode, reduce, a, s->stream));
     s->cur ^= 1;
     s->step++;
+    s->ro_slot = reduce ? 1 : 0;   // a reducing step's finish kernel moves the speed on
     if (reduce) {
         s->checks++;
         s->last_check_step = s->step;
@@ -283,6 +340,7 @@ static int launch_graph_part(aq_solver* s)
     HIPCHK(hipGraphLaunch(s->plain_graph[s->cur], s->stream));
     s->cur ^= pp.graph_launches & 1;
     s->step += pp.graph_steps;
+    s->ro_slot = 0;
     return AQ_OK;
 }
 
@@ -316,6 +374,10 @@ void raw_to_obs(const aq_solver* s, const double* r, int64_t step, aq_observable
     o->mass_flow = r[R_MASS_F];
     o->mass_thermal = r[R_MASS_T];
     o->n_nonfinite = (int64_t)r[R_NONFINITE];
+    // the speed the finish kernel derived from this check step (same expression)
+    o->u_seep = P.outlet_mode == AQ_OUTLET_LUMPED ? (P.K_tm / ((2.0 * P.tau_f - 1.0) / 6.0)) *
+                                                        ((o->p_mean_fluid - P.p_sc) / P.h_tm)
+                                                  : 0.0;
 }
 
 // Read the raw sums of reduction number `idx` (0-based) after the stream has passed it.
@@ -339,7 +401,18 @@ int set_state(aq_solver* s, const double* pops)
     HIPCHK(launch_scatter(s->mode, sc, pops, s->P.p_init - s->P.p_ref, s->P.T_init - s->P.T_ref, s->stream));
     StepArgs st = make_args(s, !prev_is_b);        // src = prev, dst = cur
     HIPCHK(launch_step(s->mode, false, st, s->stream));
+    s->ro_slot = 0;
     HIPCHK(launch_unpack(s->mode, st, 6, 0, s->P.p_ref, nullptr, s->stream));
+    return AQ_OK;
+}
+
+// Both seepage-speed slots of the lumped outlet (host values, async copy).
+int set_useep(aq_solver* s, double now, double before)
+{
+    s->useep_host[0] = now;
+    s->useep_host[1] = before;
+    HIPCHK(hipMemcpyAsync(s->base + s->L.off_counters + kUseepOffset, s->useep_host, 16, hipMemcpyHostToDevice,
+                          s->stream));
     return AQ_OK;
 }
 
@@ -352,6 +425,12 @@ int init_state(aq_solver* s)
     s->diverged = false;
     HIPCHK(hipMemsetAsync(s->base + s->L.off_counters, 0, 256, s->stream));
     HIPCHK(hipMemsetAsync(s->base + s->L.off_obs, 0, OBS_RING * NRED * 8, s->stream));
+    if (s->P.outlet_mode == AQ_OUTLET_LUMPED) {
+        // the first interval drains at the speed the initial pressure drives
+        const double u0 = seepage_speed(s->P, s->P.p_init);
+        int rc = set_useep(s, u0, u0);
+        if (rc) return rc;
+    }
     int rc = set_state(s, nullptr);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -602,7 +681,7 @@ int aq_read_field(aq_solver* s, int32_t field, int32_t q, double* host, size_t c
     if (field < AQ_FIELD_P || field > AQ_FIELD_POP_HEAT) return fail(AQ_EINVAL, "unknown field");
     if (field == AQ_FIELD_POP_FLOW && (q < 1 || q > 8)) return fail(AQ_EINVAL, "flow population q must be 1..8");
     if (field == AQ_FIELD_POP_HEAT && (q < 0 || q > 4)) return fail(AQ_EINVAL, "thermal population q must be 0..4");
-    StepArgs a = make_args(s, s->cur != 0);   // src = prev: pulls to the current state
+    StepArgs a = make_readout_args(s);   // src = prev: pulls to the current state
     double* scratch = (double*)(s->base + s->L.off_scratch);
     HIPCHK(launch_unpack(s->mode, a, field, q, s->P.p_ref, scratch, s->stream));
     HIPCHK(hipMemcpyAsync(host, scratch, count * 8, hipMemcpyDeviceToHost, s->stream));
@@ -679,6 +758,7 @@ int aq_time_step_kernel(aq_solver* s, int32_t n_launch, double* ms)
         s->cur ^= 1;
         s->step++;
     }
+    s->ro_slot = 0;
     HIPCHK(hipEventRecord(s->ev[1], s->stream));
     HIPCHK(hipEventSynchronize(s->ev[1]));
     float t = 0;
@@ -711,6 +791,7 @@ int aq_time_fused_kernel(aq_solver* s, int32_t n_launch, double* ms)
     HIPCHK(launch_step(s->mode, false, make_args(s, s->cur == 0), s->stream));
     s->cur ^= 1;
     s->step++;
+    s->ro_slot = 0;
     HIPCHK(hipEventSynchronize(s->ev[1]));
     float t = 0;
     HIPCHK(hipEventElapsedTime(&t, s->ev[0], s->ev[1]));
@@ -797,11 +878,16 @@ int aq_save(aq_solver* s, const char* path)
     HIPCHK(hipStreamSynchronize(s->stream));
     FILE* f = std::fopen(path, "wb");
     if (!f) return fail(AQ_EINVAL, std::string("cannot open ") + path);
-    const uint32_t magic = 0x4D424C41u, version = 1;   // "ALBM"
+    const uint32_t magic = 0x4D424C41u, version = 2;   // "ALBM"
     int32_t hdr[4] = {s->exp_f, s->exp_t, (int32_t)s->checks, s->cur};
+    int32_t hdr2[2] = {s->ro_slot, 0};
+    double useep[2] = {0.0, 0.0};   // lumped outlet: seepage speeds (in effect, previous)
+    HIPCHK(hipMemcpyAsync(useep, s->base + s->L.off_counters + kUseepOffset, 16, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
     bool ok = std::fwrite(&magic, 4, 1, f) == 1 && std::fwrite(&version, 4, 1, f) == 1 &&
               std::fwrite(&s->P, sizeof(aq_params), 1, f) == 1 && std::fwrite(&s->step, 8, 1, f) == 1 &&
               std::fwrite(&s->last_check_step, 8, 1, f) == 1 && std::fwrite(hdr, 16, 1, f) == 1 &&
+              std::fwrite(hdr2, 8, 1, f) == 1 && std::fwrite(useep, 16, 1, f) == 1 &&
               std::fwrite(buf.data(), 1, buf.size(), f) == buf.size();
     std::fclose(f);
     return ok ? AQ_OK : fail(AQ_EINVAL, "short write");
@@ -815,11 +901,13 @@ int aq_load(aq_solver* s, const char* path)
     uint32_t magic = 0, version = 0;
     aq_params P;
     int64_t step = 0, last = 0;
-    int32_t hdr[4];
+    int32_t hdr[4], hdr2[2];
+    double useep[2];
     bool ok = std::fread(&magic, 4, 1, f) == 1 && std::fread(&version, 4, 1, f) == 1 &&
               std::fread(&P, sizeof(aq_params), 1, f) == 1 && std::fread(&step, 8, 1, f) == 1 &&
-              std::fread(&last, 8, 1, f) == 1 && std::fread(hdr, 16, 1, f) == 1;
-    if (!ok || magic != 0x4D424C41u || version != 1 || std::memcmp(&P, &s->P, sizeof(aq_params)) != 0) {
+              std::fread(&last, 8, 1, f) == 1 && std::fread(hdr, 16, 1, f) == 1 &&
+              std::fread(hdr2, 8, 1, f) == 1 && std::fread(useep, 16, 1, f) == 1;
+    if (!ok || magic != 0x4D424C41u || version != 2 || std::memcmp(&P, &s->P, sizeof(aq_params)) != 0) {
         std::fclose(f);
         return fail(AQ_EINVAL, "checkpoint does not match this solver");
     }
@@ -841,6 +929,10 @@ int aq_load(aq_solver* s, const char* path)
     s->last_check_step = last;
     s->exp_f = hdr[0];
     s->exp_t = hdr[1];
+    s->ro_slot = hdr2[0] & 1;
+    int rc = set_useep(s, useep[0], useep[1]);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(s->stream));
     s->diverged = false;
     // the observables ring is not part of the checkpoint; the counters keep their
     // device values so the next check step lands in the expected slot

@@ -3,6 +3,7 @@ argument validation fails with AQ_EINVAL before any device work (no GPU needed).
 import ctypes as C
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -36,11 +37,27 @@ def test_header_and_exports_agree(aq):
     assert aq.version().startswith("aqlbm")
 
 
-def test_struct_sizes_match_header(aq):
-    # aq_params: 8 int32 + 17 doubles; aq_wall_node: 2 int32 + 2 doubles
-    assert C.sizeof(aq.AqParams) == 8 * 4 + 17 * 8
-    assert C.sizeof(aq.AqWallNode) == 24
-    assert C.sizeof(aq.AqObservables) == 8 + 13 * 8 + 8
+def test_struct_layouts_match_header(aq, tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets that a C
+    compiler gives the header's structure (compiled and run here with gcc)."""
+    structs = {"aq_params": aq.AqParams, "aq_wall_node": aq.AqWallNode, "aq_observables": aq.AqObservables,
+               "aq_info": aq.AqInfo, "aq_result": aq.AqResult, "aq_batch_info": aq.AqBatchInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "aqlbm.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in structs.items():
+        assert got[(cname, "sizeof")] == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
 
 
 def _create(aq, p, mask, walls=None):
@@ -59,6 +76,10 @@ def _create(aq, p, mask, walls=None):
     ({"check_interval": 0}, "check_interval"),
     ({"K": 0.0}, "K"),
     ({"w0": 1.0}, "w0"),
+    ({"outlet_mode": 2}, "outlet_mode"),
+    ({"outlet_mode": 1, "K_tm": 0.0}, "lumped"),
+    ({"outlet_mode": 1, "h_tm": -1.0}, "lumped"),
+    ({"outlet_mode": 1, "p_sc": float("nan")}, "lumped"),
 ])
 def test_invalid_parameters_rejected(aq, change, msg):
     p, mask, walls, geo = A.config0()
