@@ -380,7 +380,7 @@ def config0():
 
 
 def sweep_instance(seed: int, nx: int, ny: int, *, tau_f=None, phi_deg=None, storage=F64,
-                   check_interval=100):
+                   check_interval=100, tm="resolved"):
     """One draw of the parameter sweep: alpha ~ U(25, 45) deg, u_in ~ U(0.5, 2) x 1e-4,
     Da ~ 10^U(-5, -3), Ra ~ 10^U(3, 5).  tau_f and phi default to 0.8 and 0 deg unless
     drawn (tau_f ~ U(0.55, 1.2), phi ~ U(0, 90) deg) when passed as 'draw'."""
@@ -396,9 +396,9 @@ def sweep_instance(seed: int, nx: int, ny: int, *, tau_f=None, phi_deg=None, sto
         phi_deg = 90.0 * draw(seed, "phi")
     elif phi_deg is None:
         phi_deg = 0.0
-    mask, walls, geo = eye_mask(nx, ny, alpha)
+    mask, walls, geo = eye_mask(nx, ny, alpha, tm=tm)
     p = eye_params(nx, ny, geo, u_in=u_in, Da=Da, Ra=Ra, tau_f=tau_f, phi_deg=phi_deg,
-                   storage=storage, check_interval=check_interval)
+                   storage=storage, check_interval=check_interval, tm=tm)
     return p, mask, walls, geo
 
 
