@@ -246,6 +246,14 @@ int aq_time_step_kernel(aq_solver* s, int32_t n_launch, double* ms_per_launch);
  * exceeds the last-level cache.  Results are bitwise the same either way. */
 int aq_set_fusion(aq_solver* s, int32_t enable);
 
+/* Lumped meshwork outlet (AQ_OUTLET_LUMPED only): replace K_tm, h_tm and p_sc of a live
+ * solve (the calibration loop of section 3.1 adjusts the meshwork thickness until the
+ * steady IOP is the healthy one).  The seepage speed in effect becomes that of the new
+ * values at the last check step's IOP (p_init before the first check); later check steps
+ * re-evaluate it as usual.  Synchronises the solver's stream.  AQ_EINVAL for another
+ * outlet, invalid values or a coupling the check interval cannot hold (as aq_create). */
+int aq_set_outlet(aq_solver* s, double K_tm, double h_tm, double p_sc);
+
 /* Time n_launch back-to-back two-step launches (HIP events on the solver's stream);
  * *ms_per_launch receives the average per launch (two time steps).  One single step
  * follows, untimed.  The state advances by 2 * n_launch + 1 steps without reductions. */
@@ -325,6 +333,16 @@ int aq_batch_observe(aq_batch* b, int32_t slot, aq_observables* out);
 
 /* Free a slot (running or finished). */
 int aq_batch_release(aq_batch* b, int32_t slot);
+
+/* aq_set_outlet on the instance in a slot (running or finished and kept). */
+int aq_batch_set_outlet(aq_batch* b, int32_t slot, double K_tm, double h_tm, double p_sc);
+
+/* Put a finished instance admitted with keep back into the batch from its current state
+ * (a warm start, e.g. after aq_batch_set_outlet), to run until its residual falls below
+ * tol or for at most max_steps more steps; its result is reported again by aq_batch_poll.
+ * AQ_ESTATE if the slot is running, was not kept, or failed (diverged); AQ_EBUSY if the
+ * active-node cap or the work list has no room. */
+int aq_batch_resume(aq_batch* b, int32_t slot, double tol, int64_t max_steps);
 
 int aq_batch_get_info(aq_batch* b, aq_batch_info* out);
 

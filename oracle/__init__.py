@@ -74,6 +74,7 @@ def lib():
         L.or_step.argtypes = [C.c_void_p, C.c_int64]
         L.or_step_count.argtypes = [C.c_void_p]
         L.or_step_count.restype = C.c_int64
+        L.or_set_outlet.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double]
         L.or_observables_get.argtypes = [C.c_void_p, C.POINTER(OrObservables)]
         L.or_fields.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.or_get_populations.argtypes = [C.c_void_p, dp, dp]
@@ -137,6 +138,12 @@ class Oracle:
 
     def step(self, n: int):
         lib().or_step(self._s, int(n))
+        return self
+
+    def set_outlet(self, K_tm: float, h_tm: float, p_sc: float):
+        """New lumped-meshwork constants; the seepage speed in effect is re-evaluated at
+        once from the last check step's IOP (p_init before the first check)."""
+        lib().or_set_outlet(self._s, K_tm, h_tm, p_sc)
         return self
 
     @property

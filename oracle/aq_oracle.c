@@ -462,6 +462,17 @@ void or_step(or_state* s, int64_t nsteps)
 
 int64_t or_step_count(const or_state* s) { return s->step; }
 
+/* Replace the lumped meshwork's K_TM, h_TM and p_sc (the thickness calibration of section
+ * 3.1).  The seepage speed in effect becomes that of the new values at the IOP of the last
+ * check step (p_init before the first one). */
+void or_set_outlet(or_state* s, double K_tm, double h_tm, double p_sc)
+{
+    s->P.K_tm = K_tm;
+    s->P.h_tm = h_tm;
+    s->P.p_sc = p_sc;
+    s->u_seep = seepage_speed(&s->P, s->obs.step > 0 ? s->obs.p_mean_fluid : s->P.p_init);
+}
+
 void or_observables_get(const or_state* s, or_observables* out) { *out = s->obs; }
 
 /* Macroscopic fields of the current (pre-collision) state; NaN at non-active nodes. */

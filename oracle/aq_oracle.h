@@ -38,6 +38,7 @@ or_state* or_create(const or_params* P, const uint8_t* mask, int n_walls, const 
 void or_destroy(or_state* s);
 void or_step(or_state* s, int64_t nsteps);
 int64_t or_step_count(const or_state* s);
+void or_set_outlet(or_state* s, double K_tm, double h_tm, double p_sc);
 void or_observables_get(const or_state* s, or_observables* out);
 void or_fields(const or_state* s, double* dp, double* ux, double* uy, double* T);
 void or_get_populations(const or_state* s, double* h, double* g);

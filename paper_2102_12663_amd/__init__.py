@@ -26,9 +26,10 @@ EXPORTS = ("aq_version", "aq_last_error", "aq_required_bytes", "aq_create", "aq_
            "aq_destroy", "aq_step", "aq_run_to_steady", "aq_observe", "aq_read_field",
            "aq_write_populations", "aq_save", "aq_load", "aq_get_info", "aq_set_tile",
            "aq_time_step_kernel", "aq_run_intervals_timed", "aq_autotune_tile", "aq_set_fusion",
-           "aq_time_fused_kernel",
+           "aq_time_fused_kernel", "aq_set_outlet",
            "aq_batch_create", "aq_batch_admit", "aq_batch_run", "aq_batch_poll", "aq_batch_read_field",
-           "aq_batch_observe", "aq_batch_release", "aq_batch_get_info", "aq_batch_destroy")
+           "aq_batch_observe", "aq_batch_release", "aq_batch_get_info", "aq_batch_destroy",
+           "aq_batch_set_outlet", "aq_batch_resume")
 
 
 class AqParams(C.Structure):
@@ -128,6 +129,9 @@ def load_library(path: str = LIB_PATH):
     L.aq_run_intervals_timed.argtypes = [vp, i32, dp, dp]
     ip = C.POINTER(i32)
     L.aq_set_fusion.argtypes = [vp, i32]
+    L.aq_set_outlet.argtypes = [vp, C.c_double, C.c_double, C.c_double]
+    L.aq_batch_set_outlet.argtypes = [vp, i32, C.c_double, C.c_double, C.c_double]
+    L.aq_batch_resume.argtypes = [vp, i32, C.c_double, i64]
     L.aq_time_fused_kernel.argtypes = [vp, i32, dp]
     L.aq_autotune_tile.argtypes = [vp, i32, i32, ip, ip, dp]
     L.aq_batch_create.argtypes = [sz, i32, i64, i32, i32, vp, C.POINTER(vp)]
@@ -275,6 +279,11 @@ class Solver:
     def set_tile(self, tx: int, ty: int):
         _check(_lib.aq_set_tile(self._h, int(tx), int(ty)))
 
+    def set_outlet(self, K_tm: float, h_tm: float, p_sc: float):
+        """Lumped meshwork: new permeability, thickness and canal pressure; the seepage
+        speed in effect is re-evaluated at once from the last check step's IOP."""
+        _check(_lib.aq_set_outlet(self._h, float(K_tm), float(h_tm), float(p_sc)))
+
     def set_fusion(self, enable: bool):
         _check(_lib.aq_set_fusion(self._h, int(bool(enable))))
 
@@ -368,6 +377,17 @@ class Batch:
         o = AqObservables()
         _check(_lib.aq_batch_observe(self._h, int(slot), C.byref(o)))
         return o.asdict()
+
+    def set_outlet(self, slot: int, K_tm: float, h_tm: float, p_sc: float):
+        _check(_lib.aq_batch_set_outlet(self._h, int(slot), float(K_tm), float(h_tm), float(p_sc)))
+
+    def resume(self, slot: int, tol: float, max_steps: int) -> bool:
+        """Warm-start a finished kept instance; False when the batch has no room now."""
+        rc = _lib.aq_batch_resume(self._h, int(slot), float(tol), int(max_steps))
+        if rc == AQ_EBUSY:
+            return False
+        _check(rc)
+        return True
 
     def release(self, slot: int):
         _check(_lib.aq_batch_release(self._h, int(slot)))

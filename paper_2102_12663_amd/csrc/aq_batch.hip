@@ -571,6 +571,34 @@ int aq_batch_observe(aq_batch* b, int32_t slot, aq_observables* out)
     return aq_observe(b->slots[slot].s, out);
 }
 
+int aq_batch_set_outlet(aq_batch* b, int32_t slot, double K_tm, double h_tm, double p_sc)
+{
+    if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(AQ_EINVAL, "no such slot");
+    HIPCHK(hipStreamSynchronize(b->stream));
+    int rc = aq_set_outlet(b->slots[slot].s, K_tm, h_tm, p_sc);
+    if (rc) return rc;
+    return upload_tables(b);    // the instance table carries the constants
+}
+
+int aq_batch_resume(aq_batch* b, int32_t slot, double tol, int64_t max_steps)
+{
+    if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(AQ_EINVAL, "no such slot");
+    Slot& sl = b->slots[slot];
+    if (!sl.keep || !sl.done || sl.running) return fail(AQ_ESTATE, "only a finished instance admitted with keep can resume");
+    if (!(tol > 0) || max_steps < 1) return fail(AQ_EINVAL, "tol and max_steps must be positive");
+    if (sl.status != AQ_OK && sl.status != AQ_ENOTCONVERGED) return fail(AQ_ESTATE, "the instance failed");
+    if (b->max_active && running_active(b) + sl.s->n_active > b->max_active) return fail(AQ_EBUSY, "active-node cap reached");
+    if (b->n_work[sl.s->mode] + sl.s->n_tiles > b->max_tiles) return fail(AQ_EBUSY, "work list capacity reached");
+    sl.running = true;
+    sl.done = sl.reported = false;
+    sl.tol = tol;
+    sl.max_steps = sl.steps + max_steps;
+    sl.best_resid = 1e300;
+    sl.since_best = 0;
+    sl.status = AQ_OK;
+    return upload_tables(b);
+}
+
 int aq_batch_release(aq_batch* b, int32_t slot)
 {
     if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(AQ_EINVAL, "no such slot");

@@ -125,6 +125,7 @@ int set_state(aq_solver* s, const double* pops);
 int set_useep(aq_solver* s, double now, double before);
 StepArgs make_readout_args(const aq_solver* s);
 double seepage_speed(const aq_params& P, double p_iop);
+int lumped_guard(const aq_params& P, const uint8_t* mask, int stride);
 void raw_to_obs(const aq_solver* s, const double* raw, int64_t step, aq_observables* o);
 int create_common(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls,
                   void* arena, size_t arena_bytes, void* stream, bool own, aq_solver** out);

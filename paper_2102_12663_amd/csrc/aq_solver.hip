@@ -110,6 +110,39 @@ StepArgs make_args2(const aq_solver* s, bool a_is_src)
     return a;
 }
 
+// The seepage speed of the lumped outlet is explicit over a check interval.  The flow mass
+// of the chamber, (5/3) N dp, then relaxes toward its steady level by the factor 1 - D r per
+// interval, r = 3 A K_tm / (5 N nu h_tm), where A = sum over links into OUTLET nodes of
+// 6 w_i e_i.n is the outflow area.  Accept D r <= 1 (monotone approach; the coupling
+// oscillates beyond and diverges past 2).  `mask` holds the mask bytes with row stride
+// `stride` (bits above 4 ignored).
+int lumped_guard(const aq_params& P, const uint8_t* mask, int stride)
+{
+    static const int lx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, ly[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    if (!(P.K_tm > 0.0 && P.h_tm > 0.0 && std::isfinite(P.K_tm) && std::isfinite(P.h_tm) && std::isfinite(P.p_sc)))
+        return fail(AQ_EINVAL, "lumped outlet needs finite K_tm > 0, h_tm > 0 and p_sc");
+    double area = 0.0, n_act = 0.0;
+    for (int y = 1; y < P.ny - 1; y++)
+        for (int x = 1; x < P.nx - 1; x++) {
+            const int c = mask[(size_t)y * stride + x] & 7;
+            if (c != AQ_FLUID && c != AQ_POROUS) continue;
+            n_act += 1.0;
+            for (int i = 1; i <= 8; i++) {
+                const uint8_t m = mask[(size_t)(y + ly[i]) * stride + x + lx[i]];
+                if ((m & 7) != AQ_OUTLET) continue;
+                const int d = ((m >> 3) & 3) + 1;
+                area += 6.0 * (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0) * (lx[i] * lx[d] + ly[i] * ly[d]);
+            }
+        }
+    if (!(area > 0.0)) return fail(AQ_EINVAL, "lumped outlet: no outflow area (no link into an OUTLET node along its direction)");
+    const double nu = (2.0 * P.tau_f - 1.0) / 6.0;
+    const double dr = P.check_interval * 3.0 * area * P.K_tm / (5.0 * n_act * nu * P.h_tm);
+    if (dr > 1.0)
+        return fail(AQ_EINVAL, "lumped outlet: check_interval * 3 A K_tm / (5 N nu h_tm) = " + std::to_string(dr) +
+                                   " > 1 (the explicit coupling would overshoot); lower check_interval or K_tm");
+    return AQ_OK;
+}
+
 int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls)
 {
     if (!P || !mask) return fail(AQ_EINVAL, "null params or mask");
@@ -125,9 +158,6 @@ int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls,
         return fail(AQ_EINVAL, "fp16 exponents must be in [-1, 40]");
     if (P->outlet_mode != AQ_OUTLET_PRESSURE && P->outlet_mode != AQ_OUTLET_LUMPED)
         return fail(AQ_EINVAL, "unknown outlet_mode");
-    if (P->outlet_mode == AQ_OUTLET_LUMPED &&
-        !(P->K_tm > 0.0 && P->h_tm > 0.0 && std::isfinite(P->K_tm) && std::isfinite(P->h_tm) && std::isfinite(P->p_sc)))
-        return fail(AQ_EINVAL, "lumped outlet needs finite K_tm > 0, h_tm > 0 and p_sc");
     const int nx = P->nx, ny = P->ny;
     for (int y = 0; y < ny; y++)
         for (int x = 0; x < nx; x++) {
@@ -139,31 +169,8 @@ int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls,
                 return fail(AQ_EINVAL, "active node on the outer frame");
         }
     if (P->outlet_mode == AQ_OUTLET_LUMPED) {
-        // The seepage speed is explicit over a check interval.  The flow mass of the
-        // chamber, (5/3) N dp, then relaxes toward its steady level by the factor
-        // 1 - D r per interval, r = 3 A K_tm / (5 N nu h_tm), where A = sum over links
-        // into OUTLET nodes of 6 w_i e_i.n is the outflow area.  Accept D r <= 1
-        // (monotone approach; the coupling oscillates beyond and diverges past 2).
-        static const int lx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, ly[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-        double area = 0.0, n_act = 0.0;
-        for (int y = 1; y < ny - 1; y++)
-            for (int x = 1; x < nx - 1; x++) {
-                const int c = mask[(size_t)y * nx + x] & 7;
-                if (c != AQ_FLUID && c != AQ_POROUS) continue;
-                n_act += 1.0;
-                for (int i = 1; i <= 8; i++) {
-                    const uint8_t m = mask[(size_t)(y + ly[i]) * nx + x + lx[i]];
-                    if ((m & 7) != AQ_OUTLET) continue;
-                    const int d = ((m >> 3) & 3) + 1;
-                    area += 6.0 * (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0) * (lx[i] * lx[d] + ly[i] * ly[d]);
-                }
-            }
-        if (!(area > 0.0)) return fail(AQ_EINVAL, "lumped outlet: no outflow area (no link into an OUTLET node along its direction)");
-        const double nu = (2.0 * P->tau_f - 1.0) / 6.0;
-        const double dr = P->check_interval * 3.0 * area * P->K_tm / (5.0 * n_act * nu * P->h_tm);
-        if (dr > 1.0)
-            return fail(AQ_EINVAL, "lumped outlet: check_interval * 3 A K_tm / (5 N nu h_tm) = " + std::to_string(dr) +
-                                       " > 1 (the explicit coupling would overshoot); lower check_interval or K_tm");
+        int rc = lumped_guard(*P, mask, nx);
+        if (rc) return rc;
     }
     if (n_walls < 0 || (n_walls > 0 && !walls)) return fail(AQ_EINVAL, "invalid wall list");
     for (int w = 0; w < n_walls; w++) {
@@ -764,6 +771,41 @@ int aq_time_step_kernel(aq_solver* s, int32_t n_launch, double* ms)
     float t = 0;
     HIPCHK(hipEventElapsedTime(&t, s->ev[0], s->ev[1]));
     *ms = t / n_launch;
+    return AQ_OK;
+}
+
+int aq_set_outlet(aq_solver* s, double K_tm, double h_tm, double p_sc)
+{
+    if (!s) return fail(AQ_EINVAL, "null solver");
+    if (s->P.outlet_mode != AQ_OUTLET_LUMPED) return fail(AQ_EINVAL, "the solver's outlet is not the lumped meshwork");
+    aq_params P = s->P;
+    P.K_tm = K_tm;
+    P.h_tm = h_tm;
+    P.p_sc = p_sc;
+    int rc = lumped_guard(P, s->htype.data(), s->L.pitch);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);          // the captured launches carry the old constants
+    // the speed in effect becomes that of the new constants at the last check step's IOP
+    // (p_init before the first check); the read-out keeps the speed the last pull used
+    double p_iop = P.p_init;
+    if (s->checks > 0) {
+        double raw[NRED];
+        rc = read_raw(s, s->checks - 1, raw);
+        if (rc) return rc;
+        aq_observables o;
+        raw_to_obs(s, raw, s->last_check_step, &o);
+        p_iop = o.p_mean_fluid;
+    }
+    double cur[2];
+    HIPCHK(hipMemcpyAsync(cur, s->base + s->L.off_counters + kUseepOffset, 16, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const double before = s->ro_slot == 0 ? cur[0] : cur[1];
+    s->ro_slot = 1;
+    s->P = P;
+    rc = set_useep(s, seepage_speed(P, p_iop), before);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(s->stream));
     return AQ_OK;
 }
 

@@ -5,6 +5,10 @@
   orientation), all submitted at time zero and admitted as memory, slots and the
   active-node cap allow (continuous batching: a finished solve frees its slot for the next).
 * `serve`: the same solves arriving as a Poisson stream; latency = finish - arrival.
+* `calibrate`: the healthy-eye procedure of section 3.1 as dependent requests: for each
+  eye (lumped meshwork outlet), adjust the meshwork thickness until the steady IOP is the
+  target one.  Each round runs the resident solve to its steady residual, reads the IOP,
+  sets the new thickness and resumes from the current state (warm start).
 
 Both only schedule: admission, stepping, convergence checks and retirement run in the
 library.  Tile shapes come from `autotune_shape`, which times the candidate 256-thread tiles
@@ -168,3 +172,71 @@ def serve(rate=50.0, duration=60.0, storage=F16S, tol=1e-6, budget_bytes=64 << 3
     arr = [t for t in poisson_arrivals(n, rate, seed0) if t <= duration]
     return run_requests(lambda i: sweep_request(seed0 + i, storage, large_every=large_every), arr,
                         budget_bytes=budget_bytes, tol=tol, max_steps=max_steps, **kw)
+
+
+def thickness_update(h, rise, target, history):
+    """Next meshwork thickness: a secant step on (h, rise) pairs; the first step is
+    proportional (the steady rise IOP - p_sc of the lumped meshwork scales with h)."""
+    history.append((h, rise))
+    if len(history) >= 2:
+        (h0, r0), (h1, r1) = history[-2], history[-1]
+        if r1 != r0:
+            return h1 + (target - r1) * (h1 - h0) / (r1 - r0)
+    return h * target / rise
+
+
+def calibrate(eyes, targets, *, tol=1e-9, iop_rtol=1e-6, max_rounds=8, max_steps=400000,
+              budget_bytes=8 << 30, max_slots=64, intervals_per_call=5, check_interval=100):
+    """Calibrate the meshwork thickness of every eye (params, mask, walls with the lumped
+    outlet) so that its steady IOP - p_sc is targets[i].  All eyes share one batch.
+    Returns per-eye records (thickness per round, steps, rounds) and throughput figures."""
+    b = Batch(budget_bytes=budget_bytes, max_slots=max_slots, max_tiles=1 << 21, check_interval=check_interval)
+    n = len(eyes)
+    pending = list(range(n))
+    slot_of, rec = {}, {}
+    t0 = time.perf_counter()
+    done = 0
+    while done < n:
+        while pending:
+            i = pending[0]
+            p, mask, walls = eyes[i]
+            sl = b.admit(p, mask, walls, tile=(64, 4), tol=tol, max_steps=max_steps, request_id=i, keep=True)
+            if sl is None:
+                break
+            pending.pop(0)
+            slot_of[i] = sl
+            rec[i] = {"h": [p.h_tm], "rise": [], "steps": 0, "rounds": 0, "status": AQ_OK,
+                      "t_admit": time.perf_counter() - t0, "history": []}
+        if b.info()["running"] == 0 and not pending:
+            break
+        b.run(intervals_per_call)
+        for r in b.poll():
+            i = r["request_id"]
+            p = eyes[i][0]
+            e = rec[i]
+            e["rounds"] += 1
+            e["steps"] = r["steps"]
+            rise = r["obs"]["p_mean_fluid"] - p.p_sc
+            e["rise"].append(rise)
+            ok = r["status"] == AQ_OK and abs(rise / targets[i] - 1.0) <= iop_rtol
+            if ok or r["status"] != AQ_OK or e["rounds"] >= max_rounds:
+                e["status"] = r["status"] if r["status"] != AQ_OK else (AQ_OK if ok else -5)
+                e["t_done"] = time.perf_counter() - t0
+                b.release(slot_of[i])
+                done += 1
+                continue
+            h_new = thickness_update(e["h"][-1], rise, targets[i], e["history"])
+            b.set_outlet(slot_of[i], p.K_tm, h_new, p.p_sc)
+            e["h"].append(h_new)
+            if not b.resume(slot_of[i], tol, max_steps):
+                raise RuntimeError("no room to resume a resident instance")
+    wall = time.perf_counter() - t0
+    b.close()
+    for e in rec.values():
+        e.pop("history")
+    lat = [e["t_done"] - e["t_admit"] for e in rec.values() if "t_done" in e]
+    return {"eyes": n, "calibrated": sum(e["status"] == AQ_OK for e in rec.values()),
+            "wall_s": wall, "calibrations_per_s": n / wall if wall > 0 else 0.0,
+            "rounds_mean": float(np.mean([e["rounds"] for e in rec.values()])),
+            "steps_mean": float(np.mean([e["steps"] for e in rec.values()])),
+            "latency_p50_s": _percentile(lat, 50), "latency_p99_s": _percentile(lat, 99), "records": rec}

@@ -185,3 +185,32 @@ def test_tables_4_5_6_scaling():
     assert mine == pytest.approx(mu_ratio, rel=1e-5)
     paper = (t6[-1, 1] - 1200.0) / (t6[0, 1] - 1200.0)
     assert mine == pytest.approx(paper, rel=2e-2)
+
+
+def test_calibration_loop_reaches_closed_form_thickness():
+    """The healthy-eye procedure of section 3.1: adjust the meshwork thickness until the
+    steady IOP is the target.  With warm restarts (new thickness, same state) and the
+    library's update rule, the loop lands on h* = target K A / (mu Q_in) in two or three
+    rounds."""
+    from paper_2102_12663_amd.serve import thickness_update
+    mask, walls, geo = _eye()
+    p = _params(geo)
+    area, q_in, n = _counts(mask, p)
+    target = 1.3 * _nu(p) * p.h_tm * q_in / (p.K_tm * area)
+    h_star = target * p.K_tm * area / (_nu(p) * q_in)
+    o = O.Oracle(p, mask, walls)
+    h, history, rounds = p.h_tm, [], 0
+    while True:
+        rounds += 1
+        for _ in range(3000):
+            o.step(p.check_interval)
+            ob = o.observables()
+            if ob["resid_u"] < 1e-11:
+                break
+        rise = ob["p_mean_fluid"] - p.p_sc
+        if abs(rise / target - 1) < 1e-8 or rounds >= 5:
+            break
+        h = thickness_update(h, rise, target, history)
+        o.set_outlet(p.K_tm, h, p.p_sc)
+    assert rounds <= 3
+    assert h == pytest.approx(h_star, rel=2e-8)
