@@ -70,7 +70,7 @@ def cpu_baseline(p, mask, walls, budget_s=12.0):
             "sample": f"{n} time steps of the same 2048x1024 lattice ({act} active nodes), {dt:.1f} s"}
 
 
-def batched_vs_one_at_a_time(n, cap=50000, tol=1e-6):
+def batched_vs_one_at_a_time(n, cap=200000, tol=1e-6):
     """Solves/s and latency (all requests submitted at t = 0) of n sweep requests
     (lattices 256x128 .. 1024x512, per-request tau, Da, inflow, angle, Ra, orientation):
     continuously batched in F32 storage, and the same requests one at a time through the
@@ -97,6 +97,58 @@ def batched_vs_one_at_a_time(n, cap=50000, tol=1e-6):
                             "aggregate_active_mlups": round(res["aggregate_active_mlups"], 1)},
             "one_at_a_time_f64": {"solves_per_s": round(n / wall, 3), "p50_s": round(float(np.percentile(lat, 50)), 3),
                                   "p99_s": round(float(np.percentile(lat, 99)), 3), "converged": int(conv)}}
+
+
+def outflow_area(mask):
+    """Outflow area of a lumped-meshwork mask: sum over links from active nodes into OUTLET
+    nodes of 6 w_i (e_i . n), n the node's outward direction (mask bits 3-4)."""
+    import numpy as np
+    import aqinputs as A
+    e = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+    w = [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4
+    act = A.active(mask)
+    cls, d = mask & 7, (mask >> 3) & 3
+    area = 0.0
+    for i in range(1, 9):
+        ex, ey = e[i]
+        nb_cls = np.roll(np.roll(cls, -ey, axis=0), -ex, axis=1)
+        nb_d = np.roll(np.roll(d, -ey, axis=0), -ex, axis=1)
+        hit = act & (nb_cls == A.OUTLET)
+        for k in range(4):
+            nx_, ny_ = e[k + 1]
+            area += 6 * w[i] * (ex * nx_ + ey * ny_) * np.count_nonzero(hit & (nb_d == k))
+    return area
+
+
+def calibration_workload(n=12, cap=400000):
+    """Section 3.1's thickness calibration for n lumped-outlet eyes (sweep draws 256x128 and
+    512x256, meshwork permeability set so the coupling contracts by 0.6 per interval):
+    target IOP rise 1.25x that of the initial thickness; warm restarts of the resident
+    solves against fresh restarts every round."""
+    import aqinputs as A
+    from paper_2102_12663_amd import serve as S
+    eyes, targets = [], []
+    for i in range(n):
+        nx, ny = ((256, 128), (512, 256))[i % 2]
+        p, mask, walls, geo = A.sweep_instance(100 + i, nx, ny, tm="lumped")
+        p.gbeta = 0.0                      # Ra = 0: the secretion-driven steady state
+        nu = (2 * p.tau_f - 1) / 6
+        area = outflow_area(mask)
+        # meshwork permeability for which the explicit coupling contracts the IOP error by
+        # 0.6 per check interval (D r = 0.4, r = 3 A K / (5 N nu h))
+        p.K_tm = 0.4 * 5 * int(A.active(mask).sum()) * nu * p.h_tm / (3 * area * p.check_interval)
+        q_in = p.u_in_y * (geo.inlet_cols[1] - geo.inlet_cols[0] + 1)
+        targets.append(1.25 * nu * p.h_tm * q_in / (p.K_tm * area))
+        eyes.append((p, mask, walls))
+    out = {"workload": f"{n} lumped-outlet eyes (sweep draws 100..{99 + n}, 256x128 and 512x256, Ra = 0), "
+                       f"target IOP rise 1.25x the initial thickness's, residual 1e-9, IOP to 1e-6"}
+    for warm in (True, False):
+        r = S.calibrate(eyes, targets, tol=1e-9, iop_rtol=1e-6, max_steps=cap, warm=warm)
+        out["warm" if warm else "cold"] = {
+            "calibrated": r["calibrated"], "calibrations_per_s": round(r["calibrations_per_s"], 3),
+            "rounds_mean": round(r["rounds_mean"], 2), "steps_mean": round(r["steps_mean"]),
+            "p50_s": round(r["latency_p50_s"], 3), "p99_s": round(r["latency_p99_s"], 3)}
+    return out
 
 
 def main():
@@ -235,6 +287,7 @@ def main():
         out["lumped_outlet"] = {**brief(e), "iop_gauge": e["obs"]["iop_gauge"], "u_seep": e["obs"]["u_seep"]}
     if not args.no_batched:
         out["batched"] = batched_vs_one_at_a_time(args.batched_requests)
+        out["calibration"] = calibration_workload()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(r["p"], r["mask"], r["walls"])
     print(json.dumps(out), flush=True)

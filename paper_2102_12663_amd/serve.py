@@ -186,10 +186,12 @@ def thickness_update(h, rise, target, history):
 
 
 def calibrate(eyes, targets, *, tol=1e-9, iop_rtol=1e-6, max_rounds=8, max_steps=400000,
-              budget_bytes=8 << 30, max_slots=64, intervals_per_call=5, check_interval=100):
+              budget_bytes=8 << 30, max_slots=64, intervals_per_call=5, check_interval=100, warm=True):
     """Calibrate the meshwork thickness of every eye (params, mask, walls with the lumped
-    outlet) so that its steady IOP - p_sc is targets[i].  All eyes share one batch.
-    Returns per-eye records (thickness per round, steps, rounds) and throughput figures."""
+    outlet) so that its steady IOP - p_sc is targets[i].  All eyes share one batch.  With
+    warm=False every round starts a fresh solve from the initial state instead (the cold
+    baseline).  Returns per-eye records (thickness per round, steps, rounds) and
+    throughput figures."""
     b = Batch(budget_bytes=budget_bytes, max_slots=max_slots, max_tiles=1 << 21, check_interval=check_interval)
     n = len(eyes)
     pending = list(range(n))
@@ -215,7 +217,7 @@ def calibrate(eyes, targets, *, tol=1e-9, iop_rtol=1e-6, max_rounds=8, max_steps
             p = eyes[i][0]
             e = rec[i]
             e["rounds"] += 1
-            e["steps"] = r["steps"]
+            e["steps"] = r["steps"] + e.get("steps_before", 0)
             rise = r["obs"]["p_mean_fluid"] - p.p_sc
             e["rise"].append(rise)
             ok = r["status"] == AQ_OK and abs(rise / targets[i] - 1.0) <= iop_rtol
@@ -226,14 +228,25 @@ def calibrate(eyes, targets, *, tol=1e-9, iop_rtol=1e-6, max_rounds=8, max_steps
                 done += 1
                 continue
             h_new = thickness_update(e["h"][-1], rise, targets[i], e["history"])
-            b.set_outlet(slot_of[i], p.K_tm, h_new, p.p_sc)
             e["h"].append(h_new)
-            if not b.resume(slot_of[i], tol, max_steps):
-                raise RuntimeError("no room to resume a resident instance")
+            if warm:
+                b.set_outlet(slot_of[i], p.K_tm, h_new, p.p_sc)
+                if not b.resume(slot_of[i], tol, max_steps):
+                    raise RuntimeError("no room to resume a resident instance")
+            else:
+                b.release(slot_of[i])
+                e["steps_before"] = e.get("steps_before", 0) + r["steps"]
+                p2 = A.Params(**{**p.asdict(), "h_tm": h_new})
+                sl = b.admit(p2, eyes[i][1], eyes[i][2], tile=(64, 4), tol=tol, max_steps=max_steps,
+                             request_id=i, keep=True)
+                if sl is None:
+                    raise RuntimeError("no room to restart the instance")
+                slot_of[i] = sl
     wall = time.perf_counter() - t0
     b.close()
     for e in rec.values():
         e.pop("history")
+        e.pop("steps_before", None)
     lat = [e["t_done"] - e["t_admit"] for e in rec.values() if "t_done" in e]
     return {"eyes": n, "calibrated": sum(e["status"] == AQ_OK for e in rec.values()),
             "wall_s": wall, "calibrations_per_s": n / wall if wall > 0 else 0.0,
