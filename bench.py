@@ -219,6 +219,12 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ob = s.observe()
+        # vortex diagnostics (eq. 18) of the final state, on demand, outside the timed region
+        dg = s.diagnose()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            dg = s.diagnose()
+        dg["ms_per_call"] = (time.perf_counter() - t1) * 1e3 / 5
         s.close()
         act = info["active_nodes"]
         mlups = act * steps * D / wall / 1e6
@@ -232,7 +238,7 @@ def main():
         achieved = info["bytes_per_node_update"] * act * steps_per_launch / (launch_ms * 1e-3) / 1e9
         return dict(p=p, mask=mask, walls=walls, geo=geo, info=info, wall=wall, total_ms=total_ms,
                     launch_ms=launch_ms, steps_per_launch=steps_per_launch, kernel=kernel,
-                    achieved=achieved, mlups=mlups, obs=ob, D=D)
+                    achieved=achieved, mlups=mlups, obs=ob, D=D, diag=dg)
 
     r = run(args.storage, args.steps, args.warmup)
     info, D = r["info"], r["D"]
@@ -271,6 +277,7 @@ def main():
                      "measured_hbm_GBs": (round(traffic / (r["launch_ms"] * 1e-3) / 1e9, 1)
                                           if traffic else None)},
         "observables": {k: r["obs"][k] for k in ("step", "iop_gauge", "q_in", "q_out", "resid_u", "u_max")},
+        "diagnostics": {k: (round(v, 4) if k == "ms_per_call" else v) for k, v in r["diag"].items()},
     }
     if not args.no_extra:
         def brief(e):

@@ -246,6 +246,36 @@ int aq_time_step_kernel(aq_solver* s, int32_t n_launch, double* ms_per_launch);
  * exceeds the last-level cache.  Results are bitwise the same either way. */
 int aq_set_fusion(aq_solver* s, int32_t enable);
 
+/*
+ * Vortex diagnostics of the current state (section 3.5, Table 3, Figs. 6-7), computed on
+ * the device from the velocity (eq. 9):
+ *   vortex_intensity  I = 2 sum over FLUID nodes of |omega_z| (unit cell area), with
+ *                     omega_z = (d u_y/dx - d u_x/dy)/2 (eq. 18); a derivative is the central
+ *                     difference where both neighbours along the axis are active, the
+ *                     one-sided difference toward the active one where only one is, else 0.
+ *                     The magnitude is summed: the signed integral of eq. 18 is the
+ *                     circulation around the no-slip boundary, which vanishes.
+ *   u_max_fluid       max |u| over FLUID nodes
+ *   psi_max, psi_min  extrema over FLUID nodes of the stream function
+ *                     psi(x, y) = sum over y' <= y of u_x(x, y') (active nodes of column x),
+ *                     i.e. u_x = d psi/dy; their nodes (x, y) are the centres of the
+ *                     counter-rotating and co-rotating vortices (smallest y*nx + x on ties;
+ *                     -1 when the lattice has no FLUID node)
+ */
+typedef struct aq_diagnostics {
+    int64_t step;
+    double vortex_intensity, u_max_fluid, psi_max, psi_min;
+    int32_t psi_max_x, psi_max_y, psi_min_x, psi_min_y;
+} aq_diagnostics;
+
+/* Device workspace aq_diagnose needs for these parameters (about 16 bytes per node). */
+int aq_diagnostics_bytes(const aq_params* params, size_t* bytes);
+
+/* Compute the diagnostics above.  workspace: device memory of at least
+ * aq_diagnostics_bytes (caller-owned, 8-byte aligned, contents overwritten).  Synchronises
+ * the solver's stream.  AQ_EINVAL for a null or too small workspace. */
+int aq_diagnose(aq_solver* s, void* workspace, size_t workspace_bytes, aq_diagnostics* out);
+
 /* Lumped meshwork outlet (AQ_OUTLET_LUMPED only): replace K_tm, h_tm and p_sc of a live
  * solve (the calibration loop of section 3.1 adjusts the meshwork thickness until the
  * steady IOP is the healthy one).  The seepage speed in effect becomes that of the new
@@ -343,6 +373,9 @@ int aq_batch_set_outlet(aq_batch* b, int32_t slot, double K_tm, double h_tm, dou
  * AQ_ESTATE if the slot is running, was not kept, or failed (diverged); AQ_EBUSY if the
  * active-node cap or the work list has no room. */
 int aq_batch_resume(aq_batch* b, int32_t slot, double tol, int64_t max_steps);
+
+/* aq_diagnose on the instance in a slot (running, or finished and kept). */
+int aq_batch_diagnose(aq_batch* b, int32_t slot, void* workspace, size_t workspace_bytes, aq_diagnostics* out);
 
 int aq_batch_get_info(aq_batch* b, aq_batch_info* out);
 

@@ -29,7 +29,8 @@ EXPORTS = ("aq_version", "aq_last_error", "aq_required_bytes", "aq_create", "aq_
            "aq_time_fused_kernel", "aq_set_outlet",
            "aq_batch_create", "aq_batch_admit", "aq_batch_run", "aq_batch_poll", "aq_batch_read_field",
            "aq_batch_observe", "aq_batch_release", "aq_batch_get_info", "aq_batch_destroy",
-           "aq_batch_set_outlet", "aq_batch_resume")
+           "aq_batch_set_outlet", "aq_batch_resume", "aq_diagnostics_bytes", "aq_diagnose",
+           "aq_batch_diagnose")
 
 
 class AqParams(C.Structure):
@@ -51,6 +52,15 @@ class AqObservables(C.Structure):
         "iop_gauge", "p_mean_fluid", "q_in", "q_out", "wss_cornea_mean", "wss_cornea_max",
         "wss_iris_mean", "wss_iris_max", "resid_u", "resid_T", "u_max", "mass_flow",
         "mass_thermal")] + [("n_nonfinite", C.c_int64), ("u_seep", C.c_double)]
+
+    def asdict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class AqDiagnostics(C.Structure):
+    _fields_ = [("step", C.c_int64), ("vortex_intensity", C.c_double), ("u_max_fluid", C.c_double),
+                ("psi_max", C.c_double), ("psi_min", C.c_double), ("psi_max_x", C.c_int32),
+                ("psi_max_y", C.c_int32), ("psi_min_x", C.c_int32), ("psi_min_y", C.c_int32)]
 
     def asdict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -130,6 +140,9 @@ def load_library(path: str = LIB_PATH):
     ip = C.POINTER(i32)
     L.aq_set_fusion.argtypes = [vp, i32]
     L.aq_set_outlet.argtypes = [vp, C.c_double, C.c_double, C.c_double]
+    L.aq_diagnostics_bytes.argtypes = [C.POINTER(AqParams), C.POINTER(sz)]
+    L.aq_diagnose.argtypes = [vp, vp, sz, C.POINTER(AqDiagnostics)]
+    L.aq_batch_diagnose.argtypes = [vp, i32, vp, sz, C.POINTER(AqDiagnostics)]
     L.aq_batch_set_outlet.argtypes = [vp, i32, C.c_double, C.c_double, C.c_double]
     L.aq_batch_resume.argtypes = [vp, i32, C.c_double, i64]
     L.aq_time_fused_kernel.argtypes = [vp, i32, dp]
@@ -279,6 +292,20 @@ class Solver:
     def set_tile(self, tx: int, ty: int):
         _check(_lib.aq_set_tile(self._h, int(tx), int(ty)))
 
+    def diagnose(self) -> dict:
+        """Vortex intensity, max |u| over FLUID nodes and the stream-function extrema with
+        their nodes (aq_diagnose); the device workspace is allocated once and kept."""
+        import torch
+        nb = C.c_size_t()
+        _check(_lib.aq_diagnostics_bytes(C.byref(self._p), C.byref(nb)))
+        if getattr(self, "_diag_ws", None) is None or self._diag_ws.numel() < nb.value:
+            torch.cuda.synchronize(self.device)
+            self._diag_ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+            torch.cuda.synchronize(self.device)
+        d = AqDiagnostics()
+        _check(_lib.aq_diagnose(self._h, C.c_void_p(self._diag_ws.data_ptr()), nb.value, C.byref(d)))
+        return d.asdict()
+
     def set_outlet(self, K_tm: float, h_tm: float, p_sc: float):
         """Lumped meshwork: new permeability, thickness and canal pressure; the seepage
         speed in effect is re-evaluated at once from the last check step's IOP."""
@@ -377,6 +404,21 @@ class Batch:
         o = AqObservables()
         _check(_lib.aq_batch_observe(self._h, int(slot), C.byref(o)))
         return o.asdict()
+
+    def diagnose(self, slot: int, params) -> dict:
+        """aq_batch_diagnose; `params` are the instance's (for the workspace size)."""
+        import torch
+        nb = C.c_size_t()
+        ap = make_params(params)
+        _check(_lib.aq_diagnostics_bytes(C.byref(ap), C.byref(nb)))
+        if getattr(self, "_diag_ws", None) is None or self._diag_ws.numel() < nb.value:
+            torch.cuda.synchronize()
+            self._diag_ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+            torch.cuda.synchronize()
+        d = AqDiagnostics()
+        _check(_lib.aq_batch_diagnose(self._h, int(slot), C.c_void_p(self._diag_ws.data_ptr()), nb.value,
+                                      C.byref(d)))
+        return d.asdict()
 
     def set_outlet(self, slot: int, K_tm: float, h_tm: float, p_sc: float):
         _check(_lib.aq_batch_set_outlet(self._h, int(slot), float(K_tm), float(h_tm), float(p_sc)))

@@ -599,6 +599,12 @@ int aq_batch_resume(aq_batch* b, int32_t slot, double tol, int64_t max_steps)
     return upload_tables(b);
 }
 
+int aq_batch_diagnose(aq_batch* b, int32_t slot, void* ws, size_t ws_bytes, aq_diagnostics* out)
+{
+    if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(AQ_EINVAL, "no such slot");
+    return aq_diagnose(b->slots[slot].s, ws, ws_bytes, out);
+}
+
 int aq_batch_release(aq_batch* b, int32_t slot)
 {
     if (!b || slot < 0 || slot >= b->max_slots || !b->slots[slot].used) return fail(AQ_EINVAL, "no such slot");

@@ -106,8 +106,13 @@ hipError_t launch_scatter(int mode, const StepArgs& a, const double* pops, doubl
                           hipStream_t s);
 // Pull a.src and write one field (0 p, 1 u_x, 2 u_y, 3 T, 4 flow population q, 5 thermal
 // population q) to out[ny][nx]; field 6 stores the moments as the residual reference;
-// field 7 writes all 13 populations to out[13][ny][nx].
+// field 7 writes all 13 populations to out[13][ny][nx]; field 8 writes u_x and u_y to
+// out[2][ny][nx].
 hipError_t launch_unpack(int mode, const StepArgs& a, int field, int q, double p_ref, double* out,
                          hipStream_t s);
+// Vortex diagnostics of the state `a` pulls to (field 8 read-out, vorticity, stream
+// function); ws holds diagnostics_words(nx, ny) doubles, results in its last 8.
+size_t diagnostics_words(int nx, int ny);
+hipError_t launch_diagnostics(int mode, const StepArgs& a, double* ws, hipStream_t s);
 
 }  // namespace aq

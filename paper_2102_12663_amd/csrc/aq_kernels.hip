@@ -1021,9 +1021,9 @@ __global__ __launch_bounds__(256) void unpack_kernel(StepArgs a, int field, int 
     const long long d = (long long)y * a.nx + x;
     const uint8_t t = a.type[k];
     if (!is_active(t)) {
-        if (field == 7) {
+        if (field == 7 || field == 8) {
             const long long n2 = (long long)a.nx * a.ny;
-            for (int i = 0; i < NPOP; i++) out[i * n2 + d] = __builtin_nan("");
+            for (int i = 0; i < (field == 7 ? NPOP : 2); i++) out[i * n2 + d] = __builtin_nan("");
         } else if (field != 6) {
             out[d] = __builtin_nan("");
         }
@@ -1036,6 +1036,12 @@ __global__ __launch_bounds__(256) void unpack_kernel(StepArgs a, int field, int 
         const long long n2 = (long long)a.nx * a.ny;
         for (int i = 1; i <= 8; i++) out[(i - 1) * n2 + d] = n.h[i];
         for (int i = 0; i <= 4; i++) out[(8 + i) * n2 + d] = n.g[i];
+        return;
+    }
+    if (field == 8) {                        // u_x then u_y, dense [2][ny][nx]
+        const long long n2 = (long long)a.nx * a.ny;
+        out[d] = m.ux;
+        out[n2 + d] = m.uy;
         return;
     }
     if (field == 6) {
@@ -1136,6 +1142,160 @@ hipError_t launch_unpack(int mode, const StepArgs& a, int field, int q, double p
     case 2: hipLaunchKernelGGL(unpack_kernel<2>, lattice_grid(a), dim3(256), 0, s, a, field, q, p_ref, out); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------ diagnostics
+// Vortex diagnostics of section 3.5 (Table 3, Figs. 6-7) on the dense velocity planes
+// u[0] = u_x, u[1] = u_y ([ny][nx], written by unpack field 8).
+//
+// omega_z = (d u_y/dx - d u_x/dy) / 2 (eq. 18); a derivative is the central difference
+// when both neighbours along the axis are active, the one-sided difference toward the
+// active one when only one is, and 0 otherwise.  Vortex intensity I = 2 sum |omega_z| over
+// FLUID nodes (unit cell area; the magnitude, since the signed integral of eq. 18 is the
+// circulation around the no-slip boundary, i.e. zero).  Also max |u| over FLUID nodes.
+__device__ __forceinline__ bool act_at(const StepArgs& a, int x, int y)
+{
+    return x >= 0 && y >= 0 && x < a.nx && y < a.ny && is_active(a.type[y * a.pitch + x]);
+}
+
+__device__ __forceinline__ double axis_derivative(const StepArgs& a, const double* f, int x, int y, int dx, int dy)
+{
+    const bool up = act_at(a, x + dx, y + dy), dn = act_at(a, x - dx, y - dy);
+    const long long c = (long long)y * a.nx + x, o = (long long)dy * a.nx + dx;
+    if (up && dn) return (f[c + o] - f[c - o]) / 2.0;
+    if (up) return f[c + o] - f[c];
+    if (dn) return f[c] - f[c - o];
+    return 0.0;
+}
+
+__global__ __launch_bounds__(256) void diag_vorticity_kernel(StepArgs a, const double* u, double* partial)
+{
+    __shared__ double sm[2][4];
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    double w = 0.0, um = 0.0;
+    if (x < a.nx && y < a.ny && (a.type[y * a.pitch + x] & CLS_MASK) == FLUID) {
+        const long long n2 = (long long)a.nx * a.ny;
+        const double dvdx = axis_derivative(a, u + n2, x, y, 1, 0);
+        const double dudy = axis_derivative(a, u, x, y, 0, 1);
+        w = 2.0 * fabs(0.5 * (dvdx - dudy));
+        const long long c = (long long)y * a.nx + x;
+        um = sqrt(u[c] * u[c] + u[n2 + c] * u[n2 + c]);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        w += __shfl_xor(w, off, 64);
+        um = fmax(um, __shfl_xor(um, off, 64));
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sm[0][wv] = w;
+        sm[1][wv] = um;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const long long b = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+        partial[2 * b] = ((sm[0][0] + sm[0][1]) + sm[0][2]) + sm[0][3];
+        partial[2 * b + 1] = fmax(fmax(sm[1][0], sm[1][1]), fmax(sm[1][2], sm[1][3]));
+    }
+}
+
+// Stream function psi(x, y) = sum over y' <= y of u_x(x, y') along each column (non-active
+// nodes carry no flux), so u_x = d psi/dy; one thread per column keeps the column's largest
+// and smallest psi over FLUID nodes (first occurrence from the bottom on ties).
+__global__ __launch_bounds__(256) void diag_psi_kernel(StepArgs a, const double* u, double* col)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= a.nx) return;
+    double psi = 0.0, vmax = -__builtin_huge_val(), vmin = __builtin_huge_val();
+    int ymax = -1, ymin = -1;
+    for (int y = 0; y < a.ny; y++) {
+        const uint8_t t = a.type[y * a.pitch + x];
+        if (!is_active(t)) continue;
+        psi += u[(long long)y * a.nx + x];
+        if ((t & CLS_MASK) != FLUID) continue;
+        if (psi > vmax) { vmax = psi; ymax = y; }
+        if (psi < vmin) { vmin = psi; ymin = y; }
+    }
+    col[4LL * x] = vmax;
+    col[4LL * x + 1] = ymax;
+    col[4LL * x + 2] = vmin;
+    col[4LL * x + 3] = ymin;
+}
+
+// One block: fixed-order sum of the vorticity partials, max of the speed partials, and the
+// extrema of psi over columns (smallest node index y * nx + x on ties).  out[0] = I,
+// out[1] = max |u|, out[2..4] = psi_max, x, y, out[5..7] = psi_min, x, y.
+__global__ __launch_bounds__(256) void diag_finish_kernel(const double* partial, int n_part, const double* col, int nx,
+                                                          double* out)
+{
+    __shared__ double s_w[256], s_u[256], s_mx[256], s_mxi[256], s_mn[256], s_mni[256];
+    const int t = threadIdx.x;
+    double w = 0.0, um = 0.0;
+    for (int b = t; b < n_part; b += 256) {
+        w += partial[2 * b];
+        um = fmax(um, partial[2 * b + 1]);
+    }
+    double mx = -__builtin_huge_val(), mn = __builtin_huge_val(), mxi = -1.0, mni = -1.0;   // index y * nx + x
+    for (int x = t; x < nx; x += 256) {
+        const double* c = col + 4LL * x;
+        if (c[1] >= 0) {
+            const double i = c[1] * nx + x;
+            if (c[0] > mx || (c[0] == mx && i < mxi)) { mx = c[0]; mxi = i; }
+        }
+        if (c[3] >= 0) {
+            const double i = c[3] * nx + x;
+            if (c[2] < mn || (c[2] == mn && i < mni)) { mn = c[2]; mni = i; }
+        }
+    }
+    s_w[t] = w; s_u[t] = um; s_mx[t] = mx; s_mxi[t] = mxi; s_mn[t] = mn; s_mni[t] = mni;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (t < h) {
+            s_w[t] += s_w[t + h];
+            s_u[t] = fmax(s_u[t], s_u[t + h]);
+            const double v = s_mx[t + h], vi = s_mxi[t + h];
+            if (vi >= 0 && (s_mxi[t] < 0 || v > s_mx[t] || (v == s_mx[t] && vi < s_mxi[t]))) { s_mx[t] = v; s_mxi[t] = vi; }
+            const double m2 = s_mn[t + h], mi = s_mni[t + h];
+            if (mi >= 0 && (s_mni[t] < 0 || m2 < s_mn[t] || (m2 == s_mn[t] && mi < s_mni[t]))) { s_mn[t] = m2; s_mni[t] = mi; }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = s_w[0];
+        out[1] = s_u[0];
+        const long long im = (long long)s_mxi[0], in = (long long)s_mni[0];
+        out[2] = s_mx[0];
+        out[3] = im >= 0 ? (double)(im % nx) : -1.0;
+        out[4] = im >= 0 ? (double)(im / nx) : -1.0;
+        out[5] = s_mn[0];
+        out[6] = in >= 0 ? (double)(in % nx) : -1.0;
+        out[7] = in >= 0 ? (double)(in / nx) : -1.0;
+    }
+}
+
+size_t diagnostics_words(int nx, int ny)
+{
+    const size_t n2 = (size_t)nx * ny;
+    const size_t nb = (size_t)((nx + 63) / 64) * ((ny + 3) / 4);
+    return 2 * n2 + 2 * nb + 4 * (size_t)nx + 8;
+}
+
+// ws: diagnostics_words(nx, ny) doubles.  Reads the state through `a` (a read-out pull)
+// and leaves the 8 results in ws[2 n2 + 2 nb + 4 nx ...].
+hipError_t launch_diagnostics(int mode, const StepArgs& a, double* ws, hipStream_t s)
+{
+    const long long n2 = (long long)a.nx * a.ny;
+    const dim3 g = lattice_grid(a);
+    const int nb = (int)(g.x * g.y);
+    double* part = ws + 2 * n2;
+    double* col = part + 2LL * nb;
+    double* out = col + 4LL * a.nx;
+    hipError_t e = launch_unpack(mode, a, 8, 0, 0.0, ws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(diag_vorticity_kernel, g, dim3(256), 0, s, a, (const double*)ws, part);
+    hipLaunchKernelGGL(diag_psi_kernel, dim3((a.nx + 255) / 256), dim3(256), 0, s, a, (const double*)ws, col);
+    hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(256), 0, s, (const double*)part, nb, (const double*)col, a.nx, out);
     return hipGetLastError();
 }
 

@@ -809,6 +809,35 @@ int aq_set_outlet(aq_solver* s, double K_tm, double h_tm, double p_sc)
     return AQ_OK;
 }
 
+int aq_diagnostics_bytes(const aq_params* P, size_t* bytes)
+{
+    if (!P || !bytes || P->nx < 1 || P->ny < 1) return fail(AQ_EINVAL, "invalid arguments");
+    *bytes = diagnostics_words(P->nx, P->ny) * sizeof(double);
+    return AQ_OK;
+}
+
+int aq_diagnose(aq_solver* s, void* ws, size_t ws_bytes, aq_diagnostics* out)
+{
+    if (!s || !ws || !out) return fail(AQ_EINVAL, "null argument");
+    const size_t words = diagnostics_words(s->P.nx, s->P.ny);
+    if (ws_bytes < words * sizeof(double) || ((uintptr_t)ws & 7)) return fail(AQ_EINVAL, "workspace too small or misaligned");
+    double* w = (double*)ws;
+    HIPCHK(launch_diagnostics(s->mode, make_readout_args(s), w, s->stream));
+    HIPCHK(hipMemcpyAsync(s->obs_pinned, w + words - 8, 8 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const double* r = s->obs_pinned;
+    out->step = s->step;
+    out->vortex_intensity = r[0];
+    out->u_max_fluid = r[1];
+    out->psi_max = r[2];
+    out->psi_max_x = (int32_t)r[3];
+    out->psi_max_y = (int32_t)r[4];
+    out->psi_min = r[5];
+    out->psi_min_x = (int32_t)r[6];
+    out->psi_min_y = (int32_t)r[7];
+    return AQ_OK;
+}
+
 int aq_set_fusion(aq_solver* s, int32_t enable)
 {
     if (!s) return fail(AQ_EINVAL, "null solver");

@@ -41,7 +41,8 @@ def test_struct_layouts_match_header(aq, tmp_path):
     """Every ctypes structure of the binding has the size and field offsets that a C
     compiler gives the header's structure (compiled and run here with gcc)."""
     structs = {"aq_params": aq.AqParams, "aq_wall_node": aq.AqWallNode, "aq_observables": aq.AqObservables,
-               "aq_info": aq.AqInfo, "aq_result": aq.AqResult, "aq_batch_info": aq.AqBatchInfo}
+               "aq_info": aq.AqInfo, "aq_result": aq.AqResult, "aq_batch_info": aq.AqBatchInfo,
+               "aq_diagnostics": aq.AqDiagnostics}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "aqlbm.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
