@@ -41,7 +41,11 @@ WALL_BOX, WALL_CORNEA, WALL_IRIS = 0, 1, 2
 DIR_PX, DIR_PY, DIR_MX, DIR_MY = 0, 1, 2, 3
 OUTLET_PRESSURE, OUTLET_LUMPED = 0, 1
 
-WALL_DTYPE = np.dtype([("node", "<i4"), ("wall", "<i4"), ("nx", "<f8"), ("ny", "<f8")])
+# Wall-node list entry: node index, wall id, analytic unit normal into the fluid, and for
+# each link i = 1..8 (q[i-1]) the fraction of the link from the node to the wall surface
+# when the neighbour along e_i is a CORNEA or IRIS solid (in (0, 1]), else -1.
+WALL_DTYPE = np.dtype([("node", "<i4"), ("wall", "<i4"), ("nx", "<f8"), ("ny", "<f8"), ("q", "<f8", (8,))])
+BC_LINKWISE, BC_PAPER = 0, 1
 
 # D2Q9 link directions, used here only to find which active nodes touch a wall.
 _LINKS = [(1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
@@ -180,8 +184,23 @@ def eye_mask(nx: int, ny: int, alpha_deg: float = 45.0, R: float | None = None,
         geo.outlet_cols.append(oc)
 
     _frame(mask)
-    walls = wall_list(mask, normal_fn=lambda x, y, wall: _eye_normal(geo, x, y, wall))
+    walls = wall_list(mask, normal_fn=lambda x, y, wall: _eye_normal(geo, x, y, wall),
+                      q_fn=lambda x, y, ex, ey, wall: _eye_fraction(geo, x, y, ex, ey, wall))
     return mask, walls, geo
+
+
+def _eye_fraction(geo: EyeGeometry, x, y, ex, ey, wall):
+    """Fraction t in (0, 1] of the link from node (x, y) along (ex, ey) at which it meets
+    the wall: the cornea circle for a CORNEA neighbour, the floor's half-way line
+    y = jf - 1/2 for an IRIS neighbour."""
+    if wall == WALL_IRIS:
+        return (geo.jf - 0.5 - y) / ey if ey != 0 else 0.5
+    dx, dy = x - geo.xc, y - geo.yc
+    a = ex * ex + ey * ey
+    b = dx * ex + dy * ey
+    c = dx * dx + dy * dy - geo.R * geo.R
+    t = (-b + math.sqrt(max(b * b - a * c, 0.0))) / a
+    return min(max(t, 1e-6), 1.0)
 
 
 def _eye_normal(geo: EyeGeometry, x, y, wall):
@@ -208,11 +227,14 @@ def _frame(mask: np.ndarray, periodic_x: bool = False, periodic_y: bool = False)
         mask[e] = m
 
 
-def wall_list(mask: np.ndarray, normal_fn, periodic_x: bool = False, periodic_y: bool = False):
+def wall_list(mask: np.ndarray, normal_fn, periodic_x: bool = False, periodic_y: bool = False,
+              q_fn=None):
     """FLUID nodes with at least one link to a CORNEA or IRIS solid, sorted by node index.
 
     A node touching both walls is listed once, as CORNEA.  The normal comes from
     `normal_fn(x, y, wall)` on arrays (analytic, unit length, pointing into the fluid).
+    The link fractions come from `q_fn(x, y, ex, ey, wall_of_neighbour)` (scalars), or are
+    1/2 (the half-way wall) without one.
     """
     ny, nx = mask.shape
     cls = mask & 7
@@ -253,6 +275,18 @@ def wall_list(mask: np.ndarray, normal_fn, periodic_x: bool = False, periodic_y:
     n_x, n_y = normal_fn(x, y, w)
     out["nx"] = n_x
     out["ny"] = n_y
+    out["q"] = -1.0
+    for k, node in enumerate(idx):
+        xx, yy = int(node % nx), int(node // nx)
+        for i, (ex, ey) in enumerate(_LINKS):
+            x2, y2 = xx + ex, yy + ey
+            if periodic_x:
+                x2 %= nx
+            if periodic_y:
+                y2 %= ny
+            if not (0 <= x2 < nx and 0 <= y2 < ny) or cls[y2, x2] != SOLID or wl[y2, x2] == WALL_BOX:
+                continue
+            out["q"][k, i] = 0.5 if q_fn is None else q_fn(xx, yy, ex, ey, int(wl[y2, x2]))
     return out
 
 
@@ -332,6 +366,9 @@ class Params:
     # lumped meshwork outlet (outlet_mode = OUTLET_LUMPED): permeability, thickness and
     # Schlemm's-canal pressure, lattice units
     outlet_mode: int = OUTLET_PRESSURE
+    # boundary scheme: BC_LINKWISE (half-way bounce-back) or BC_PAPER (interpolated
+    # bounce-back of Bouzidi et al. on CORNEA / IRIS walls with the wall list's fractions)
+    bc_scheme: int = BC_LINKWISE
     K_tm: float = 1.0
     h_tm: float = 1.0
     p_sc: float = 1.0 / 3.0

@@ -75,6 +75,10 @@ enum { AQ_DIR_PX = 0, AQ_DIR_PY = 1, AQ_DIR_MX = 2, AQ_DIR_MY = 3 };
  * section 2.2.4 (Darcy seepage driven by the IOP, applied as a velocity condition). */
 enum { AQ_OUTLET_PRESSURE = 0, AQ_OUTLET_LUMPED = 1 };
 
+/* Boundary schemes: link-wise (half-way bounce-back walls) or the paper's (section 2.3:
+ * the interpolated bounce-back of Bouzidi et al. on CORNEA and IRIS walls). */
+enum { AQ_BC_LINKWISE = 0, AQ_BC_PAPER = 1 };
+
 /*
  * Solver parameters (lattice units).  struct_size must be sizeof(aq_params).
  *
@@ -111,6 +115,14 @@ enum { AQ_OUTLET_PRESSURE = 0, AQ_OUTLET_LUMPED = 1 };
  *                     along its outward direction (moving-wall bounce-back).
  *   K_tm, h_tm, p_sc  lumped meshwork permeability and thickness (> 0) and Schlemm's-
  *                     canal pressure (absolute)
+ *   bc_scheme         AQ_BC_LINKWISE, or AQ_BC_PAPER: the flow populations of a wall-list
+ *                     node's links into CORNEA / IRIS solids take the linear interpolated
+ *                     bounce-back of Bouzidi et al. with the link fractions q of the wall
+ *                     list (q < 1/2: 2q h*_o(x) + (1 - 2q) h*_o(x - e_o); q >= 1/2:
+ *                     h*_o(x)/(2q) + (2q - 1)/(2q) h*_i(x), o the link toward the wall,
+ *                     i its opposite, h* post-collision; half-way bounce-back when q < 1/2
+ *                     and x - e_o is not active).  Not mass-conserving on curved walls.
+ *   reserved1         0
  */
 typedef struct aq_params {
     uint32_t struct_size;
@@ -119,6 +131,7 @@ typedef struct aq_params {
     int32_t check_interval;
     int32_t fp16_exp_flow, fp16_exp_thermal;
     int32_t outlet_mode;
+    int32_t bc_scheme, reserved1;
     double tau_f, tau_t, w0;
     double u_in_x, u_in_y;
     double p_ref, p_out, p_init;
@@ -128,12 +141,16 @@ typedef struct aq_params {
     double K_tm, h_tm, p_sc;
 } aq_params;
 
-/* Wall-shear-stress node: an active FLUID node next to a CORNEA or IRIS solid, with the
- * unit normal (n_x, n_y) pointing into the fluid.  Lists must be sorted by node. */
+/* Wall node: an active FLUID node next to a CORNEA or IRIS solid, with the unit normal
+ * (n_x, n_y) pointing into the fluid (wall shear stress) and, for each link i = 1..8, the
+ * fraction q[i-1] in (0, 1] of the link along e_i at which it meets the wall when the
+ * neighbour along e_i is a CORNEA or IRIS solid, else -1 (AQ_BC_PAPER).  Lists must be
+ * sorted by node. */
 typedef struct aq_wall_node {
     int32_t node;   /* y*nx + x */
     int32_t wall;   /* AQ_WALL_CORNEA or AQ_WALL_IRIS */
     double n_x, n_y;
+    double q[8];
 } aq_wall_node;
 
 /*

@@ -38,6 +38,7 @@ def build(force: bool = True) -> str:
 class OrParams(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("periodic_x", C.c_int32),
                 ("periodic_y", C.c_int32), ("check_interval", C.c_int32), ("outlet_mode", C.c_int32),
+                ("bc_scheme", C.c_int32), ("pad_", C.c_int32),
                 ("tau_f", C.c_double), ("tau_t", C.c_double), ("w0", C.c_double),
                 ("u_in_x", C.c_double), ("u_in_y", C.c_double),
                 ("p_ref", C.c_double), ("p_out", C.c_double), ("p_init", C.c_double),
@@ -68,7 +69,7 @@ def lib():
         L = C.CDLL(_LIB)
         dp = C.POINTER(C.c_double)
         L.or_create.restype = C.c_void_p
-        L.or_create.argtypes = [C.POINTER(OrParams), C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+        L.or_create.argtypes = [C.POINTER(OrParams), C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_void_p]
         L.or_destroy.argtypes = [C.c_void_p]
         L.or_step.argtypes = [C.c_void_p, C.c_int64]
@@ -96,7 +97,8 @@ def make_params(p) -> OrParams:
     d = p if isinstance(p, dict) else p.asdict()
     op = OrParams()
     for name, _ in OrParams._fields_:
-        setattr(op, name, d[name])
+        if name != "pad_":
+            setattr(op, name, d[name])
     return op
 
 
@@ -118,15 +120,18 @@ class Oracle:
         if walls is None or len(walls) == 0:
             node = np.zeros(1, np.int32); wid = np.zeros(1, np.int32)
             wnx = np.zeros(1); wny = np.zeros(1); nw = 0
+            wq = -np.ones(8)
         else:
             node = np.ascontiguousarray(walls["node"], np.int32)
             wid = np.ascontiguousarray(walls["wall"], np.int32)
             wnx = np.ascontiguousarray(walls["nx"], np.float64)
             wny = np.ascontiguousarray(walls["ny"], np.float64)
+            wq = (np.ascontiguousarray(walls["q"], np.float64) if "q" in walls.dtype.names
+                  else -np.ones((len(walls), 8)))
             nw = len(walls)
-        self._keep = (node, wid, wnx, wny)
+        self._keep = (node, wid, wnx, wny, wq)
         self._s = lib().or_create(C.byref(self._p), self.mask.ctypes.data, nw, node.ctypes.data,
-                                  wid.ctypes.data, wnx.ctypes.data, wny.ctypes.data)
+                                  wid.ctypes.data, wnx.ctypes.data, wny.ctypes.data, wq.ctypes.data)
         if not self._s:
             raise ValueError("oracle rejected the parameters")
 

@@ -45,6 +45,14 @@
  *     at INLET (wall velocity u_in), anti-bounce-back pressure at OUTLET (p_out, the
  *     O(u^2) term dropped).  Thermal: anti-bounce-back Dirichlet at CORNEA, IRIS and
  *     INLET (T_cornea, T_iris, T_inlet), adiabatic bounce-back at BOX and OUTLET.
+ *   - The paper's wall scheme (bc_scheme = 1, section 2.3: Bouzidi et al.): a population
+ *     leaving fluid node x along e_o toward a CORNEA or IRIS wall that the link meets at the
+ *     fraction q of its length returns along e_i = -e_o as the linear interpolation
+ *     q < 1/2:  2q f*_o(x) + (1 - 2q) f*_o(x - e_o)
+ *     q >= 1/2: f*_o(x) / (2q) + (2q - 1)/(2q) f*_i(x)
+ *     (f* post-collision); q = 1/2 is the half-way bounce-back.  Where q < 1/2 and x - e_o
+ *     is not an active node the half-way bounce-back is kept.  Thermal walls and the inlet
+ *     and outlet keep the link-wise rules.
  *   - Lumped meshwork outlet (the coupling of section 2.2.4 with eq. 2 and eq. 4): the
  *     pressure in the meshwork falls linearly over its thickness h_TM from the IOP to the
  *     Schlemm's-canal pressure p_sc, so Darcy's law gives the seepage speed
@@ -106,6 +114,8 @@ struct or_state {
     double* T_prev;
     int n_walls;
     int32_t* wall_node;
+    double* wall_q;          /* [n_walls][8] link fractions */
+    int32_t* wall_of;        /* [n] index into the wall list, -1 off it */
     int32_t* wall_id;
     double* wall_nx;
     double* wall_ny;
@@ -251,7 +261,17 @@ static void step_once(or_state* s)
                 if (c == OR_FLUID || c == OR_POROUS) {
                     s->hn[(size_t)(i - 1) * n + kk] = hout;
                 } else if (c == OR_SOLID) {
-                    *back = hout;                                       /* half-way bounce-back */
+                    double q = -1.0;
+                    if (P->bc_scheme == OR_BC_PAPER && s->wall_of[k] >= 0)
+                        q = s->wall_q[(size_t)s->wall_of[k] * 8 + (i - 1)];
+                    long kb = neighbour(s, x, y, -ex[i], -ey[i]);       /* x - e_o */
+                    if (q >= 0.5) {                                     /* interpolated bounce-back */
+                        *back = hout / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * s->hs[(size_t)(ib - 1) * n + k];
+                    } else if (q > 0.0 && kb >= 0 && is_active(s, (size_t)kb)) {
+                        *back = 2.0 * q * hout + (1.0 - 2.0 * q) * s->hs[(size_t)(i - 1) * n + kb];
+                    } else {
+                        *back = hout;                                   /* half-way bounce-back */
+                    }
                 } else if (c == OR_INLET) {
                     double eu = ex[i] * P->u_in_x + ey[i] * P->u_in_y;
                     *back = hout - 6.0 * w_flow(i) * eu;                /* moving wall u_in */
@@ -388,7 +408,7 @@ static void set_prev_from_state(or_state* s)
 
 /* ---------------------------------------------------------------- API */
 or_state* or_create(const or_params* P, const uint8_t* mask, int n_walls, const int32_t* wall_node,
-                    const int32_t* wall_id, const double* wall_nx, const double* wall_ny)
+                    const int32_t* wall_id, const double* wall_nx, const double* wall_ny, const double* wall_q)
 {
     if (P->nx < 3 || P->ny < 3 || P->tau_f <= 0.5 || P->tau_t <= 0.5 || P->check_interval < 1) return NULL;
     if (P->outlet_mode == OR_OUTLET_LUMPED && !(P->K_tm > 0 && P->h_tm > 0)) return NULL;
@@ -420,11 +440,16 @@ or_state* or_create(const or_params* P, const uint8_t* mask, int n_walls, const 
     s->wall_id = (int32_t*)malloc((n_walls + 1) * sizeof(int32_t));
     s->wall_nx = (double*)malloc((n_walls + 1) * sizeof(double));
     s->wall_ny = (double*)malloc((n_walls + 1) * sizeof(double));
+    s->wall_q = (double*)malloc(((size_t)n_walls + 1) * 8 * sizeof(double));
+    s->wall_of = (int32_t*)malloc(n * sizeof(int32_t));
+    for (size_t k = 0; k < n; k++) s->wall_of[k] = -1;
     for (int w = 0; w < n_walls; w++) {
         s->wall_node[w] = wall_node[w];
         s->wall_id[w] = wall_id[w];
         s->wall_nx[w] = wall_nx[w];
         s->wall_ny[w] = wall_ny[w];
+        for (int i = 0; i < 8; i++) s->wall_q[(size_t)w * 8 + i] = wall_q ? wall_q[(size_t)w * 8 + i] : -1.0;
+        s->wall_of[wall_node[w]] = w;
     }
 
     /* initial state: equilibrium at (p_init, u = 0, T_init), eq. 7 and eq. 12 */
@@ -449,6 +474,7 @@ void or_destroy(or_state* s)
     free(s->g); free(s->gs); free(s->gn);
     free(s->u_prev_x); free(s->u_prev_y); free(s->T_prev);
     free(s->wall_node); free(s->wall_id); free(s->wall_nx); free(s->wall_ny);
+    free(s->wall_q); free(s->wall_of);
     free(s);
 }
 

@@ -10,9 +10,12 @@ enum { OR_WALL_BOX = 0, OR_WALL_CORNEA = 1, OR_WALL_IRIS = 2 };
 /* outlet_mode: 0 = pressure outlet at p_out; 1 = lumped trabecular meshwork (Darcy
  * seepage velocity from the IOP, applied as a velocity boundary condition) */
 enum { OR_OUTLET_PRESSURE = 0, OR_OUTLET_LUMPED = 1 };
+/* bc_scheme: 0 = half-way bounce-back walls; 1 = the paper's (section 2.3) interpolated
+ * bounce-back of Bouzidi et al. on CORNEA and IRIS walls, with the wall list's fractions */
+enum { OR_BC_LINKWISE = 0, OR_BC_PAPER = 1 };
 
 typedef struct {
-    int32_t nx, ny, periodic_x, periodic_y, check_interval, outlet_mode;
+    int32_t nx, ny, periodic_x, periodic_y, check_interval, outlet_mode, bc_scheme, pad_;
     double tau_f, tau_t, w0;
     double u_in_x, u_in_y;
     double p_ref, p_out, p_init;
@@ -33,8 +36,9 @@ typedef struct {
 
 typedef struct or_state or_state;
 
+/* wall_q: [n_walls][8] link fractions (q[i-1] for link i; -1 where the link meets no wall) */
 or_state* or_create(const or_params* P, const uint8_t* mask, int n_walls, const int32_t* wall_node,
-                    const int32_t* wall_id, const double* wall_nx, const double* wall_ny);
+                    const int32_t* wall_id, const double* wall_nx, const double* wall_ny, const double* wall_q);
 void or_destroy(or_state* s);
 void or_step(or_state* s, int64_t nsteps);
 int64_t or_step_count(const or_state* s);

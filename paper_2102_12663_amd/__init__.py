@@ -37,14 +37,16 @@ class AqParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32),
                 ("storage", C.c_int32), ("check_interval", C.c_int32),
                 ("fp16_exp_flow", C.c_int32), ("fp16_exp_thermal", C.c_int32),
-                ("outlet_mode", C.c_int32)] + [(n, C.c_double) for n in (
+                ("outlet_mode", C.c_int32), ("bc_scheme", C.c_int32), ("reserved1", C.c_int32)] + [
+                    (n, C.c_double) for n in (
                     "tau_f", "tau_t", "w0", "u_in_x", "u_in_y", "p_ref", "p_out", "p_init",
                     "T_ref", "T_init", "T0", "T_cornea", "T_iris", "T_inlet", "gbeta",
                     "gravity_angle", "K", "K_tm", "h_tm", "p_sc")]
 
 
 class AqWallNode(C.Structure):
-    _fields_ = [("node", C.c_int32), ("wall", C.c_int32), ("n_x", C.c_double), ("n_y", C.c_double)]
+    _fields_ = [("node", C.c_int32), ("wall", C.c_int32), ("n_x", C.c_double), ("n_y", C.c_double),
+                ("q", C.c_double * 8)]
 
 
 class AqObservables(C.Structure):
@@ -179,7 +181,7 @@ def make_params(p) -> AqParams:
     ap = AqParams()
     ap.struct_size = C.sizeof(AqParams)
     for name, _ in AqParams._fields_:
-        if name in ("struct_size", "reserved0"):
+        if name in ("struct_size", "reserved0", "reserved1"):
             continue
         setattr(ap, name, d[name])
     return ap
@@ -191,6 +193,9 @@ def _walls(walls):
     arr = (AqWallNode * len(walls))()
     for i, w in enumerate(walls):
         arr[i].node, arr[i].wall, arr[i].n_x, arr[i].n_y = int(w["node"]), int(w["wall"]), float(w["nx"]), float(w["ny"])
+        q = w["q"] if "q" in w.dtype.names else [-1.0] * 8
+        for j in range(8):
+            arr[i].q[j] = float(q[j])
     return C.cast(arr, C.c_void_p), len(walls), arr
 
 

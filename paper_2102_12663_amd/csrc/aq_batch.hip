@@ -306,6 +306,7 @@ int convert_to_f32(aq_batch* b, int i)
         walls[w].wall = s16->hwall_id[w];
         walls[w].n_x = s16->hwall_n[2 * w];
         walls[w].n_y = s16->hwall_n[2 * w + 1];
+        for (int i = 0; i < 8; i++) walls[w].q[i] = s16->hwall_q[8 * (size_t)w + i];
     }
     const Layout L32 = make_layout(P, s16->n_walls);
     size_t off = 0;

@@ -65,7 +65,10 @@ struct StepArgs {
     const int* wall_node;     // sorted node indices (y * pitch + x)
     const int* wall_id;
     const double* wall_n;     // interleaved (n_x, n_y)
+    const double* wall_q;     // [n_walls][8] link fractions (-1: no wall on the link)
+    const int* widx;          // [qs] wall-list index of a node, -1 off the list
     int n_walls;
+    int bc_paper;             // interpolated bounce-back on wall-list links (Bouzidi et al.)
 };
 
 // One instance of a batch (device table entry).  `a` has buffer A as src (even parity).

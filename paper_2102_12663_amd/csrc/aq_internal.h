@@ -30,7 +30,7 @@ struct Layout {
     int pitch;
     long long qs;
     size_t off_a, off_b, off_type, off_uprev, off_tiles, off_tiles2, off_partials, off_counters, off_obs,
-        off_walls, off_scratch, total;
+        off_walls, off_widx, off_scratch, total;
     int max_tiles, max_tiles2;
 };
 
@@ -55,7 +55,9 @@ inline Layout make_layout(const aq_params& P, int n_walls)
     L.off_partials = o; o += align_up((size_t)L.max_tiles * NRED * 8, 256);
     L.off_counters = o; o += 256;
     L.off_obs = o; o += align_up((size_t)OBS_RING * NRED * 8, 256);
-    L.off_walls = o; o += align_up((size_t)std::max(n_walls, 1) * (4 + 4 + 16), 256);
+    // wall list: node, id, normal (2 doubles), link fractions (8 doubles)
+    L.off_walls = o; o += align_up((size_t)std::max(n_walls, 1) * (4 + 4 + 16 + 64), 256);
+    L.off_widx = o; o += align_up((size_t)L.qs * 4, 256);   // node -> wall-list index, -1 off it
     L.off_scratch = o; o += align_up((size_t)P.nx * P.ny * 8, 256);
     L.total = o;
     return L;
@@ -88,7 +90,7 @@ struct aq_solver {
     std::vector<uint8_t> htype;   // [ny][pitch]
     int64_t n_active = 0, n_fluid = 0, n_cornea = 0, n_iris = 0;
     std::vector<int> hwall_node, hwall_id;
-    std::vector<double> hwall_n;
+    std::vector<double> hwall_n, hwall_q;
     int n_walls = 0;
 
     int tile_x = 64, tile_y = 4, tiles_x = 0, n_tiles = 0, xcd_remap = 1;

@@ -123,13 +123,36 @@ __device__ __forceinline__ void pull_loads(const StepArgs& a, const typename Tra
     }
 }
 
-// (3) The link rules on the loaded values of links into non-active nodes.
+// Interpolated bounce-back (Bouzidi et al.; the paper's wall scheme, section 2.3) for link
+// i of node k, whose upstream node x - e_i = x + e_o is a wall the link from x along e_o
+// meets at the fraction q; v = h*_o(x) (the half-way value), `own_i` = h*_i(x) and
+// `behind` = h*_o(x + e_i) (the node behind x, used for q < 1/2).
 template <typename R>
-__device__ __forceinline__ void pull_rules(const StepArgs& a, const uint8_t* nt, bool boundary, Node<R>& n)
+__device__ __forceinline__ R bouzidi(R q, R v, R own_i, R behind)
 {
+    if (q >= R(0.5)) return v / (R(2) * q) + (R(2) * q - R(1)) / (R(2) * q) * own_i;
+    return R(2) * q * v + (R(1) - R(2) * q) * behind;
+}
+
+// Link fraction of the wall that link i's upstream solid presents to wall-list node w
+// (q of the link toward it, -1 if none).
+__device__ __forceinline__ double wall_fraction(const StepArgs& a, int w, int i)
+{
+    return w < 0 ? -1.0 : a.wall_q[8LL * w + (OPP[i] - 1)];
+}
+
+// (3) The link rules on the loaded values of links into non-active nodes.  `t` is the
+// node's type byte; the paper's wall scheme loads the extra population it needs here.
+template <int MODE>
+__device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Traits<MODE>::S* src, int k, uint8_t t,
+                                           const uint8_t* nt, Node<typename Traits<MODE>::R>& n)
+{
+    using T = Traits<MODE>;
+    using R = typename T::R;
     n.qin = R(0);
     n.qout = R(0);
-    if (!boundary) return;
+    if (!(t & F_BOUNDARY)) return;
+    const int w = (a.bc_paper && (t & F_WSS)) ? a.widx[k] : -1;
 #pragma unroll
     for (int i = 1; i <= 8; i++) {
         if (is_active(nt[i])) continue;
@@ -150,7 +173,16 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const uint8_t* nt,
                 n.qout += v - out;
                 n.h[i] = out;
             }
-        }                                                      // SOLID: half-way bounce-back
+        } else if (w >= 0) {                                   // SOLID on the wall list
+            const double q = wall_fraction(a, w, i);
+            const R inv_f = R(a.inv_sf);
+            if (q >= 0.5) {
+                n.h[i] = bouzidi(R(q), v, T::ld(src + (long long)(i - 1) * a.qs + k, inv_f), R(0));
+            } else if (q > 0.0 && is_active(nt[OPP[i]])) {
+                const R behind = T::ld(src + (long long)(OPP[i] - 1) * a.qs + (k + EY[i] * a.pitch + EX[i]), inv_f);
+                n.h[i] = bouzidi(R(q), v, R(0), behind);
+            }
+        }                                                      // else half-way bounce-back
     }
 #pragma unroll
     for (int i = 1; i <= 4; i++) {
@@ -165,13 +197,13 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const uint8_t* nt,
 }
 
 template <int MODE>
-__device__ __forceinline__ void pull_all(const StepArgs& a, const typename Traits<MODE>::S* src, int k,
-                                         bool boundary, Node<typename Traits<MODE>::R>& n)
+__device__ __forceinline__ void pull_all(const StepArgs& a, const typename Traits<MODE>::S* src, int k, uint8_t t,
+                                         Node<typename Traits<MODE>::R>& n)
 {
     uint8_t nt[9];
-    pull_types(a, k, boundary, nt);
+    pull_types(a, k, (t & F_BOUNDARY) != 0, nt);
     pull_loads<MODE>(a, src, k, nt, n);
-    pull_rules(a, nt, boundary, n);
+    pull_rules<MODE>(a, src, k, t, nt, n);
 }
 
 // ------------------------------------------------------------------------------ moments
@@ -483,18 +515,6 @@ __device__ __forceinline__ double wall_stress(const StepArgs& a, const Node<R>& 
     return sqrt(sx * sx + sy * sy);
 }
 
-__device__ __forceinline__ int find_wall(const StepArgs& a, int k)
-{
-    int lo = 0, hi = a.n_walls - 1;
-    while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const int v = a.wall_node[mid];
-        if (v == k) return mid;
-        if (v < k) lo = mid + 1; else hi = mid - 1;
-    }
-    return -1;
-}
-
 // ------------------------------------------------------------------------------ step
 __device__ __forceinline__ int tile_of_block(const StepArgs& a)
 {
@@ -531,7 +551,7 @@ __device__ __forceinline__ void process_tile(const StepArgs& a, int tile, double
     }
     if (act) {
         Node<R> n;
-        pull_all<MODE>(a, src, k, (t & F_BOUNDARY) != 0, n);
+        pull_all<MODE>(a, src, k, t, n);
         const Moments<R> m = moments(n);
         R hs[9], gs[5];
         collide(a, (t & CLS_MASK) == POROUS, n, m, hs, gs);
@@ -543,7 +563,7 @@ __device__ __forceinline__ void process_tile(const StepArgs& a, int tile, double
             r[R_QOUT] = n.qout;
             r[R_QIN] = n.qin;
             if (t & F_WSS) {
-                const int wi = find_wall(a, k);
+                const int wi = a.widx[k];
                 if (wi >= 0) {
                     const double tw = wall_stress(a, n, m, a.wall_n[2 * wi], a.wall_n[2 * wi + 1]);
                     if (a.wall_id[wi] == WALL_CORNEA) { r[R_WSS_C_SUM] = tw; r[R_WSS_C_MAX] = tw; }
@@ -694,9 +714,10 @@ __device__ __forceinline__ int lds_g0(int ly, int lx)
 // Pull from the LDS image of step n+1 (E coordinates: the tile node is (ex, ey)).
 template <int MODE>
 __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Traits<MODE>::R* lds, int k, int ex,
-                                         int ey, bool boundary, Node<typename Traits<MODE>::R>& n)
+                                         int ey, uint8_t t, Node<typename Traits<MODE>::R>& n)
 {
     using R = typename Traits<MODE>::R;
+    const bool boundary = (t & F_BOUNDARY) != 0;
     uint8_t nt[9];
     if (boundary) {
 #pragma unroll
@@ -718,6 +739,7 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
     n.qin = R(0);
     n.qout = R(0);
     if (!boundary) return;
+    const int w = (a.bc_paper && (t & F_WSS)) ? a.widx[k] : -1;
 #pragma unroll
     for (int i = 1; i <= 8; i++) {
         if (up[i]) continue;
@@ -733,6 +755,12 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
             } else {
                 n.h[i] = -v + R(2.0) * lam<R>(i) * R(a.dp_out);
             }
+        } else if (w >= 0) {                              // interpolated bounce-back
+            const double q = wall_fraction(a, w, i);
+            if (q >= 0.5)
+                n.h[i] = bouzidi(R(q), v, lds[lds_at<MODE>(i - 1, ey, ex)], R(0));
+            else if (q > 0.0 && up[OPP[i]])
+                n.h[i] = bouzidi(R(q), v, R(0), lds[lds_at<MODE>(OPP[i] - 1, ey + EY[i], ex + EX[i])]);
         }
     }
 #pragma unroll
@@ -822,7 +850,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
         for (int j = 0; j < F::NA; j++)
             if (is_active(tA[j])) pull_loads<MODE>(a, src, kA[j], ntA[j], nA[j]);
 #pragma unroll
-        for (int j = 0; j < F::NA; j++) pull_rules(a, ntA[j], (tA[j] & F_BOUNDARY) != 0, nA[j]);
+        for (int j = 0; j < F::NA; j++) pull_rules<MODE>(a, src, kA[j], tA[j], ntA[j], nA[j]);
 #pragma unroll
         for (int j = 0; j < F::NA; j++) {
             const int e = threadIdx.x + F::THREADS * j;
@@ -838,7 +866,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
             const uint8_t t = a.type[k];
             if (!is_active(t)) continue;
             Node<R> n;
-            pull_all<MODE>(a, src, k, (t & F_BOUNDARY) != 0, n);
+            pull_all<MODE>(a, src, k, t, n);
             step_a_store<MODE>(a, n, (t & CLS_MASK) == POROUS, ex, ey, lds);
         }
     }
@@ -853,7 +881,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
         const uint8_t t = a.type[k];
         if (!is_active(t)) continue;
         Node<R> n;
-        pull_lds<MODE>(a, lds, k, lx + 1, ly + 1, (t & F_BOUNDARY) != 0, n);
+        pull_lds<MODE>(a, lds, k, lx + 1, ly + 1, t, n);
         const Moments<R> m = moments(n);
         R hs[9], gs[5];
         collide(a, (t & CLS_MASK) == POROUS, n, m, hs, gs);
@@ -1030,7 +1058,7 @@ __global__ __launch_bounds__(256) void unpack_kernel(StepArgs a, int field, int 
         return;
     }
     Node<R> n;
-    pull_all<MODE>(a, (const typename T::S*)a.src, k, (t & F_BOUNDARY) != 0, n);
+    pull_all<MODE>(a, (const typename T::S*)a.src, k, t, n);
     const Moments<R> m = moments(n);
     if (field == 7) {                        // all 13 populations, dense [13][ny][nx]
         const long long n2 = (long long)a.nx * a.ny;

@@ -70,7 +70,10 @@ StepArgs make_args(const aq_solver* s, bool a_is_src)
     a.wall_node = (const int*)(b + s->L.off_walls);
     a.wall_id = (const int*)(b + s->L.off_walls + 4 * (size_t)std::max(s->n_walls, 1));
     a.wall_n = (const double*)(b + s->L.off_walls + 8 * (size_t)std::max(s->n_walls, 1));
+    a.wall_q = (const double*)(b + s->L.off_walls + 24 * (size_t)std::max(s->n_walls, 1));
+    a.widx = (const int*)(b + s->L.off_widx);
     a.n_walls = s->n_walls;
+    a.bc_paper = P.bc_scheme == AQ_BC_PAPER ? 1 : 0;
     a.lumped = P.outlet_mode == AQ_OUTLET_LUMPED ? 1 : 0;
     a.useep_state = (double*)(b + s->L.off_counters + kUseepOffset);
     a.useep = a.useep_state;          // a step pulls with the speed in effect
@@ -158,6 +161,7 @@ int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls,
         return fail(AQ_EINVAL, "fp16 exponents must be in [-1, 40]");
     if (P->outlet_mode != AQ_OUTLET_PRESSURE && P->outlet_mode != AQ_OUTLET_LUMPED)
         return fail(AQ_EINVAL, "unknown outlet_mode");
+    if (P->bc_scheme != AQ_BC_LINKWISE && P->bc_scheme != AQ_BC_PAPER) return fail(AQ_EINVAL, "unknown bc_scheme");
     const int nx = P->nx, ny = P->ny;
     for (int y = 0; y < ny; y++)
         for (int x = 0; x < nx; x++) {
@@ -180,6 +184,10 @@ int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls,
         if (walls[w].wall != AQ_WALL_CORNEA && walls[w].wall != AQ_WALL_IRIS) return fail(AQ_EINVAL, "wall id must be CORNEA or IRIS");
         if (w > 0 && walls[w - 1].node >= k) return fail(AQ_EINVAL, "wall list must be sorted by node, without repeats");
         if (!std::isfinite(walls[w].n_x) || !std::isfinite(walls[w].n_y)) return fail(AQ_EINVAL, "non-finite wall normal");
+        for (int i = 0; i < 8; i++) {
+            const double q = walls[w].q[i];
+            if (!(q == -1.0 || (q > 0.0 && q <= 1.0))) return fail(AQ_EINVAL, "wall link fraction must be -1 or in (0, 1]");
+        }
     }
     return AQ_OK;
 }
@@ -472,12 +480,16 @@ int setup(aq_solver* s, const uint8_t* mask, const aq_wall_node* walls, int32_t 
     s->hwall_node.resize(std::max(n_walls, 1));
     s->hwall_id.resize(std::max(n_walls, 1));
     s->hwall_n.resize(2 * (size_t)std::max(n_walls, 1));
+    s->hwall_q.assign(8 * (size_t)std::max(n_walls, 1), -1.0);
+    std::vector<int> widx((size_t)s->L.qs, -1);
     for (int w = 0; w < n_walls; w++) {
         const int k = walls[w].node, x = k % nx, y = k / nx;
         s->hwall_node[w] = y * pitch + x;
         s->hwall_id[w] = walls[w].wall;
         s->hwall_n[2 * w] = walls[w].n_x;
         s->hwall_n[2 * w + 1] = walls[w].n_y;
+        for (int i = 0; i < 8; i++) s->hwall_q[8 * (size_t)w + i] = walls[w].q[i];
+        widx[(size_t)y * pitch + x] = w;
         s->htype[(size_t)y * pitch + x] |= F_WSS;
         if (walls[w].wall == AQ_WALL_CORNEA) s->n_cornea++; else s->n_iris++;
     }
@@ -492,6 +504,9 @@ int setup(aq_solver* s, const uint8_t* mask, const aq_wall_node* walls, int32_t 
     HIPCHK(hipMemcpyAsync(wb, s->hwall_node.data(), 4 * W, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipMemcpyAsync(wb + 4 * W, s->hwall_id.data(), 4 * W, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipMemcpyAsync(wb + 8 * W, s->hwall_n.data(), 16 * W, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(wb + 24 * W, s->hwall_q.data(), 64 * W, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->base + s->L.off_widx, widx.data(), widx.size() * 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));   // the host vector goes out of scope
     int rc = upload_tiles(s);
     if (rc) return rc;
     for (auto& e : s->ev) HIPCHK(hipEventCreate(&e));

@@ -88,8 +88,8 @@ def _poiseuille(ny, tau=0.8, F=1e-6):
     m = A.channel_mask(nx, ny)
     walls = np.zeros(2 * nx, dtype=A.WALL_DTYPE)
     for x in range(nx):
-        walls[x] = (1 * nx + x, A.WALL_IRIS, 0.0, 1.0)
-        walls[nx + x] = ((ny - 2) * nx + x, A.WALL_CORNEA, 0.0, -1.0)
+        walls[x] = (1 * nx + x, A.WALL_IRIS, 0.0, 1.0, [-1.0] * 8)
+        walls[nx + x] = ((ny - 2) * nx + x, A.WALL_CORNEA, 0.0, -1.0, [-1.0] * 8)
     o = O.Oracle(P, m, np.sort(walls, order="node"))
     nu = (2 * tau - 1) / 6
     o.step((int(8 * H * H / nu) // 1000 + 1) * 1000)
@@ -258,3 +258,46 @@ def test_rayleigh_benard_onset():
     assert glo < 0 < ghi
     fac = lo - glo * (hi - lo) / (ghi - glo)
     assert abs(fac - 1) < 0.08
+
+
+def _poiseuille_offgrid(ny, qb, qt, scheme, tau=0.8, F=1e-6):
+    """Channel with its walls off the half-way lines: at y_b = 1 - qb below row 1 and at
+    y_t = ny - 2 + qt above row ny - 2 (the link fractions of the wall list)."""
+    nx = 4
+    P = A.Params(nx=nx, ny=ny, tau_f=tau, periodic_x=1, check_interval=1000, gbeta=F,
+                 gravity_angle=math.pi / 2, T_init=1.5, T0=0.5, bc_scheme=scheme)
+    m = A.channel_mask(nx, ny)
+    walls = np.zeros(2 * nx, dtype=A.WALL_DTYPE)
+    down = [-1, -1, -1, qb, -1, -1, qb, qb]          # links 4, 7, 8 point to the bottom wall
+    up = [-1, qt, -1, -1, qt, qt, -1, -1]            # links 2, 5, 6 point to the top wall
+    for x in range(nx):
+        walls[x] = (1 * nx + x, A.WALL_IRIS, 0.0, 1.0, down)
+        walls[nx + x] = ((ny - 2) * nx + x, A.WALL_CORNEA, 0.0, -1.0, up)
+    o = O.Oracle(P, m, np.sort(walls, order="node"))
+    nu = (2 * tau - 1) / 6
+    H = ny - 3 + qb + qt
+    o.step((int(10 * H * H / nu) // 1000 + 1) * 1000)
+    y = np.arange(1, ny - 1)
+    exact = F / (2 * nu) * (y - (1 - qb)) * (ny - 2 + qt - y)
+    u = o.fields()[1][1:ny - 1, 1]
+    return np.max(np.abs(u - exact)) / np.max(exact)
+
+
+def test_interpolated_bounce_back_places_the_wall():
+    """The paper's wall scheme (section 2.3, Bouzidi et al.): with walls a fraction q of a
+    link from the nodes, the steady channel flow converges at second order to the parabola
+    between the true wall positions, while half-way bounce-back (the walls it assumes are at
+    q = 1/2) misses it by far more."""
+    qb, qt = 0.3, 0.8
+    errs = [_poiseuille_offgrid(ny, qb, qt, A.BC_PAPER, F=1e-6 * (16 / ny) ** 2) for ny in (16, 32)]
+    half = _poiseuille_offgrid(32, qb, qt, A.BC_LINKWISE, F=1e-6 * (16 / 32) ** 2)
+    assert errs[1] < 3e-3
+    assert 3.0 < errs[0] / errs[1] < 5.0
+    assert half > 10 * errs[1]
+
+
+def test_interpolated_bounce_back_at_half_is_half_way():
+    """q = 1/2 on every wall link reproduces the half-way bounce-back exactly."""
+    a = _poiseuille_offgrid(16, 0.5, 0.5, A.BC_PAPER)
+    b = _poiseuille_offgrid(16, 0.5, 0.5, A.BC_LINKWISE)
+    assert a == b
