@@ -51,8 +51,19 @@
  *     q < 1/2:  2q f*_o(x) + (1 - 2q) f*_o(x - e_o)
  *     q >= 1/2: f*_o(x) / (2q) + (2q - 1)/(2q) f*_i(x)
  *     (f* post-collision); q = 1/2 is the half-way bounce-back.  Where q < 1/2 and x - e_o
- *     is not an active node the half-way bounce-back is kept.  Thermal walls and the inlet
- *     and outlet keep the link-wise rules.
+ *     is not an active node the half-way bounce-back is kept.
+ *     Inlet and outlet (section 2.3: Guo et al.'s non-equilibrium extrapolation): the
+ *     population entering fluid node x from an INLET or OUTLET node b along e_i is b's
+ *     post-collision value, the equilibrium of b's state plus the non-equilibrium part of
+ *     x's post-collision population along e_i:
+ *         f_i = f^eq_i(p_b, u_b) + [f*_i(x) - f^eq_i(p*, u*)],
+ *     (p*, u*) the moments of x's post-collision populations; INLET: u_b = u_in, p_b = p*;
+ *     pressure OUTLET: p_b = p_out, u_b = u*; lumped OUTLET: u_b = u_s n, p_b = p*.
+ *     Thermal Dirichlet walls and the inlet (section 2.3, the extrapolation method) likewise:
+ *         T_i = T^eq_i(T_w, u_b) + [T*_i(x) - T^eq_i(T*, u*)],  u_b = u_in at INLET, 0 at
+ *     walls, T* = sum of x's post-collision thermal populations.  The boundary node b is
+ *     taken to lie on the boundary (one link from x).  At t = 0 these populations are those
+ *     the rules give from the initial equilibrium.
  *   - Lumped meshwork outlet (the coupling of section 2.2.4 with eq. 2 and eq. 4): the
  *     pressure in the meshwork falls linearly over its thickness h_TM from the IOP to the
  *     Schlemm's-canal pressure p_sc, so Darcy's law gives the seepage speed
@@ -224,6 +235,25 @@ static double wall_temperature(const or_state* s, int wall)
     return wall == OR_WALL_CORNEA ? s->P.T_cornea : s->P.T_iris;
 }
 
+/* Deviation-form equilibria (eq. 7-8, eq. 12) and post-collision moments, for the paper's
+ * boundary scheme. */
+static double heq_of(int i, double dp, double ux, double uy) { return lambda_i(i) * dp + S(i, ux, uy); }
+
+static double geq_of(const or_params* P, int i, double T, double ux, double uy)
+{
+    double eu = ex[i] * ux + ey[i] * uy;
+    return w_heat(P, i) * ((T - P->T_ref) + T * eu / ((1.0 - P->w0) / 2.0));
+}
+
+/* moments of node k's post-collision populations: (p* - p_ref, u*, T*) */
+static moments post_moments(const or_state* s, size_t k)
+{
+    double h8[8], g5[5];
+    for (int i = 1; i <= 8; i++) h8[i - 1] = s->hs[(size_t)(i - 1) * s->n + k];
+    for (int i = 0; i <= 4; i++) g5[i] = s->gs[(size_t)i * s->n + k];
+    return moments_of(s, h8, g5);
+}
+
 /* One full time step. */
 static void step_once(or_state* s)
 {
@@ -272,6 +302,22 @@ static void step_once(or_state* s)
                     } else {
                         *back = hout;                                   /* half-way bounce-back */
                     }
+                } else if (P->bc_scheme == OR_BC_PAPER) {                /* INLET or OUTLET, extrapolation */
+                    moments ms = post_moments(s, k);
+                    double dpb = ms.dp, uxb = ms.ux, uyb = ms.uy;
+                    if (c == OR_INLET) {
+                        uxb = P->u_in_x;
+                        uyb = P->u_in_y;
+                    } else if (P->outlet_mode == OR_OUTLET_LUMPED) {
+                        int d = s->wall[kk] + 1;
+                        uxb = ex[d] * s->u_seep;
+                        uyb = ey[d] * s->u_seep;
+                    } else {
+                        dpb = P->p_out - P->p_ref;
+                    }
+                    *back = heq_of(ib, dpb, uxb, uyb) + (s->hs[(size_t)(ib - 1) * n + k] - heq_of(ib, ms.dp, ms.ux, ms.uy));
+                    if (c == OR_INLET) q_in += *back - hout;
+                    else q_out += hout - *back;
                 } else if (c == OR_INLET) {
                     double eu = ex[i] * P->u_in_x + ey[i] * P->u_in_y;
                     *back = hout - 6.0 * w_flow(i) * eu;                /* moving wall u_in */
@@ -295,6 +341,11 @@ static void step_once(or_state* s)
                 double* back = &s->gn[(size_t)ib * n + k];
                 if (c == OR_FLUID || c == OR_POROUS) {
                     s->gn[(size_t)i * n + kk] = gout;
+                } else if (((c == OR_SOLID && wall != OR_WALL_BOX) || c == OR_INLET) && P->bc_scheme == OR_BC_PAPER) {
+                    double Tw = (c == OR_INLET) ? P->T_inlet : wall_temperature(s, wall);
+                    double uxb = c == OR_INLET ? P->u_in_x : 0.0, uyb = c == OR_INLET ? P->u_in_y : 0.0;
+                    moments ms = post_moments(s, k);                        /* extrapolation */
+                    *back = geq_of(P, ib, Tw, uxb, uyb) + (s->gs[(size_t)ib * n + k] - geq_of(P, ib, ms.T, ms.ux, ms.uy));
                 } else if ((c == OR_SOLID && wall != OR_WALL_BOX) || c == OR_INLET) {
                     double Tw = (c == OR_INLET) ? P->T_inlet : wall_temperature(s, wall);
                     *back = -gout + 2.0 * w_heat(P, i) * (Tw - P->T_ref);   /* Dirichlet ABB */
@@ -406,6 +457,49 @@ static void set_prev_from_state(or_state* s)
     }
 }
 
+/* The paper's scheme at t = 0: the populations entering from INLET / OUTLET nodes and
+ * Dirichlet thermal walls are what the extrapolation gives when every post-collision
+ * population is the initial equilibrium. */
+static void initial_boundary_populations(or_state* s)
+{
+    const or_params* P = &s->P;
+    size_t n = s->n;
+    memcpy(s->hs, s->h, 8 * n * sizeof(double));
+    memcpy(s->gs, s->g, 5 * n * sizeof(double));
+    for (int y = 0; y < s->ny; y++)
+        for (int x = 0; x < s->nx; x++) {
+            size_t k = (size_t)y * s->nx + x;
+            if (!is_active(s, k)) continue;
+            moments ms = post_moments(s, k);
+            for (int i = 1; i <= 8; i++) {
+                long kk = neighbour(s, x, y, ex[i], ey[i]);
+                int c = kk < 0 ? OR_SOLID : s->cls[kk];
+                int ib = opposite[i];
+                if (c == OR_INLET || c == OR_OUTLET) {
+                    double dpb = ms.dp, uxb = ms.ux, uyb = ms.uy;
+                    if (c == OR_INLET) {
+                        uxb = P->u_in_x;
+                        uyb = P->u_in_y;
+                    } else if (P->outlet_mode == OR_OUTLET_LUMPED) {
+                        int d = s->wall[kk] + 1;
+                        uxb = ex[d] * s->u_seep;
+                        uyb = ey[d] * s->u_seep;
+                    } else {
+                        dpb = P->p_out - P->p_ref;
+                    }
+                    H(s, ib, k) = heq_of(ib, dpb, uxb, uyb) + (s->hs[(size_t)(ib - 1) * n + k] - heq_of(ib, ms.dp, ms.ux, ms.uy));
+                }
+                if (i > 4) continue;
+                int wall = kk < 0 ? OR_WALL_BOX : s->wall[kk];
+                if ((c == OR_SOLID && wall != OR_WALL_BOX) || c == OR_INLET) {
+                    double Tw = (c == OR_INLET) ? P->T_inlet : wall_temperature(s, wall);
+                    double uxb = c == OR_INLET ? P->u_in_x : 0.0, uyb = c == OR_INLET ? P->u_in_y : 0.0;
+                    G(s, ib, k) = geq_of(P, ib, Tw, uxb, uyb) + (s->gs[(size_t)ib * n + k] - geq_of(P, ib, ms.T, ms.ux, ms.uy));
+                }
+            }
+        }
+}
+
 /* ---------------------------------------------------------------- API */
 or_state* or_create(const or_params* P, const uint8_t* mask, int n_walls, const int32_t* wall_node,
                     const int32_t* wall_id, const double* wall_nx, const double* wall_ny, const double* wall_q)
@@ -460,9 +554,10 @@ or_state* or_create(const or_params* P, const uint8_t* mask, int n_walls, const 
         for (int i = 0; i <= 4; i++)
             G(s, i, k) = act ? w_heat(P, i) * (P->T_init - P->T_ref) : NAN;
     }
+    s->u_seep = P->outlet_mode == OR_OUTLET_LUMPED ? seepage_speed(P, P->p_init) : 0.0;
+    if (P->bc_scheme == OR_BC_PAPER) initial_boundary_populations(s);
     set_prev_from_state(s);
     memset(&s->obs, 0, sizeof(s->obs));
-    s->u_seep = P->outlet_mode == OR_OUTLET_LUMPED ? seepage_speed(P, P->p_init) : 0.0;
     return s;
 }
 

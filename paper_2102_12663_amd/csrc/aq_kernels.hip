@@ -80,6 +80,26 @@ __device__ __forceinline__ bool is_active(uint8_t t)
     return c == FLUID || c == POROUS;
 }
 
+// ------------------------------------------------------------------------------ moments
+template <typename R> struct Moments {
+    R sum, ux, uy, uu, dp, th;   // th = T - T_ref
+};
+
+template <typename R>
+__device__ __forceinline__ Moments<R> moments(const Node<R>& n)
+{
+    Moments<R> m;
+    const R* h = n.h;
+    m.sum = ((h[1] + h[2]) + (h[3] + h[4])) + ((h[5] + h[6]) + (h[7] + h[8]));
+    m.ux = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
+    m.uy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
+    m.uu = fma(m.ux, m.ux, m.uy * m.uy);
+    // p - p_ref = c^2/(4 sigma) [sum h_i + S_0(u)], S_0 = -(2/3)|u|^2, sigma = 5/12
+    m.dp = R(0.6) * (m.sum - R(2.0 / 3.0) * m.uu);
+    m.th = (n.g[0] + n.g[1]) + (n.g[2] + n.g[3]) + n.g[4];
+    return m;
+}
+
 // ------------------------------------------------------------------------------ pull
 // All 13 loads are issued without intervening branches: a boundary node first reads its
 // 8 neighbours' type bytes, each load address is then selected (upstream slot, or the
@@ -134,6 +154,81 @@ __device__ __forceinline__ R bouzidi(R q, R v, R own_i, R behind)
     return R(2) * q * v + (R(1) - R(2) * q) * behind;
 }
 
+// Deviation-form equilibria (eq. 7-8 and eq. 12) for the extrapolated boundaries.
+template <typename R>
+__device__ __forceinline__ R heq_dev(int i, R dp, R ux, R uy)
+{
+    const R eu = R(EX[i]) * ux + R(EY[i]) * uy;
+    return lam<R>(i) * dp + wflow<R>(i) * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * (ux * ux + uy * uy));
+}
+
+// T_abs = T_ref + th
+template <typename R>
+__device__ __forceinline__ R geq_dev(const StepArgs& a, int i, R th, R T_abs, R ux, R uy)
+{
+    const R eu = R(EX[i]) * ux + R(EY[i]) * uy;
+    return R(a.wT) * (th + T_abs * eu * R(a.inv_cs2T));
+}
+
+// Does node (type t, neighbour types nt) have a link that the paper's extrapolation
+// handles: from an INLET / OUTLET node (flow) or a Dirichlet wall or INLET (thermal)?
+__device__ __forceinline__ bool needs_extrapolation(const StepArgs& a, const uint8_t* nt)
+{
+    bool e = false;
+#pragma unroll
+    for (int i = 1; i <= 8; i++) {
+        const uint8_t c = nt[i] & CLS_MASK;
+        if (is_active(nt[i])) continue;
+        if (c == INLET || c == OUTLET) e = true;
+        if (i <= 4 && c == SOLID && ((nt[i] >> WALL_SHIFT) & 3) != WALL_BOX) e = true;
+    }
+    return a.bc_paper && e;
+}
+
+// The extrapolated boundary values (Guo et al.'s non-equilibrium extrapolation; section
+// 2.3's inlet/outlet and thermal-wall schemes): for flow link i from an INLET / OUTLET
+// node, h_i = h^eq_i(p_b, u_b) + (h*_i(x) - h^eq_i(p*, u*)); for thermal link i from a
+// Dirichlet wall or INLET, g_i = g^eq_i(T_w, u_b) + (g*_i(x) - g^eq_i(T*, u*)).  `own`
+// holds x's post-collision populations and `ms` their moments.  Returns the flow mass the
+// link brings in (for the inflow / outflow sums) through `net`.
+template <typename R>
+__device__ __forceinline__ void extrapolate_links(const StepArgs& a, const uint8_t* nt, const Node<R>& own,
+                                                  const Moments<R>& ms, Node<R>& n)
+{
+#pragma unroll
+    for (int i = 1; i <= 8; i++) {
+        if (is_active(nt[i])) continue;
+        const uint8_t c = nt[i] & CLS_MASK;
+        if (c != INLET && c != OUTLET) continue;
+        R dpb = ms.dp, uxb = ms.ux, uyb = ms.uy;
+        if (c == INLET) {
+            uxb = R(a.uin_x);
+            uyb = R(a.uin_y);
+        } else if (a.lumped) {
+            const int d = ((nt[i] >> WALL_SHIFT) & 3) + 1;
+            uxb = R(EX[d]) * R(*a.useep);
+            uyb = R(EY[d]) * R(*a.useep);
+        } else {
+            dpb = R(a.dp_out);
+        }
+        const R v = n.h[i];
+        n.h[i] = heq_dev(i, dpb, uxb, uyb) + (own.h[i] - heq_dev(i, ms.dp, ms.ux, ms.uy));
+        if (c == INLET) n.qin += n.h[i] - v;
+        else n.qout += v - n.h[i];
+    }
+    const R T_abs = R(a.T_ref) + ms.th;
+#pragma unroll
+    for (int i = 1; i <= 4; i++) {
+        if (is_active(nt[i])) continue;
+        const uint8_t c = nt[i] & CLS_MASK;
+        const uint8_t wall = (nt[i] >> WALL_SHIFT) & 3;
+        if (!(c == INLET || (c == SOLID && wall != WALL_BOX))) continue;
+        const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
+        const R uxb = c == INLET ? R(a.uin_x) : R(0), uyb = c == INLET ? R(a.uin_y) : R(0);
+        n.g[i] = geq_dev(a, i, R(tw), R(a.T_ref) + R(tw), uxb, uyb) + (own.g[i] - geq_dev(a, i, ms.th, T_abs, ms.ux, ms.uy));
+    }
+}
+
 // Link fraction of the wall that link i's upstream solid presents to wall-list node w
 // (q of the link toward it, -1 if none).
 __device__ __forceinline__ double wall_fraction(const StepArgs& a, int w, int i)
@@ -153,12 +248,15 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Tra
     n.qout = R(0);
     if (!(t & F_BOUNDARY)) return;
     const int w = (a.bc_paper && (t & F_WSS)) ? a.widx[k] : -1;
+    const bool extra = needs_extrapolation(a, nt);
 #pragma unroll
     for (int i = 1; i <= 8; i++) {
         if (is_active(nt[i])) continue;
         const uint8_t c = nt[i] & CLS_MASK;
         const R v = n.h[i];
-        if (c == INLET) {                                      // moving wall at u_in
+        if (extra && (c == INLET || c == OUTLET)) {
+            // extrapolated below
+        } else if (c == INLET) {                               // moving wall at u_in
             const R corr = R(6.0) * wflow<R>(i) * (R(EX[i]) * R(a.uin_x) + R(EY[i]) * R(a.uin_y));
             n.h[i] = v + corr;
             n.qin += corr;
@@ -186,13 +284,24 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Tra
     }
 #pragma unroll
     for (int i = 1; i <= 4; i++) {
-        if (is_active(nt[i])) continue;
+        if (extra || is_active(nt[i])) continue;
         const uint8_t c = nt[i] & CLS_MASK;
         const uint8_t wall = (nt[i] >> WALL_SHIFT) & 3;
         if (c == INLET || (c == SOLID && wall != WALL_BOX)) {  // Dirichlet anti-bounce-back
             const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
             n.g[i] = -n.g[i] + R(2.0) * R(a.wT) * R(tw);
         }                                                      // else adiabatic bounce-back
+    }
+    if (extra) {
+        // the node's own post-collision populations and their moments
+        Node<R> own;
+        const R inv_f = R(a.inv_sf), inv_t = R(a.inv_st);
+#pragma unroll
+        for (int i = 1; i <= 8; i++) own.h[i] = T::ld(src + (long long)(i - 1) * a.qs + k, inv_f);
+#pragma unroll
+        for (int i = 0; i <= 4; i++) own.g[i] = T::ld(src + (8LL + i) * a.qs + k, inv_t);
+        const Moments<R> ms = moments(own);
+        extrapolate_links(a, nt, own, ms, n);
     }
 }
 
@@ -204,26 +313,6 @@ __device__ __forceinline__ void pull_all(const StepArgs& a, const typename Trait
     pull_types(a, k, (t & F_BOUNDARY) != 0, nt);
     pull_loads<MODE>(a, src, k, nt, n);
     pull_rules<MODE>(a, src, k, t, nt, n);
-}
-
-// ------------------------------------------------------------------------------ moments
-template <typename R> struct Moments {
-    R sum, ux, uy, uu, dp, th;   // th = T - T_ref
-};
-
-template <typename R>
-__device__ __forceinline__ Moments<R> moments(const Node<R>& n)
-{
-    Moments<R> m;
-    const R* h = n.h;
-    m.sum = ((h[1] + h[2]) + (h[3] + h[4])) + ((h[5] + h[6]) + (h[7] + h[8]));
-    m.ux = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
-    m.uy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
-    m.uu = fma(m.ux, m.ux, m.uy * m.uy);
-    // p - p_ref = c^2/(4 sigma) [sum h_i + S_0(u)], S_0 = -(2/3)|u|^2, sigma = 5/12
-    m.dp = R(0.6) * (m.sum - R(2.0 / 3.0) * m.uu);
-    m.th = (n.g[0] + n.g[1]) + (n.g[2] + n.g[3]) + n.g[4];
-    return m;
 }
 
 // ------------------------------------------------------------------------------ collide
@@ -740,12 +829,15 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
     n.qout = R(0);
     if (!boundary) return;
     const int w = (a.bc_paper && (t & F_WSS)) ? a.widx[k] : -1;
+    const bool extra = needs_extrapolation(a, nt);
 #pragma unroll
     for (int i = 1; i <= 8; i++) {
         if (up[i]) continue;
         const uint8_t c = nt[i] & CLS_MASK;
         const R v = n.h[i];
-        if (c == INLET) {
+        if (extra && (c == INLET || c == OUTLET)) {
+            // extrapolated below
+        } else if (c == INLET) {
             const R corr = R(6.0) * wflow<R>(i) * (R(EX[i]) * R(a.uin_x) + R(EY[i]) * R(a.uin_y));
             n.h[i] = v + corr;
         } else if (c == OUTLET) {
@@ -765,13 +857,23 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
     }
 #pragma unroll
     for (int i = 1; i <= 4; i++) {
-        if (up[i]) continue;
+        if (extra || up[i]) continue;
         const uint8_t c = nt[i] & CLS_MASK;
         const uint8_t wall = (nt[i] >> WALL_SHIFT) & 3;
         if (c == INLET || (c == SOLID && wall != WALL_BOX)) {
             const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
             n.g[i] = -n.g[i] + R(2.0) * R(a.wT) * R(tw);
         }
+    }
+    if (extra) {
+        Node<R> own;
+#pragma unroll
+        for (int i = 1; i <= 8; i++) own.h[i] = lds[lds_at<MODE>(i - 1, ey, ex)];
+        own.g[0] = lds[lds_g0<MODE>(ey, ex)];
+#pragma unroll
+        for (int i = 1; i <= 4; i++) own.g[i] = lds[lds_at<MODE>(7 + i, ey, ex)];
+        const Moments<R> ms = moments(own);
+        extrapolate_links(a, nt, own, ms, n);
     }
 }
 
@@ -1000,6 +1102,10 @@ __global__ __launch_bounds__(256) void scatter_kernel(StepArgs a, const double* 
         const uint8_t c = a.type[ks] & CLS_MASK;
         if (c == FLUID || c == POROUS) {
             T::st(X + (long long)(i - 1) * a.qs + ks, f, sf);
+        } else if (a.bc_paper && (c == INLET || c == OUTLET)) {
+            // the extrapolation reads this slot as the node's own post-collision value
+            const R own = pops ? R(pops[(OPP[i] - 1) * n2 + d]) : lam<R>(OPP[i]) * R(dp0);
+            T::st(X + (long long)(OPP[i] - 1) * a.qs + k, own, sf);
         } else {
             R v;
             if (c == SOLID) v = f;
@@ -1024,7 +1130,9 @@ __global__ __launch_bounds__(256) void scatter_kernel(StepArgs a, const double* 
         } else {
             const uint8_t wall = (tn >> WALL_SHIFT) & 3;
             R v;
-            if (c == INLET || (c == SOLID && wall != WALL_BOX)) {
+            if (a.bc_paper && (c == INLET || (c == SOLID && wall != WALL_BOX))) {
+                v = pops ? R(pops[(8 + OPP[i]) * n2 + d]) : R(a.wT) * R(th0);   // own value (extrapolation)
+            } else if (c == INLET || (c == SOLID && wall != WALL_BOX)) {
                 const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
                 v = R(2.0) * R(a.wT) * R(tw) - f;
             } else {

@@ -301,3 +301,47 @@ def test_interpolated_bounce_back_at_half_is_half_way():
     a = _poiseuille_offgrid(16, 0.5, 0.5, A.BC_PAPER)
     b = _poiseuille_offgrid(16, 0.5, 0.5, A.BC_LINKWISE)
     assert a == b
+
+
+def _plug(scheme, steps=300, U=0.02, nx=24, ny=6):
+    """Duct periodic in y: INLET column x = 0 (velocity U along x), OUTLET column
+    x = nx - 1 (p_out), no walls; started from the uniform flow U at p = p_out."""
+    mask = np.full((ny, nx), A.encode(A.FLUID), np.uint8)
+    mask[:, 0] = A.encode(A.INLET)
+    mask[:, nx - 1] = A.encode(A.OUTLET)
+    P = A.Params(nx=nx, ny=ny, tau_f=0.8, periodic_y=1, u_in_x=U, p_out=1.0 / 3.0 + 1e-4,
+                 check_interval=100, bc_scheme=scheme)
+    o = O.Oracle(P, mask)
+    init_from_fields(o, P, P.p_out, U, 0.0, P.T_ref)
+    h0 = o.populations()[0].copy()
+    o.step(steps)
+    act = A.active(mask)
+    return np.max(np.abs(o.populations()[0][:, act] - h0[:, act])) / np.max(np.abs(h0[:, act]))
+
+
+def test_extrapolated_inlet_outlet_keep_uniform_flow():
+    """Guo et al.'s non-equilibrium extrapolation (the paper's inlet/outlet scheme, section
+    2.3): uniform flow at the outlet pressure is an exact fixed point (the inlet gives the
+    equilibrium at u_in and the fluid's pressure, the outlet at p_out and the fluid's
+    velocity, with no non-equilibrium part), while the link-wise outlet, which drops the
+    O(u^2) term, disturbs it."""
+    assert _plug(A.BC_PAPER) < 1e-13
+    assert _plug(A.BC_LINKWISE) > 1e-6
+
+
+@pytest.mark.parametrize("scheme,ends", [(A.BC_PAPER, (0.0, 0.0)), (A.BC_LINKWISE, (0.5, 0.5))])
+def test_thermal_walls_place_the_temperature(scheme, ends):
+    """Conduction between Dirichlet walls (T = 1 below, 0 above): the extrapolation of the
+    paper's scheme imposes the wall temperature on the solid rows themselves (T linear from
+    y = 0 to y = ny - 1), the link-wise anti-bounce-back half a link inside them; both
+    profiles are exactly linear."""
+    nx, ny = 4, 12
+    mask = A.channel_mask(nx, ny, bottom_wall=A.WALL_IRIS, top_wall=A.WALL_CORNEA)
+    P = A.Params(nx=nx, ny=ny, tau_t=0.9, periodic_x=1, check_interval=1000, T_iris=1.0, T_cornea=0.0,
+                 bc_scheme=scheme)
+    o = O.Oracle(P, mask)
+    o.step(40000)
+    T = o.fields()[3][1:ny - 1, 1]
+    y = np.arange(1, ny - 1)
+    y0, y1 = ends[0], ny - 1 - ends[1]
+    assert np.max(np.abs(T - (1.0 - (y - y0) / (y1 - y0)))) < 1e-12
