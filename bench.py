@@ -234,8 +234,9 @@ def main():
         launch_ms = plain_ms / (steps * info["graph_launches"])
         steps_per_launch = 2 if info["fusion"] else 1
         nt = "true" if info["nt_store"] else "false"
-        kernel = (f"step2_kernel<{STORAGES[storage_name]}, {nt}> (two time steps per launch)" if info["fusion"]
-                  else f"step_kernel<{STORAGES[storage_name]}, false, {nt}>")
+        bcs = "true" if bc else "false"
+        kernel = (f"step2_kernel<{STORAGES[storage_name]}, {nt}, {bcs}> (two time steps per launch)" if info["fusion"]
+                  else f"step_kernel<{STORAGES[storage_name]}, false, {nt}, {bcs}>")
         achieved = info["bytes_per_node_update"] * act * steps_per_launch / (launch_ms * 1e-3) / 1e9
         return dict(p=p, mask=mask, walls=walls, geo=geo, info=info, wall=wall, total_ms=total_ms,
                     launch_ms=launch_ms, steps_per_launch=steps_per_launch, kernel=kernel,

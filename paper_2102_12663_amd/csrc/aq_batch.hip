@@ -116,6 +116,10 @@ bool resid_done(Slot& sl, int mode, int n_intervals)
 
 }  // namespace
 
+constexpr int NKIND = 6;
+
+inline int kind_of(const aq_solver* s) { return s->mode + (s->P.bc_scheme == AQ_BC_PAPER ? 3 : 0); }
+
 struct aq_batch {
     size_t budget = 0;
     char* arena = nullptr;
@@ -127,17 +131,19 @@ struct aq_batch {
     std::vector<Slot> slots;
     int64_t step = 0;
 
+    // Instances are grouped into kernel classes ("kinds"): storage mode + 3 * boundary
+    // scheme (the paper's schemes are a compile-time variant of the step kernels).
     InstDesc* d_inst = nullptr;
-    int2* d_work[3] = {nullptr, nullptr, nullptr};
-    int2* d_work2[3] = {nullptr, nullptr, nullptr};
-    int* d_nwork = nullptr;         // [0..2] single-step items, [3..5] two-step items
-    int fuse[3] = {1, 1, 0};        // two steps per launch: F64 and F32 yes, F16S no
-    double* d_partials[3] = {nullptr, nullptr, nullptr};
+    int2* d_work[NKIND] = {};
+    int2* d_work2[NKIND] = {};
+    int* d_nwork = nullptr;         // [0, NKIND) single-step items, [NKIND, 2 NKIND) two-step items
+    int fuse[NKIND] = {1, 1, 0, 1, 1, 0};   // two steps per launch: F64 and F32 yes, F16S no
+    double* d_partials[NKIND] = {};
     double* d_latest = nullptr;
     double* h_latest = nullptr;     // pinned
     std::vector<InstDesc> h_inst;
-    int n_work[3] = {0, 0, 0};
-    int n_work2[3] = {0, 0, 0};
+    int n_work[NKIND] = {};
+    int n_work2[NKIND] = {};
 
     int nt_store = 0;               // non-temporal stores for the current working set
     int graph_mask = -1;
@@ -147,29 +153,49 @@ struct aq_batch {
 
 namespace {
 
-BatchArgs batch_args(const aq_batch* b, int mode, int parity)
+BatchArgs batch_args(const aq_batch* b, int kind, int parity)
 {
     BatchArgs a;
     a.inst = b->d_inst;
-    a.work = b->d_work[mode];
-    a.n_work = b->d_nwork + mode;
-    a.work2 = b->d_work2[mode];
-    a.n_work2 = b->d_nwork + 3 + mode;
-    a.partials = b->d_partials[mode];
+    a.work = b->d_work[kind];
+    a.n_work = b->d_nwork + kind;
+    a.work2 = b->d_work2[kind];
+    a.n_work2 = b->d_nwork + NKIND + kind;
+    a.partials = b->d_partials[kind];
     a.latest = b->d_latest;
     a.parity = parity;
     a.max_slots = b->max_slots;
-    a.mode = mode;
+    a.mode = kind % 3;
+    a.kind = kind;
     a.nt_store = b->nt_store;
+    a.bc = kind / 3;
     return a;
 }
 
 int active_mask(const aq_batch* b)
 {
     int m = 0;
-    for (int i = 0; i < 3; i++)
+    for (int i = 0; i < NKIND; i++)
         if (b->n_work[i] > 0) m |= 1 << i;
     return m;
+}
+
+// Work lists and partials of a kernel class, allocated when its first instance arrives.
+int ensure_kind(aq_batch* b, int k)
+{
+    if (b->d_work[k]) return AQ_OK;
+    const size_t mt = (size_t)b->max_tiles;
+    if (hipMalloc((void**)&b->d_work[k], mt * sizeof(int2)) != hipSuccess ||
+        hipMalloc((void**)&b->d_work2[k], mt * sizeof(int2)) != hipSuccess ||
+        hipMalloc((void**)&b->d_partials[k], mt * NRED * 8) != hipSuccess) {
+        (void)hipFree(b->d_work[k]);
+        (void)hipFree(b->d_work2[k]);
+        (void)hipFree(b->d_partials[k]);
+        b->d_work[k] = b->d_work2[k] = nullptr;
+        b->d_partials[k] = nullptr;
+        return fail(AQ_ENOMEM, "cannot allocate the batch work lists");
+    }
+    return AQ_OK;
 }
 
 void drop_graph(aq_batch* b)
@@ -190,7 +216,7 @@ int ensure_graph(aq_batch* b)
     drop_graph(b);
     HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
-    for (int m = 0; m < 3 && err == hipSuccess; m++) {
+    for (int m = 0; m < NKIND && err == hipSuccess; m++) {
         if (!(mask & (1 << m))) continue;
         // interval - 1 plain steps then the reducing one; with fusion, an even number F of
         // two-step launches so every interval swaps the buffers an even number of times
@@ -199,12 +225,12 @@ int ensure_graph(aq_batch* b)
         const int F = b->fuse[m] ? (plain / 2) & ~1 : 0;
         int parity = 0;
         for (int j = 0; j < F && err == hipSuccess; j++, parity ^= 1)
-            err = launch_batch_step2(m, batch_args(b, m, parity), b->grid, b->stream);
+            err = launch_batch_step2(m % 3, batch_args(b, m, parity), b->grid, b->stream);
         for (int j = 2 * F; j < plain && err == hipSuccess; j++, parity ^= 1)
-            err = launch_batch_step(m, false, batch_args(b, m, parity), b->grid, b->stream);
-        if (err == hipSuccess) err = launch_batch_step(m, true, batch_args(b, m, parity), b->grid, b->stream);
+            err = launch_batch_step(m % 3, false, batch_args(b, m, parity), b->grid, b->stream);
+        if (err == hipSuccess) err = launch_batch_step(m % 3, true, batch_args(b, m, parity), b->grid, b->stream);
     }
-    for (int m = 0; m < 3 && err == hipSuccess; m++)
+    for (int m = 0; m < NKIND && err == hipSuccess; m++)
         if (mask & (1 << m)) err = launch_batch_finish(batch_args(b, m, 0), b->stream);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
@@ -228,7 +254,7 @@ int ensure_graph(aq_batch* b)
 // copy them to the device (ordered on the batch stream, then synchronised).
 int upload_tables(aq_batch* b)
 {
-    std::vector<int2> work[3], work2[3];
+    std::vector<int2> work[NKIND], work2[NKIND];
     double bytes = 0;
     for (const Slot& sl : b->slots)
         if (sl.used && sl.running) bytes += (double)sl.s->n_active * bytes_per_update(sl.s->mode);
@@ -242,7 +268,7 @@ int upload_tables(aq_batch* b)
         std::memset(&d, 0, sizeof(d));
         const Slot& sl = b->slots[i];
         if (!sl.used || !sl.running) continue;
-        const int m = sl.s->mode;
+        const int m = kind_of(sl.s);
         d.a = make_args(sl.s, true);
         d.a.nt_store = nt;
         d.a2 = make_args2(sl.s, true);
@@ -250,13 +276,17 @@ int upload_tables(aq_batch* b)
         d.work_start = (int)work[m].size();
         d.work_count = sl.s->n_tiles;
         d.running = 1;
-        d.mode = m;
+        d.mode = m;                    // the instance's kernel class
         for (int t : sl.s->htiles) work[m].push_back(make_int2(i, t));
         for (int t : sl.s->htiles2) work2[m].push_back(make_int2(i, t));
     }
-    for (int m = 0; m < 3; m++) {
+    for (int m = 0; m < NKIND; m++) {
         if ((int)work[m].size() > b->max_tiles || (int)work2[m].size() > b->max_tiles)
             return fail(AQ_EBUSY, "work list capacity exceeded");
+        if (!work[m].empty()) {
+            int rc = ensure_kind(b, m);
+            if (rc) return rc;
+        }
         b->n_work[m] = (int)work[m].size();
         b->n_work2[m] = (int)work2[m].size();
         if (!work[m].empty())
@@ -264,7 +294,11 @@ int upload_tables(aq_batch* b)
         if (!work2[m].empty())
             HIPCHK(hipMemcpyAsync(b->d_work2[m], work2[m].data(), work2[m].size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
     }
-    int counts[6] = {b->n_work[0], b->n_work[1], b->n_work[2], b->n_work2[0], b->n_work2[1], b->n_work2[2]};
+    int counts[2 * NKIND];
+    for (int m = 0; m < NKIND; m++) {
+        counts[m] = b->n_work[m];
+        counts[NKIND + m] = b->n_work2[m];
+    }
     HIPCHK(hipMemcpyAsync(b->d_nwork, counts, sizeof(counts), hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipMemcpyAsync(b->d_inst, b->h_inst.data(), b->h_inst.size() * sizeof(InstDesc), hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
@@ -390,10 +424,6 @@ int aq_batch_create(size_t budget_bytes, int32_t max_slots, int64_t max_active_n
               hipMalloc((void**)&b->d_nwork, 64) == hipSuccess &&
               hipMalloc((void**)&b->d_latest, (size_t)max_slots * NRED * 8) == hipSuccess &&
               hipHostMalloc((void**)&b->h_latest, (size_t)max_slots * NRED * 8, hipHostMallocDefault) == hipSuccess;
-    for (int m = 0; m < 3 && ok; m++)
-        ok = hipMalloc((void**)&b->d_work[m], (size_t)max_tiles * sizeof(int2)) == hipSuccess &&
-             hipMalloc((void**)&b->d_work2[m], (size_t)max_tiles * sizeof(int2)) == hipSuccess &&
-             hipMalloc((void**)&b->d_partials[m], (size_t)max_tiles * NRED * 8) == hipSuccess;
     if (!ok) return cleanup(fail(AQ_ENOMEM, "cannot allocate the batch tables"));
     int rc = upload_tables(b);
     if (rc) return cleanup(rc);
@@ -412,7 +442,7 @@ int aq_batch_destroy(aq_batch* b)
     (void)hipFree(b->d_nwork);
     (void)hipFree(b->d_latest);
     if (b->h_latest) (void)hipHostFree(b->h_latest);
-    for (int m = 0; m < 3; m++) {
+    for (int m = 0; m < NKIND; m++) {
         (void)hipFree(b->d_work[m]);
         (void)hipFree(b->d_work2[m]);
         (void)hipFree(b->d_partials[m]);
@@ -444,10 +474,10 @@ int aq_batch_admit(aq_batch* b, const aq_params* P, const uint8_t* mask, const a
     rc = create_common(P, mask, walls, n_walls, b->arena + off, L.total, b->stream, false, &s);
     if (rc == AQ_OK) rc = aq_set_tile(s, tile_x, tile_y);
     int tiles_now = 0;
-    for (int m = 0; m < 3; m++) tiles_now += b->n_work[m];
+    for (int m = 0; m < NKIND; m++) tiles_now += b->n_work[m];
     if (rc == AQ_OK && b->max_active && running_active(b) + s->n_active > b->max_active)
         rc = fail(AQ_EBUSY, "active-node cap reached");
-    if (rc == AQ_OK && b->n_work[s->mode] + s->n_tiles > b->max_tiles)
+    if (rc == AQ_OK && b->n_work[kind_of(s)] + s->n_tiles > b->max_tiles)
         rc = fail(AQ_EBUSY, "work list capacity reached");
     if (rc != AQ_OK) {
         std::string keep_err = aq_last_error();
@@ -589,7 +619,7 @@ int aq_batch_resume(aq_batch* b, int32_t slot, double tol, int64_t max_steps)
     if (!(tol > 0) || max_steps < 1) return fail(AQ_EINVAL, "tol and max_steps must be positive");
     if (sl.status != AQ_OK && sl.status != AQ_ENOTCONVERGED) return fail(AQ_ESTATE, "the instance failed");
     if (b->max_active && running_active(b) + sl.s->n_active > b->max_active) return fail(AQ_EBUSY, "active-node cap reached");
-    if (b->n_work[sl.s->mode] + sl.s->n_tiles > b->max_tiles) return fail(AQ_EBUSY, "work list capacity reached");
+    if (b->n_work[kind_of(sl.s)] + sl.s->n_tiles > b->max_tiles) return fail(AQ_EBUSY, "work list capacity reached");
     sl.running = true;
     sl.done = sl.reported = false;
     sl.tol = tol;
@@ -626,7 +656,7 @@ int aq_batch_get_info(aq_batch* b, aq_batch_info* o)
         if (sl.running) o->running++;
         else o->finished++;
     }
-    for (int m = 0; m < 3; m++) o->n_work[m] = b->n_work[m];
+    for (int m = 0; m < NKIND; m++) o->n_work[m % 3] += b->n_work[m];
     o->active_nodes = running_active(b);
     o->budget_bytes = b->budget;
     o->used_bytes = b->pool.used();

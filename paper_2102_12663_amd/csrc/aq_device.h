@@ -76,7 +76,7 @@ struct InstDesc {
     StepArgs a;
     StepArgs a2;                  // the same instance with its fused (two-step) tile list
     int work_start, work_count;   // this instance's run in its storage mode's work list
-    int running, mode;
+    int running, mode;            // mode: the instance's kernel class (storage + 3 * paper scheme)
 };
 
 // Arguments of the batched kernels (one storage mode per launch).
@@ -90,8 +90,10 @@ struct BatchArgs {
     double* latest;            // [max_slots][NRED]: latest raw sums of every instance
     int parity;                // 0: buffer A is src
     int max_slots;
-    int mode;
+    int mode;                  // storage mode of this launch
+    int kind;                  // kernel class of this launch (instances with InstDesc.mode == kind)
     int nt_store;              // non-temporal population stores
+    int bc;                    // 1: the instances of this launch use the paper's boundary schemes
 };
 
 // Host-side launchers (defined in aq_kernels.hip).

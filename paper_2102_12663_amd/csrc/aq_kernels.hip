@@ -238,7 +238,7 @@ __device__ __forceinline__ double wall_fraction(const StepArgs& a, int w, int i)
 
 // (3) The link rules on the loaded values of links into non-active nodes.  `t` is the
 // node's type byte; the paper's wall scheme loads the extra population it needs here.
-template <int MODE>
+template <int MODE, bool BC>
 __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Traits<MODE>::S* src, int k, uint8_t t,
                                            const uint8_t* nt, Node<typename Traits<MODE>::R>& n)
 {
@@ -247,8 +247,8 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Tra
     n.qin = R(0);
     n.qout = R(0);
     if (!(t & F_BOUNDARY)) return;
-    const int w = (a.bc_paper && (t & F_WSS)) ? a.widx[k] : -1;
-    const bool extra = needs_extrapolation(a, nt);
+    const int w = (BC && (t & F_WSS)) ? a.widx[k] : -1;
+    const bool extra = BC && needs_extrapolation(a, nt);
 #pragma unroll
     for (int i = 1; i <= 8; i++) {
         if (is_active(nt[i])) continue;
@@ -271,7 +271,7 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Tra
                 n.qout += v - out;
                 n.h[i] = out;
             }
-        } else if (w >= 0) {                                   // SOLID on the wall list
+        } else if (BC && w >= 0) {                             // SOLID on the wall list
             const double q = wall_fraction(a, w, i);
             const R inv_f = R(a.inv_sf);
             if (q >= 0.5) {
@@ -292,7 +292,8 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Tra
             n.g[i] = -n.g[i] + R(2.0) * R(a.wT) * R(tw);
         }                                                      // else adiabatic bounce-back
     }
-    if (extra) {
+    if constexpr (BC) {
+        if (!extra) return;
         // the node's own post-collision populations and their moments
         Node<R> own;
         const R inv_f = R(a.inv_sf), inv_t = R(a.inv_st);
@@ -305,14 +306,14 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Tra
     }
 }
 
-template <int MODE>
+template <int MODE, bool BC>
 __device__ __forceinline__ void pull_all(const StepArgs& a, const typename Traits<MODE>::S* src, int k, uint8_t t,
                                          Node<typename Traits<MODE>::R>& n)
 {
     uint8_t nt[9];
     pull_types(a, k, (t & F_BOUNDARY) != 0, nt);
     pull_loads<MODE>(a, src, k, nt, n);
-    pull_rules<MODE>(a, src, k, t, nt, n);
+    pull_rules<MODE, BC>(a, src, k, t, nt, n);
 }
 
 // ------------------------------------------------------------------------------ collide
@@ -617,7 +618,7 @@ __device__ __forceinline__ int tile_of_block(const StepArgs& a)
 
 // One tile of one time step: pull, moments, forces, both collisions, store; on check
 // steps also this tile's partial sums (written to `partial`).
-template <int MODE, bool REDUCE, bool NT>
+template <int MODE, bool REDUCE, bool NT, bool BC>
 __device__ __forceinline__ void process_tile(const StepArgs& a, int tile, double* partial)
 {
     using T = Traits<MODE>;
@@ -640,7 +641,7 @@ __device__ __forceinline__ void process_tile(const StepArgs& a, int tile, double
     }
     if (act) {
         Node<R> n;
-        pull_all<MODE>(a, src, k, t, n);
+        pull_all<MODE, BC>(a, src, k, t, n);
         const Moments<R> m = moments(n);
         R hs[9], gs[5];
         collide(a, (t & CLS_MASK) == POROUS, n, m, hs, gs);
@@ -679,11 +680,11 @@ __device__ __forceinline__ void process_tile(const StepArgs& a, int tile, double
 
 // One time step of one lattice: one block per active tile.  The partial of a tile is
 // stored at its index in the tile list.
-template <int MODE, bool REDUCE, bool NT>
+template <int MODE, bool REDUCE, bool NT, bool BC>
 __global__ __launch_bounds__(256) void step_kernel(StepArgs a)
 {
     const int ti = tile_of_block(a);
-    process_tile<MODE, REDUCE, NT>(a, a.tiles[ti], a.partials + (long long)ti * NRED);
+    process_tile<MODE, REDUCE, NT, BC>(a, a.tiles[ti], a.partials + (long long)ti * NRED);
 }
 
 // The instance table and the work list do not change during a launch: read them through
@@ -725,7 +726,7 @@ __device__ __forceinline__ int2 load_item(const int2* work, int w)
 // a contiguous run of work items (neighbouring tiles of one instance stay on one CU); the
 // next item is fetched while the current tile is processed, and an instance's arguments
 // are reloaded only when the slot changes.
-template <int MODE, bool REDUCE, bool NT>
+template <int MODE, bool REDUCE, bool NT, bool BC>
 __global__ __launch_bounds__(256) void batch_step_kernel(BatchArgs b)
 {
     const int n = *b.n_work;
@@ -747,7 +748,7 @@ __global__ __launch_bounds__(256) void batch_step_kernel(BatchArgs b)
             }
             cur_slot = it.x;
         }
-        process_tile<MODE, REDUCE, NT>(a, it.y, b.partials + (long long)w * NRED);
+        process_tile<MODE, REDUCE, NT, BC>(a, it.y, b.partials + (long long)w * NRED);
         if (REDUCE) __syncthreads();
     }
 }
@@ -757,7 +758,7 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(BatchArgs b)
 {
     for (int sl = blockIdx.x; sl < b.max_slots; sl += gridDim.x) {
         const InstDesc* d = b.inst + sl;
-        if (!d->running || d->mode != b.mode) continue;
+        if (!d->running || d->mode != b.kind) continue;
         finish_sum(d->a, b.partials + (long long)d->work_start * NRED, d->work_count, b.latest + (long long)sl * NRED);
     }
 }
@@ -801,7 +802,7 @@ __device__ __forceinline__ int lds_g0(int ly, int lx)
 }
 
 // Pull from the LDS image of step n+1 (E coordinates: the tile node is (ex, ey)).
-template <int MODE>
+template <int MODE, bool BC>
 __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Traits<MODE>::R* lds, int k, int ex,
                                          int ey, uint8_t t, Node<typename Traits<MODE>::R>& n)
 {
@@ -828,8 +829,8 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
     n.qin = R(0);
     n.qout = R(0);
     if (!boundary) return;
-    const int w = (a.bc_paper && (t & F_WSS)) ? a.widx[k] : -1;
-    const bool extra = needs_extrapolation(a, nt);
+    const int w = (BC && (t & F_WSS)) ? a.widx[k] : -1;
+    const bool extra = BC && needs_extrapolation(a, nt);
 #pragma unroll
     for (int i = 1; i <= 8; i++) {
         if (up[i]) continue;
@@ -847,7 +848,7 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
             } else {
                 n.h[i] = -v + R(2.0) * lam<R>(i) * R(a.dp_out);
             }
-        } else if (w >= 0) {                              // interpolated bounce-back
+        } else if (BC && w >= 0) {                        // interpolated bounce-back
             const double q = wall_fraction(a, w, i);
             if (q >= 0.5)
                 n.h[i] = bouzidi(R(q), v, lds[lds_at<MODE>(i - 1, ey, ex)], R(0));
@@ -865,7 +866,8 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
             n.g[i] = -n.g[i] + R(2.0) * R(a.wT) * R(tw);
         }
     }
-    if (extra) {
+    if constexpr (BC) {
+        if (!extra) return;
         Node<R> own;
 #pragma unroll
         for (int i = 1; i <= 8; i++) own.h[i] = lds[lds_at<MODE>(i - 1, ey, ex)];
@@ -920,7 +922,7 @@ __device__ __forceinline__ void step_a_store(const StepArgs& a, const Node<typen
 
 // PF: step A issues the loads of all of a thread's nodes before computing any (more bytes
 // in flight, more registers).
-template <int MODE, bool NT, bool PF>
+template <int MODE, bool NT, bool PF, bool BC>
 __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typename Traits<MODE>::R* lds)
 {
     using T = Traits<MODE>;
@@ -952,7 +954,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
         for (int j = 0; j < F::NA; j++)
             if (is_active(tA[j])) pull_loads<MODE>(a, src, kA[j], ntA[j], nA[j]);
 #pragma unroll
-        for (int j = 0; j < F::NA; j++) pull_rules<MODE>(a, src, kA[j], tA[j], ntA[j], nA[j]);
+        for (int j = 0; j < F::NA; j++) pull_rules<MODE, BC>(a, src, kA[j], tA[j], ntA[j], nA[j]);
 #pragma unroll
         for (int j = 0; j < F::NA; j++) {
             const int e = threadIdx.x + F::THREADS * j;
@@ -968,7 +970,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
             const uint8_t t = a.type[k];
             if (!is_active(t)) continue;
             Node<R> n;
-            pull_all<MODE>(a, src, k, t, n);
+            pull_all<MODE, BC>(a, src, k, t, n);
             step_a_store<MODE>(a, n, (t & CLS_MASK) == POROUS, ex, ey, lds);
         }
     }
@@ -983,7 +985,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
         const uint8_t t = a.type[k];
         if (!is_active(t)) continue;
         Node<R> n;
-        pull_lds<MODE>(a, lds, k, lx + 1, ly + 1, t, n);
+        pull_lds<MODE, BC>(a, lds, k, lx + 1, ly + 1, t, n);
         const Moments<R> m = moments(n);
         R hs[9], gs[5];
         collide(a, (t & CLS_MASK) == POROUS, n, m, hs, gs);
@@ -993,30 +995,36 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
 
 // Two time steps of one lattice; one block per active 64 x TY tile (tile list in
 // a.tiles, laid out with a.tiles_x = ceil(nx / 64) tiles per row).
-template <int MODE, bool NT>
+template <int MODE, bool NT, bool BC>
 __global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void step2_kernel(StepArgs a)
 {
     __shared__ typename Traits<MODE>::R lds[Fuse<MODE>::WORDS];
-    process_tile2<MODE, NT, true>(a, a.tiles[tile_of_block(a)], lds);
+    process_tile2<MODE, NT, true, BC>(a, a.tiles[tile_of_block(a)], lds);
 }
 
-template <int MODE, bool NT>
+template <int MODE, bool NT, bool BC>
 static hipError_t launch_step2_t(const StepArgs& a, hipStream_t s)
 {
     if (a.n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((step2_kernel<MODE, NT>), dim3(a.n_tiles), dim3(Fuse<MODE>::THREADS), 0, s, a);
+    hipLaunchKernelGGL((step2_kernel<MODE, NT, BC>), dim3(a.n_tiles), dim3(Fuse<MODE>::THREADS), 0, s, a);
     return hipGetLastError();
+}
+
+template <int MODE, bool NT>
+static hipError_t launch_step2_bc(const StepArgs& a, hipStream_t s)
+{
+    return a.bc_paper ? launch_step2_t<MODE, NT, true>(a, s) : launch_step2_t<MODE, NT, false>(a, s);
 }
 
 hipError_t launch_step2(int mode, const StepArgs& a, hipStream_t s)
 {
     switch (mode * 2 + (a.nt_store ? 1 : 0)) {
-    case 0: return launch_step2_t<0, false>(a, s);
-    case 1: return launch_step2_t<0, true>(a, s);
-    case 2: return launch_step2_t<1, false>(a, s);
-    case 3: return launch_step2_t<1, true>(a, s);
-    case 4: return launch_step2_t<2, false>(a, s);
-    case 5: return launch_step2_t<2, true>(a, s);
+    case 0: return launch_step2_bc<0, false>(a, s);
+    case 1: return launch_step2_bc<0, true>(a, s);
+    case 2: return launch_step2_bc<1, false>(a, s);
+    case 3: return launch_step2_bc<1, true>(a, s);
+    case 4: return launch_step2_bc<2, false>(a, s);
+    case 5: return launch_step2_bc<2, true>(a, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1025,7 +1033,7 @@ int fused_tile_rows(int mode) { return mode == 0 ? Fuse<0>::TY : mode == 1 ? Fus
 
 // Two time steps of every running instance of a batch whose storage is MODE (fused tile
 // work list; same walk, prefetch and descriptor caching as batch_step_kernel).
-template <int MODE, bool NT>
+template <int MODE, bool NT, bool BC>
 __global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void batch_step2_kernel(BatchArgs b)
 {
     __shared__ typename Traits<MODE>::R lds[Fuse<MODE>::WORDS];
@@ -1048,7 +1056,7 @@ __global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void batch_step2_kernel(Bat
             }
             cur_slot = it.x;
         }
-        process_tile2<MODE, NT, Fuse<MODE>::BATCH_PF>(a, it.y, lds);
+        process_tile2<MODE, NT, Fuse<MODE>::BATCH_PF, BC>(a, it.y, lds);
         __syncthreads();   // the next tile overwrites the LDS image
     }
 }
@@ -1056,7 +1064,8 @@ __global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void batch_step2_kernel(Bat
 template <int MODE, bool NT>
 static hipError_t launch_batch2_t(const BatchArgs& b, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((batch_step2_kernel<MODE, NT>), dim3(grid), dim3(Fuse<MODE>::THREADS), 0, s, b);
+    if (b.bc) hipLaunchKernelGGL((batch_step2_kernel<MODE, NT, true>), dim3(grid), dim3(Fuse<MODE>::THREADS), 0, s, b);
+    else hipLaunchKernelGGL((batch_step2_kernel<MODE, NT, false>), dim3(grid), dim3(Fuse<MODE>::THREADS), 0, s, b);
     return hipGetLastError();
 }
 
@@ -1166,7 +1175,8 @@ __global__ __launch_bounds__(256) void unpack_kernel(StepArgs a, int field, int 
         return;
     }
     Node<R> n;
-    pull_all<MODE>(a, (const typename T::S*)a.src, k, t, n);
+    if (a.bc_paper) pull_all<MODE, true>(a, (const typename T::S*)a.src, k, t, n);
+    else pull_all<MODE, false>(a, (const typename T::S*)a.src, k, t, n);
     const Moments<R> m = moments(n);
     if (field == 7) {                        // all 13 populations, dense [13][ny][nx]
         const long long n2 = (long long)a.nx * a.ny;
@@ -1205,12 +1215,14 @@ static hipError_t launch_step_t(bool reduce, const StepArgs& a, hipStream_t s)
     const dim3 grid(a.n_tiles), block(a.tile_x * a.tile_y);
     if (a.n_tiles == 0) return hipSuccess;
     if (reduce) {
-        hipLaunchKernelGGL((step_kernel<MODE, true, NT>), grid, block, 0, s, a);
+        if (a.bc_paper) hipLaunchKernelGGL((step_kernel<MODE, true, NT, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((step_kernel<MODE, true, NT, false>), grid, block, 0, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, s, a);
     } else {
-        hipLaunchKernelGGL((step_kernel<MODE, false, NT>), grid, block, 0, s, a);
+        if (a.bc_paper) hipLaunchKernelGGL((step_kernel<MODE, false, NT, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((step_kernel<MODE, false, NT, false>), grid, block, 0, s, a);
     }
     return hipGetLastError();
 }
@@ -1231,8 +1243,10 @@ hipError_t launch_step(int mode, bool reduce, const StepArgs& a, hipStream_t s)
 template <int MODE, bool NT>
 static hipError_t launch_batch_t(bool reduce, const BatchArgs& b, int grid, hipStream_t s)
 {
-    if (reduce) hipLaunchKernelGGL((batch_step_kernel<MODE, true, NT>), dim3(grid), dim3(256), 0, s, b);
-    else hipLaunchKernelGGL((batch_step_kernel<MODE, false, NT>), dim3(grid), dim3(256), 0, s, b);
+    if (reduce && b.bc) hipLaunchKernelGGL((batch_step_kernel<MODE, true, NT, true>), dim3(grid), dim3(256), 0, s, b);
+    else if (reduce) hipLaunchKernelGGL((batch_step_kernel<MODE, true, NT, false>), dim3(grid), dim3(256), 0, s, b);
+    else if (b.bc) hipLaunchKernelGGL((batch_step_kernel<MODE, false, NT, true>), dim3(grid), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((batch_step_kernel<MODE, false, NT, false>), dim3(grid), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 
