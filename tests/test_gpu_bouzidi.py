@@ -91,3 +91,24 @@ def test_bouzidi_two_step_launches_bitwise(aq, storage):
     for x, y in zip(out[0][0], out[1][0]):
         assert np.array_equal(np.nan_to_num(x, nan=7.0), np.nan_to_num(y, nan=7.0))
     assert out[0][1] == out[1][1]
+
+
+def test_paper_scheme_in_a_batch_bitwise(aq):
+    """Instances with the paper's schemes and link-wise ones share a batch (separate kernel
+    classes); each computes exactly what it computes alone."""
+    p1, m1, w1 = _eye()
+    p2, m2, w2, geo2 = A.sweep_instance(3, 256, 128)
+    p3 = A.Params(**{**p1.asdict(), "storage": A.F32})
+    b = aq.Batch(budget_bytes=1 << 30, max_slots=8)
+    slots = [b.admit(p, m, w, tile=(64, 4), tol=1e-14, max_steps=10 ** 6, keep=True)
+             for p, m, w in ((p1, m1, w1), (p2, m2, w2), (p3, m1, w1))]
+    b.run(5)
+    for sl, (p, m, w) in zip(slots, ((p1, m1, w1), (p2, m2, w2), (p3, m1, w1))):
+        alone = aq.Solver(p, m, w)
+        alone.set_tile(64, 4)
+        alone.step(500)
+        for f in ("p", "ux", "uy", "T"):
+            assert np.array_equal(np.nan_to_num(b.read_field(sl, f), nan=7.0), np.nan_to_num(alone.read_field(f), nan=7.0))
+        assert b.observe(sl) == alone.observe()
+        alone.close()
+    b.close()
