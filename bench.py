@@ -99,6 +99,40 @@ def batched_vs_one_at_a_time(n, cap=200000, tol=1e-6):
                                   "p99_s": round(float(np.percentile(lat, 99)), 3), "converged": int(conv)}}
 
 
+def batch_sweep(n=512, intervals=10, storages=("f32", "f16s")):
+    """The batched parameter sweep: n instances of the sweep distribution (lattices
+    256x128 .. 1024x512, per-instance tau, Da, inflow, angle, Ra, gravity orientation) resident
+    in one batch and stepped together, per storage.  Aggregate active-node MLUPS over
+    `intervals` check intervals (after two warm-up intervals; residual target 1e-30 so no
+    instance retires) and its fraction of the HBM roofline for the algorithmic bytes."""
+    import torch
+    import aqinputs as A
+    import paper_2102_12663_amd as aq
+    from paper_2102_12663_amd import serve as S
+    reqs = [S.sweep_request(i, aq.F32) for i in range(n)]
+    act = sum(int(A.active(m).sum()) for _, m, _ in reqs)
+    out = {"workload": f"{n} sweep requests (seeds 0..{n - 1}), {act} active nodes, "
+                       f"{intervals} check intervals of 100 time steps"}
+    for st in storages:
+        b = aq.Batch(budget_bytes=96 << 30, max_slots=n, max_tiles=1 << 21)
+        for p, m, w in reqs:
+            b.admit(A.Params(**{**p.asdict(), "storage": STORAGES[st]}), m, w, tile=(64, 4), tol=1e-30,
+                    max_steps=10 ** 9)
+        b.run(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(intervals)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        info = b.info()
+        b.close()
+        mlups = act * intervals * 100 / wall / 1e6
+        bpu = {"f64": 209, "f32": 105, "f16s": 53}[st]
+        out[st] = {"mlups": round(mlups, 1), "achieved_GBs": round(mlups * bpu / 1e3, 1),
+                   "frac": round(mlups * bpu / 1e3 / HBM_PEAK_GBS, 4), "running_after": info["running"]}
+    return out
+
+
 def outflow_area(mask):
     """Outflow area of a lumped-meshwork mask: sum over links from active nodes into OUTLET
     nodes of 6 w_i (e_i . n), n the node's outward direction (mask bits 3-4)."""
@@ -151,6 +185,65 @@ def calibration_workload(n=12, cap=400000):
     return out
 
 
+def dense_box(storages, intervals=10, nx=8192, ny=4096):
+    """The dense variant of the largest lattice: an 8192x4096 closed box, every interior node
+    active (heated floor, cooled lid, buoyancy on), per storage: active MLUPS and the
+    algorithmic bandwidth of the launches that make up the graph part of an interval."""
+    import aqinputs as A
+    import paper_2102_12663_amd as aq
+    mask = A.box_mask(nx, ny, wall_ids=(A.WALL_IRIS, A.WALL_CORNEA, A.WALL_BOX, A.WALL_BOX))
+    out = {"workload": f"{nx}x{ny} closed box, {(nx - 2) * (ny - 2)} active nodes, heated floor, "
+                       f"{intervals} check intervals of 100 time steps"}
+    for st in storages:
+        p = A.Params(nx=nx, ny=ny, gbeta=1e-6, storage=STORAGES[st], check_interval=100)
+        s = aq.Solver(p, mask, A.no_walls())
+        s.run_intervals_timed(1)
+        t0 = time.perf_counter()
+        total_ms, plain_ms = s.run_intervals_timed(intervals)
+        wall = time.perf_counter() - t0
+        info = s.info()
+        s.close()
+        act = info["active_nodes"]
+        spl = 2 if info["fusion"] else 1
+        launch_ms = plain_ms / (intervals * info["graph_launches"])
+        gbs = info["bytes_per_node_update"] * act * spl / (launch_ms * 1e-3) / 1e9
+        out[st] = {"mlups": round(act * intervals * 100 / wall / 1e6, 1), "kernel_ms": round(launch_ms, 4),
+                   "time_steps_per_launch": spl, "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def precision_sweep(steps=20000, nx=8192, ny=4096, seed=0):
+    """The 8192x4096 eye (sweep draw seed 0) for `steps` time steps in each storage, from
+    the same initial state: active MLUPS, and the IOP and velocity errors of FP32 and F16S
+    storage against the FP64 run on the GPU (velocity: L2 over active nodes, relative)."""
+    import numpy as np
+    import aqinputs as A
+    import paper_2102_12663_amd as aq
+    out = {"workload": f"{nx}x{ny} eye section (sweep draw seed {seed}), {steps} time steps per storage"}
+    ref = None
+    for st in ("f64", "f32", "f16s"):
+        p, mask, walls, geo = A.sweep_instance(seed, nx, ny, storage=STORAGES[st])
+        s = aq.Solver(p, mask, walls)
+        D = s.info()["check_interval"]
+        t0 = time.perf_counter()
+        s.run_intervals_timed(steps // D)
+        wall = time.perf_counter() - t0
+        act = s.info()["active_nodes"]
+        ob = s.observe()
+        ux, uy = s.read_field("ux"), s.read_field("uy")
+        s.close()
+        on = A.active(mask)
+        e = {"mlups": round(act * steps / wall / 1e6, 1), "iop_gauge": ob["iop_gauge"]}
+        if ref is None:
+            ref = (ob["iop_gauge"], ux[on], uy[on])
+        else:
+            du = np.sqrt(np.sum((ux[on] - ref[1]) ** 2 + (uy[on] - ref[2]) ** 2))
+            e["velocity_l2_rel"] = float(du / np.sqrt(np.sum(ref[1] ** 2 + ref[2] ** 2)))
+            e["iop_rel"] = abs(ob["iop_gauge"] - ref[0]) / abs(ref[0])
+        out[st] = e
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,13 +256,16 @@ def main():
     ap.add_argument("--tile", default="64x4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the f32 / f16s storages and the lumped-outlet variant of the workload")
+                    help="skip the other storages, the lumped-outlet and paper-boundary variants of the "
+                         "workload, the dense 8192x4096 box and the 8192x4096 precision sweep")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-requests", type=int, default=16)
     ap.add_argument("--probe", action="store_true",
                     help="for hardware-counter runs: 10 launches of the plain step kernel of the workload "
                          "(two-step kernel when fusion is on), then "
                          "3 device copies of 256 MiB (a copy kernel of known size for calibration)")
+    ap.add_argument("--batch-sweep", action="store_true",
+                    help="only the 512-instance batched sweep (FP32 and F16S storage); one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
@@ -184,6 +280,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     tx, ty = (int(v) for v in args.tile.split("x"))
+    if args.batch_sweep:
+        print(json.dumps({"batch_sweep": batch_sweep()}), flush=True)
+        return
     if args.probe:
         p, mask, walls, geo = A.sweep_instance(args.seed, args.nx, args.ny, storage=STORAGES[args.storage])
         s = aq.Solver(p, mask, walls)
@@ -298,7 +397,10 @@ def main():
         # extrapolated inlet / outlet and thermal walls)
         e = run(args.storage, args.steps, args.warmup, bc=1)
         out["paper_boundaries"] = {**brief(e), "iop_gauge": e["obs"]["iop_gauge"]}
+        out["dense_box"] = dense_box(("f64", "f32", "f16s"))
+        out["precision_sweep"] = precision_sweep()
     if not args.no_batched:
+        out["batch_sweep"] = batch_sweep()
         out["batched"] = batched_vs_one_at_a_time(args.batched_requests)
         out["calibration"] = calibration_workload()
     if not args.no_cpu_baseline:

@@ -204,8 +204,10 @@ int aq_required_bytes(const aq_params* params, const uint8_t* mask, size_t* byte
 
 /* Create a solver.  mask: ny*nx bytes; walls: n_walls entries (may be NULL if 0).  The
  * state starts as the equilibrium of (p_init, u = 0, T_init).  Errors: AQ_EINVAL for
- * tau <= 1/2, nx or ny < 4, an active node on the outer frame, unknown storage, an odd or
- * < 2 check_interval, K <= 0, or an invalid wall list; AQ_ENOMEM; AQ_EDEVICE. */
+ * tau <= 1/2, nx or ny < 4, more than 2^30 nodes or, in F32 storage, a population plane
+ * beyond 4 GiB (ny x nx rounded up to 64 columns, times 4 bytes), an active node on the
+ * outer frame, unknown storage, an odd or < 2 check_interval, K <= 0, or an invalid wall
+ * list; AQ_ENOMEM; AQ_EDEVICE. */
 int aq_create(const aq_params* params, const uint8_t* mask, const aq_wall_node* walls,
               int32_t n_walls, aq_solver** out);
 

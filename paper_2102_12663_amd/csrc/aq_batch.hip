@@ -124,7 +124,7 @@ struct aq_batch {
     size_t budget = 0;
     char* arena = nullptr;
     Pool pool;
-    int max_slots = 0, max_tiles = 0, grid = 2048, interval = 0;
+    int max_slots = 0, max_tiles = 0, interval = 0;
     int64_t max_active = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -147,6 +147,7 @@ struct aq_batch {
 
     int nt_store = 0;               // non-temporal stores for the current working set
     int graph_mask = -1;
+    int graph_items[2 * NKIND] = {};   // work-list lengths the captured launches were sized for
     hipGraph_t graph_src = nullptr;
     hipGraphExec_t graph = nullptr;
 };
@@ -205,14 +206,20 @@ void drop_graph(aq_batch* b)
     b->graph = nullptr;
     b->graph_src = nullptr;
     b->graph_mask = -1;
+    std::fill(b->graph_items, b->graph_items + 2 * NKIND, 0);
 }
 
 // One check interval for every storage mode present: interval-1 plain steps, the
-// reducing step, and the per-instance finishing sums.
+// reducing step, and the per-instance finishing sums.  Every launch has one block per work
+// item (the hardware dispatcher then balances uneven tiles across the chip), so the graph
+// is captured again whenever admissions or retirements change a work list's length.
 int ensure_graph(aq_batch* b)
 {
     const int mask = active_mask(b);
-    if (b->graph && b->graph_mask == mask) return AQ_OK;
+    bool same = b->graph && b->graph_mask == mask;
+    for (int m = 0; m < NKIND && same; m++)
+        same = b->graph_items[m] == b->n_work[m] && b->graph_items[NKIND + m] == b->n_work2[m];
+    if (same) return AQ_OK;
     drop_graph(b);
     HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
@@ -225,10 +232,10 @@ int ensure_graph(aq_batch* b)
         const int F = b->fuse[m] ? (plain / 2) & ~1 : 0;
         int parity = 0;
         for (int j = 0; j < F && err == hipSuccess; j++, parity ^= 1)
-            err = launch_batch_step2(m % 3, batch_args(b, m, parity), b->grid, b->stream);
+            err = launch_batch_step2(m % 3, batch_args(b, m, parity), b->n_work2[m], b->stream);
         for (int j = 2 * F; j < plain && err == hipSuccess; j++, parity ^= 1)
-            err = launch_batch_step(m % 3, false, batch_args(b, m, parity), b->grid, b->stream);
-        if (err == hipSuccess) err = launch_batch_step(m % 3, true, batch_args(b, m, parity), b->grid, b->stream);
+            err = launch_batch_step(m % 3, false, batch_args(b, m, parity), b->n_work[m], b->stream);
+        if (err == hipSuccess) err = launch_batch_step(m % 3, true, batch_args(b, m, parity), b->n_work[m], b->stream);
     }
     for (int m = 0; m < NKIND && err == hipSuccess; m++)
         if (mask & (1 << m)) err = launch_batch_finish(batch_args(b, m, 0), b->stream);
@@ -247,6 +254,8 @@ int ensure_graph(aq_batch* b)
     b->graph_src = g;
     b->graph = ge;
     b->graph_mask = mask;
+    std::copy(b->n_work, b->n_work + NKIND, b->graph_items);
+    std::copy(b->n_work2, b->n_work2 + NKIND, b->graph_items + NKIND);
     return AQ_OK;
 }
 

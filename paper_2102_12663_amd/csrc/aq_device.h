@@ -25,8 +25,8 @@ enum {
 constexpr int NPOP = 13;    // 8 flow (q = 1..8) + 5 thermal (q = 0..4)
 constexpr int OBS_RING = 64;
 
-// Kernel arguments, passed by value.  Physical constants are double and converted to the
-// compute precision inside the kernel.
+// Kernel arguments, passed by value.  Physical constants are double, with single-precision
+// copies for the storages that compute in FP32.
 struct StepArgs {
     const void* src;          // 13 population arrays, qs elements apart
     void* dst;
@@ -47,6 +47,11 @@ struct StepArgs {
     double dp_out;            // p_out - p_ref
     double tw_cornea, tw_iris, tw_inlet;   // T_w - T_ref
     double sf, inv_sf, st, inv_st;         // F16S scales (flow, thermal)
+    // The constants the step uses, rounded to single precision once on the host (the same
+    // rounding a conversion in the kernel would give): the FP32-compute storages read
+    // these, so no thread converts a double constant.
+    float omega_f32, omega_t32, w0T32, wT32, inv_cs2T32, nuK32, drag_den32, bx32, by32, dT032, T_ref32;
+    float sf32, inv_sf32, st32, inv_st32;
 
     // lumped meshwork outlet: OUTLET links are walls moving at the seepage speed *useep
     // along the node's outward direction; the finish kernel re-evaluates it at check steps

@@ -64,6 +64,12 @@ template <> struct Traits<2> {   // AQ_F16S: binary16 of (deviation * 2^s)
     __device__ static Acc dec(S s, R inv) { return (R)s * inv; }
 };
 
+// A step constant in the compute type: the double itself, or its single-precision copy
+// (rounded on the host), so that FP32 compute converts no constant per node.
+template <typename R> __device__ __forceinline__ R cst(double d, float f);
+template <> __device__ __forceinline__ double cst<double>(double d, float) { return d; }
+template <> __device__ __forceinline__ float cst<float>(double, float f) { return f; }
+
 template <typename R> struct Node {
     R h[9];   // h[1..8] flow (h[0] unused)
     R g[5];   // g[0..4] thermal
@@ -100,6 +106,38 @@ __device__ __forceinline__ Moments<R> moments(const Node<R>& n)
     return m;
 }
 
+// ------------------------------------------------------------------------------ addressing
+// Element at byte offset `kb` from `p + off` elements, where p + off is the same for every
+// thread of the block (a plane base shifted by a link): the base goes through a scalar
+// register, so a load or store takes it with the 32-bit per-node offset as its offset
+// operand and no thread does 64-bit address arithmetic.  The offsets stay below 4 GiB: the
+// node-type bytes (at most 2^30 nodes) and the F32 and F16S population planes (checked at
+// creation).
+__device__ __forceinline__ const char* uniform_base(const void* p)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const unsigned long long b = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    typedef const __attribute__((address_space(1))) char GlobalChar;
+    return (const char*)(GlobalChar*)(((unsigned long long)hi << 32) | lo);
+#else
+    return (const char*)p;
+#endif
+}
+
+template <typename S>
+__device__ __forceinline__ const S* at(const S* p, long long off, unsigned kb)
+{
+    return (const S*)(uniform_base(p + off) + kb);
+}
+
+template <typename S>
+__device__ __forceinline__ S* at(S* p, long long off, unsigned kb)
+{
+    return (S*)(const_cast<char*>(uniform_base(p + off)) + kb);
+}
+
 // ------------------------------------------------------------------------------ pull
 // All 13 loads are issued without intervening branches: a boundary node first reads its
 // 8 neighbours' type bytes, each load address is then selected (upstream slot, or the
@@ -112,28 +150,43 @@ __device__ __forceinline__ void pull_types(const StepArgs& a, int k, bool bounda
 {
     if (boundary) {
 #pragma unroll
-        for (int i = 1; i <= 8; i++) nt[i] = a.type[k - EY[i] * a.pitch - EX[i]];
+        for (int i = 1; i <= 8; i++) nt[i] = *at(a.type, -(EY[i] * a.pitch + EX[i]), (unsigned)k);
     } else {
 #pragma unroll
         for (int i = 1; i <= 8; i++) nt[i] = FLUID;
     }
 }
 
-// (2) The 13 loads: upstream slot, or the own opposite slot for a link into a non-active node.
+// (2) The 13 loads: upstream slot, or the own opposite slot for a link into a non-active
+// node.  In the FP32-compute storages an interior node (all neighbours active) pulls every
+// link from upstream with one addressing form: a plane base shifted by the link (uniform,
+// scalar arithmetic) plus the node's own byte offset, the same for all 13 loads; that
+// saves the integer work of the compute-bound formats.  FP64 keeps one 64-bit address per
+// load (measured: the split costs the bandwidth-bound FP64 kernels about 1%).
 template <int MODE>
 __device__ __forceinline__ void pull_loads(const StepArgs& a, const typename Traits<MODE>::S* src, int k,
-                                           const uint8_t* nt, Node<typename Traits<MODE>::R>& n)
+                                           bool boundary, const uint8_t* nt, Node<typename Traits<MODE>::R>& n)
 {
     using T = Traits<MODE>;
     using R = typename T::R;
-    const R inv_f = R(a.inv_sf), inv_t = R(a.inv_st);
+    using S = typename T::S;
+    const R inv_f = cst<R>(a.inv_sf, a.inv_sf32), inv_t = cst<R>(a.inv_st, a.inv_st32);
+    const unsigned kb = (unsigned)k * (unsigned)sizeof(S);
+    if (MODE != 0 && !boundary) {
+#pragma unroll
+        for (int i = 1; i <= 8; i++) n.h[i] = T::ld(at(src, (i - 1) * a.qs - (EY[i] * a.pitch + EX[i]), kb), inv_f);
+        n.g[0] = T::ld(at(src, 8 * a.qs, kb), inv_t);
+#pragma unroll
+        for (int i = 1; i <= 4; i++) n.g[i] = T::ld(at(src, (8 + i) * a.qs - (EY[i] * a.pitch + EX[i]), kb), inv_t);
+        return;
+    }
 #pragma unroll
     for (int i = 1; i <= 8; i++) {
         const long long off = is_active(nt[i]) ? (long long)(i - 1) * a.qs + (k - EY[i] * a.pitch - EX[i])
                                                : (long long)(OPP[i] - 1) * a.qs + k;
         n.h[i] = T::ld(src + off, inv_f);
     }
-    const typename T::S* tsrc = src + 8LL * a.qs;
+    const S* tsrc = src + 8LL * a.qs;
     n.g[0] = T::ld(tsrc + k, inv_t);
 #pragma unroll
     for (int i = 1; i <= 4; i++) {
@@ -167,7 +220,7 @@ template <typename R>
 __device__ __forceinline__ R geq_dev(const StepArgs& a, int i, R th, R T_abs, R ux, R uy)
 {
     const R eu = R(EX[i]) * ux + R(EY[i]) * uy;
-    return R(a.wT) * (th + T_abs * eu * R(a.inv_cs2T));
+    return cst<R>(a.wT, a.wT32) * (th + T_abs * eu * cst<R>(a.inv_cs2T, a.inv_cs2T32));
 }
 
 // Does node (type t, neighbour types nt) have a link that the paper's extrapolation
@@ -216,7 +269,7 @@ __device__ __forceinline__ void extrapolate_links(const StepArgs& a, const uint8
         if (c == INLET) n.qin += n.h[i] - v;
         else n.qout += v - n.h[i];
     }
-    const R T_abs = R(a.T_ref) + ms.th;
+    const R T_abs = cst<R>(a.T_ref, a.T_ref32) + ms.th;
 #pragma unroll
     for (int i = 1; i <= 4; i++) {
         if (is_active(nt[i])) continue;
@@ -225,7 +278,7 @@ __device__ __forceinline__ void extrapolate_links(const StepArgs& a, const uint8
         if (!(c == INLET || (c == SOLID && wall != WALL_BOX))) continue;
         const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
         const R uxb = c == INLET ? R(a.uin_x) : R(0), uyb = c == INLET ? R(a.uin_y) : R(0);
-        n.g[i] = geq_dev(a, i, R(tw), R(a.T_ref) + R(tw), uxb, uyb) + (own.g[i] - geq_dev(a, i, ms.th, T_abs, ms.ux, ms.uy));
+        n.g[i] = geq_dev(a, i, R(tw), cst<R>(a.T_ref, a.T_ref32) + R(tw), uxb, uyb) + (own.g[i] - geq_dev(a, i, ms.th, T_abs, ms.ux, ms.uy));
     }
 }
 
@@ -273,7 +326,7 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Tra
             }
         } else if (BC && w >= 0) {                             // SOLID on the wall list
             const double q = wall_fraction(a, w, i);
-            const R inv_f = R(a.inv_sf);
+            const R inv_f = cst<R>(a.inv_sf, a.inv_sf32);
             if (q >= 0.5) {
                 n.h[i] = bouzidi(R(q), v, T::ld(src + (long long)(i - 1) * a.qs + k, inv_f), R(0));
             } else if (q > 0.0 && is_active(nt[OPP[i]])) {
@@ -289,14 +342,14 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Tra
         const uint8_t wall = (nt[i] >> WALL_SHIFT) & 3;
         if (c == INLET || (c == SOLID && wall != WALL_BOX)) {  // Dirichlet anti-bounce-back
             const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
-            n.g[i] = -n.g[i] + R(2.0) * R(a.wT) * R(tw);
+            n.g[i] = -n.g[i] + R(2.0) * cst<R>(a.wT, a.wT32) * R(tw);
         }                                                      // else adiabatic bounce-back
     }
     if constexpr (BC) {
         if (!extra) return;
         // the node's own post-collision populations and their moments
         Node<R> own;
-        const R inv_f = R(a.inv_sf), inv_t = R(a.inv_st);
+        const R inv_f = cst<R>(a.inv_sf, a.inv_sf32), inv_t = cst<R>(a.inv_st, a.inv_st32);
 #pragma unroll
         for (int i = 1; i <= 8; i++) own.h[i] = T::ld(src + (long long)(i - 1) * a.qs + k, inv_f);
 #pragma unroll
@@ -311,8 +364,9 @@ __device__ __forceinline__ void pull_all(const StepArgs& a, const typename Trait
                                          Node<typename Traits<MODE>::R>& n)
 {
     uint8_t nt[9];
-    pull_types(a, k, (t & F_BOUNDARY) != 0, nt);
-    pull_loads<MODE>(a, src, k, nt, n);
+    const bool boundary = (t & F_BOUNDARY) != 0;
+    pull_types(a, k, boundary, nt);
+    pull_loads<MODE>(a, src, k, boundary, nt, n);
     pull_rules<MODE, BC>(a, src, k, t, nt, n);
 }
 
@@ -321,13 +375,13 @@ template <typename R>
 __device__ __forceinline__ void collide(const StepArgs& a, bool porous, const Node<R>& n,
                                         const Moments<R>& m, R* hs, R* gs)
 {
-    const R om = R(a.omega_f), omc = R(1) - om;
+    const R om = cst<R>(a.omega_f, a.omega_f32), omc = R(1) - om;
     // buoyancy, eq. 15-16
-    const R tm = m.th + R(a.dT0);              // T - T0
-    const R Bx = R(a.bx) * tm, By = R(a.by) * tm;
+    const R tm = m.th + cst<R>(a.dT0, a.dT032);              // T - T0
+    const R Bx = cst<R>(a.bx, a.bx32) * tm, By = cst<R>(a.by, a.by32) * tm;
     R Dx = R(0), Dy = R(0);
     if (porous) {                              // Darcy drag on the mid-step velocity, eq. 4
-        const R dd = R(a.drag_den), nk = R(a.nuK);
+        const R dd = cst<R>(a.drag_den, a.drag_den32), nk = cst<R>(a.nuK, a.nuK32);
         Dx = -nk * ((m.ux + R(0.5) * Bx) * dd);
         Dy = -nk * ((m.uy + R(0.5) * By) * dd);
     }
@@ -378,10 +432,10 @@ __device__ __forceinline__ void collide(const StepArgs& a, bool porous, const No
         hs[8] = fma(omc, n.h[8], fma(om, heq, (d12 * (Dx - Dy))));
     }
     // eq. 11-12: thermal relaxation toward w_i [(T - T_ref) + T e_i.u / c_sT^2]
-    const R omT = R(a.omega_t), omTc = R(1) - omT;
-    const R T = R(a.T_ref) + m.th;
-    const R wT = R(a.wT), k2 = R(a.inv_cs2T) * T;
-    gs[0] = fma(omTc, n.g[0], omT * (R(a.w0T) * m.th));
+    const R omT = cst<R>(a.omega_t, a.omega_t32), omTc = R(1) - omT;
+    const R T = cst<R>(a.T_ref, a.T_ref32) + m.th;
+    const R wT = cst<R>(a.wT, a.wT32), k2 = cst<R>(a.inv_cs2T, a.inv_cs2T32) * T;
+    gs[0] = fma(omTc, n.g[0], omT * (cst<R>(a.w0T, a.w0T32) * m.th));
     gs[1] = fma(omTc, n.g[1], omT * (wT * fma(k2, ux, m.th)));
     gs[2] = fma(omTc, n.g[2], omT * (wT * fma(k2, uy, m.th)));
     gs[3] = fma(omTc, n.g[3], omT * (wT * fma(-k2, ux, m.th)));
@@ -395,12 +449,22 @@ template <int MODE, bool NT>
 __device__ __forceinline__ void put_all(const StepArgs& a, typename Traits<MODE>::S* dst, int k,
                                         const typename Traits<MODE>::S* e)
 {
-    if (NT) {
+    const unsigned kb = (unsigned)k * (unsigned)sizeof(typename Traits<MODE>::S);
+    // FP64 addresses each store in 64 bits, the FP32-compute storages as the loads do
+    if (MODE == 0) {
 #pragma unroll
-        for (int i = 0; i < NPOP; i++) __builtin_nontemporal_store(e[i], dst + (long long)i * a.qs + k);
+        for (int i = 0; i < NPOP; i++) {
+            typename Traits<MODE>::S* p = dst + (long long)i * a.qs + k;
+            if (NT) __builtin_nontemporal_store(e[i], p);
+            else *p = e[i];
+        }
     } else {
 #pragma unroll
-        for (int i = 0; i < NPOP; i++) dst[(long long)i * a.qs + k] = e[i];
+        for (int i = 0; i < NPOP; i++) {
+            typename Traits<MODE>::S* p = at(dst, i * a.qs, kb);
+            if (NT) __builtin_nontemporal_store(e[i], p);
+            else *p = e[i];
+        }
     }
 }
 
@@ -411,7 +475,7 @@ __device__ __forceinline__ void store_all(const StepArgs& a, typename Traits<MOD
 {
     using T = Traits<MODE>;
     using R = typename T::R;
-    const R sf = R(a.sf), st = R(a.st);
+    const R sf = cst<R>(a.sf, a.sf32), st = cst<R>(a.st, a.st32);
     typename T::S e[NPOP];
 #pragma unroll
     for (int i = 1; i <= 8; i++) e[i - 1] = T::enc((typename T::Acc)hs[i], sf);
@@ -467,8 +531,8 @@ __device__ __forceinline__ void store_conserving(const StepArgs& a, typename Tra
         return;
     }
     typename T::S e[NPOP];
-    conserve_encode<MODE, 8>(n.h + 1, hs + 1, e, R(a.sf), R(a.inv_sf));
-    conserve_encode<MODE, 5>(n.g, gs, e + 8, R(a.st), R(a.inv_st));
+    conserve_encode<MODE, 8>(n.h + 1, hs + 1, e, cst<R>(a.sf, a.sf32), cst<R>(a.inv_sf, a.inv_sf32));
+    conserve_encode<MODE, 5>(n.g, gs, e + 8, cst<R>(a.st, a.st32), cst<R>(a.inv_st, a.inv_st32));
     put_all<MODE, NT>(a, dst, k, e);
 }
 
@@ -616,6 +680,27 @@ __device__ __forceinline__ int tile_of_block(const StepArgs& a)
     return xcd * q + min(xcd, r) + seq;
 }
 
+// Work items [w0, w1) of a batched launch over n items.  With a block per item (the
+// launch the library makes) the item follows the XCD-aware order of tile_of_block, so
+// neighbouring tiles of an instance share an L2; a smaller grid takes contiguous runs.
+__device__ __forceinline__ void batch_items(int n, int& w0, int& w1)
+{
+    const int G = gridDim.x, b = blockIdx.x;
+    if (G >= n) {
+        int w = b;
+        if (G >= 8) {
+            const int xcd = b & 7, seq = b >> 3, q = G >> 3, r = G & 7;
+            w = xcd * q + min(xcd, r) + seq;
+        }
+        w0 = w;
+        w1 = min(n, w + 1);
+        return;
+    }
+    const int per = (n + G - 1) / G;
+    w0 = b * per;
+    w1 = min(n, w0 + per);
+}
+
 // One tile of one time step: pull, moments, forces, both collisions, store; on check
 // steps also this tile's partial sums (written to `partial`).
 template <int MODE, bool REDUCE, bool NT, bool BC>
@@ -628,7 +713,7 @@ __device__ __forceinline__ void process_tile(const StepArgs& a, int tile, double
     const int x = tx * a.tile_x + lx, y = ty * a.tile_y + ly;
     const bool inb = x < a.nx && y < a.ny;
     const int k = y * a.pitch + x;
-    const uint8_t t = inb ? a.type[k] : (uint8_t)0;
+    const uint8_t t = inb ? *at(a.type, 0, (unsigned)k) : (uint8_t)0;
     const bool act = is_active(t);
     if (!REDUCE && !act) return;
 
@@ -720,18 +805,16 @@ __device__ __forceinline__ int2 load_item(const int2* work, int w)
 #endif
 }
 
-// One time step of every running instance of a batch whose storage is MODE.  A fixed grid
-// walks the (slot, tile) work list, which lives in device memory with its length, so a
-// captured graph stays valid while instances are admitted and retired.  Each block takes
-// a contiguous run of work items (neighbouring tiles of one instance stay on one CU); the
-// next item is fetched while the current tile is processed, and an instance's arguments
-// are reloaded only when the slot changes.
+// One time step of every running instance of a batch in kernel class b.kind.  The grid
+// covers the (slot, tile) work list, one block per item (batch_items); the block reads its
+// instance's arguments from the device instance table.  A grid smaller than the list
+// walks contiguous runs of items instead: the next item is fetched while the current
+// tile is processed, and the arguments are reloaded only when the slot changes.
 template <int MODE, bool REDUCE, bool NT, bool BC>
 __global__ __launch_bounds__(256) void batch_step_kernel(BatchArgs b)
 {
-    const int n = *b.n_work;
-    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int w0 = blockIdx.x * per, w1 = min(n, w0 + per);
+    int w0, w1;
+    batch_items(*b.n_work, w0, w1);
     if (w0 >= w1) return;
     int2 nxt = load_item(b.work, w0);
     int cur_slot = -1;
@@ -863,7 +946,7 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
         const uint8_t wall = (nt[i] >> WALL_SHIFT) & 3;
         if (c == INLET || (c == SOLID && wall != WALL_BOX)) {
             const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
-            n.g[i] = -n.g[i] + R(2.0) * R(a.wT) * R(tw);
+            n.g[i] = -n.g[i] + R(2.0) * cst<R>(a.wT, a.wT32) * R(tw);
         }
     }
     if constexpr (BC) {
@@ -890,12 +973,12 @@ __device__ __forceinline__ void encode_decoded(const StepArgs& a, const Node<typ
     using R = typename T::R;
     if (MODE == 0) {
 #pragma unroll
-        for (int i = 1; i <= 8; i++) e[i - 1] = T::enc((typename T::Acc)hs[i], R(a.sf));
+        for (int i = 1; i <= 8; i++) e[i - 1] = T::enc((typename T::Acc)hs[i], cst<R>(a.sf, a.sf32));
 #pragma unroll
-        for (int i = 0; i <= 4; i++) e[8 + i] = T::enc((typename T::Acc)gs[i], R(a.st));
+        for (int i = 0; i <= 4; i++) e[8 + i] = T::enc((typename T::Acc)gs[i], cst<R>(a.st, a.st32));
     } else {
-        conserve_encode<MODE, 8>(n.h + 1, hs + 1, e, R(a.sf), R(a.inv_sf));
-        conserve_encode<MODE, 5>(n.g, gs, e + 8, R(a.st), R(a.inv_st));
+        conserve_encode<MODE, 8>(n.h + 1, hs + 1, e, cst<R>(a.sf, a.sf32), cst<R>(a.inv_sf, a.inv_sf32));
+        conserve_encode<MODE, 5>(n.g, gs, e + 8, cst<R>(a.st, a.st32), cst<R>(a.inv_st, a.inv_st32));
     }
 }
 
@@ -914,10 +997,10 @@ __device__ __forceinline__ void step_a_store(const StepArgs& a, const Node<typen
     typename T::S enc[NPOP];
     encode_decoded<MODE>(a, n, hs, gs, enc);
 #pragma unroll
-    for (int q = 0; q < 8; q++) lds[lds_at<MODE>(q, ey, ex)] = T::ldv(enc[q], R(a.inv_sf));
+    for (int q = 0; q < 8; q++) lds[lds_at<MODE>(q, ey, ex)] = T::ldv(enc[q], cst<R>(a.inv_sf, a.inv_sf32));
 #pragma unroll
-    for (int i = 1; i <= 4; i++) lds[lds_at<MODE>(7 + i, ey, ex)] = T::ldv(enc[8 + i], R(a.inv_st));
-    if (ex >= 1 && ex <= 64 && ey >= 1 && ey <= F::TY) lds[lds_g0<MODE>(ey, ex)] = T::ldv(enc[8], R(a.inv_st));
+    for (int i = 1; i <= 4; i++) lds[lds_at<MODE>(7 + i, ey, ex)] = T::ldv(enc[8 + i], cst<R>(a.inv_st, a.inv_st32));
+    if (ex >= 1 && ex <= 64 && ey >= 1 && ey <= F::TY) lds[lds_g0<MODE>(ey, ex)] = T::ldv(enc[8], cst<R>(a.inv_st, a.inv_st32));
 }
 
 // PF: step A issues the loads of all of a thread's nodes before computing any (more bytes
@@ -944,7 +1027,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
             const int x = x0 - 1 + ex, y = y0 - 1 + ey;
             const bool in = e < F::EN && x >= 0 && y >= 0 && x < a.nx && y < a.ny;
             kA[j] = in ? y * a.pitch + x : 0;
-            tA[j] = in ? a.type[kA[j]] : (uint8_t)0;   // 0 = SOLID: not active
+            tA[j] = in ? *at(a.type, 0, (unsigned)kA[j]) : (uint8_t)0;   // 0 = SOLID: not active
         }
         Node<R> nA[F::NA];
         uint8_t ntA[F::NA][9];
@@ -952,7 +1035,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
         for (int j = 0; j < F::NA; j++) pull_types(a, kA[j], is_active(tA[j]) && (tA[j] & F_BOUNDARY), ntA[j]);
 #pragma unroll
         for (int j = 0; j < F::NA; j++)
-            if (is_active(tA[j])) pull_loads<MODE>(a, src, kA[j], ntA[j], nA[j]);
+            if (is_active(tA[j])) pull_loads<MODE>(a, src, kA[j], (tA[j] & F_BOUNDARY) != 0, ntA[j], nA[j]);
 #pragma unroll
         for (int j = 0; j < F::NA; j++) pull_rules<MODE, BC>(a, src, kA[j], tA[j], ntA[j], nA[j]);
 #pragma unroll
@@ -967,7 +1050,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
             const int x = x0 - 1 + ex, y = y0 - 1 + ey;
             if (x < 0 || y < 0 || x >= a.nx || y >= a.ny) continue;
             const int k = y * a.pitch + x;
-            const uint8_t t = a.type[k];
+            const uint8_t t = *at(a.type, 0, (unsigned)k);
             if (!is_active(t)) continue;
             Node<R> n;
             pull_all<MODE, BC>(a, src, k, t, n);
@@ -982,7 +1065,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
         const int x = x0 + lx, y = y0 + ly;
         if (x >= a.nx || y >= a.ny) continue;
         const int k = y * a.pitch + x;
-        const uint8_t t = a.type[k];
+        const uint8_t t = *at(a.type, 0, (unsigned)k);
         if (!is_active(t)) continue;
         Node<R> n;
         pull_lds<MODE, BC>(a, lds, k, lx + 1, ly + 1, t, n);
@@ -1031,15 +1114,14 @@ hipError_t launch_step2(int mode, const StepArgs& a, hipStream_t s)
 
 int fused_tile_rows(int mode) { return mode == 0 ? Fuse<0>::TY : mode == 1 ? Fuse<1>::TY : Fuse<2>::TY; }
 
-// Two time steps of every running instance of a batch whose storage is MODE (fused tile
-// work list; same walk, prefetch and descriptor caching as batch_step_kernel).
+// Two time steps of every running instance of a batch in kernel class b.kind (fused tile
+// work list; the same item assignment and argument loads as batch_step_kernel).
 template <int MODE, bool NT, bool BC>
 __global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void batch_step2_kernel(BatchArgs b)
 {
     __shared__ typename Traits<MODE>::R lds[Fuse<MODE>::WORDS];
-    const int n = *b.n_work2;
-    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int w0 = blockIdx.x * per, w1 = min(n, w0 + per);
+    int w0, w1;
+    batch_items(*b.n_work2, w0, w1);
     if (w0 >= w1) return;
     int2 nxt = load_item(b.work2, w0);
     int cur_slot = -1;
@@ -1061,12 +1143,18 @@ __global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void batch_step2_kernel(Bat
     }
 }
 
+template <int MODE, bool NT, bool BC>
+static hipError_t launch_batch2_k(const BatchArgs& b, int grid, hipStream_t s)
+{
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((batch_step2_kernel<MODE, NT, BC>), dim3(grid), dim3(Fuse<MODE>::THREADS), 0, s, b);
+    return hipGetLastError();
+}
+
 template <int MODE, bool NT>
 static hipError_t launch_batch2_t(const BatchArgs& b, int grid, hipStream_t s)
 {
-    if (b.bc) hipLaunchKernelGGL((batch_step2_kernel<MODE, NT, true>), dim3(grid), dim3(Fuse<MODE>::THREADS), 0, s, b);
-    else hipLaunchKernelGGL((batch_step2_kernel<MODE, NT, false>), dim3(grid), dim3(Fuse<MODE>::THREADS), 0, s, b);
-    return hipGetLastError();
+    return b.bc ? launch_batch2_k<MODE, NT, true>(b, grid, s) : launch_batch2_k<MODE, NT, false>(b, grid, s);
 }
 
 hipError_t launch_batch_step2(int mode, const BatchArgs& b, int grid, hipStream_t s)
@@ -1240,14 +1328,19 @@ hipError_t launch_step(int mode, bool reduce, const StepArgs& a, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
+template <int MODE, bool REDUCE, bool NT, bool BC>
+static hipError_t launch_batch_k(const BatchArgs& b, int grid, hipStream_t s)
+{
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((batch_step_kernel<MODE, REDUCE, NT, BC>), dim3(grid), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
 template <int MODE, bool NT>
 static hipError_t launch_batch_t(bool reduce, const BatchArgs& b, int grid, hipStream_t s)
 {
-    if (reduce && b.bc) hipLaunchKernelGGL((batch_step_kernel<MODE, true, NT, true>), dim3(grid), dim3(256), 0, s, b);
-    else if (reduce) hipLaunchKernelGGL((batch_step_kernel<MODE, true, NT, false>), dim3(grid), dim3(256), 0, s, b);
-    else if (b.bc) hipLaunchKernelGGL((batch_step_kernel<MODE, false, NT, true>), dim3(grid), dim3(256), 0, s, b);
-    else hipLaunchKernelGGL((batch_step_kernel<MODE, false, NT, false>), dim3(grid), dim3(256), 0, s, b);
-    return hipGetLastError();
+    if (reduce) return b.bc ? launch_batch_k<MODE, true, NT, true>(b, grid, s) : launch_batch_k<MODE, true, NT, false>(b, grid, s);
+    return b.bc ? launch_batch_k<MODE, false, NT, true>(b, grid, s) : launch_batch_k<MODE, false, NT, false>(b, grid, s);
 }
 
 hipError_t launch_batch_step(int mode, bool reduce, const BatchArgs& b, int grid, hipStream_t s)

@@ -62,6 +62,21 @@ StepArgs make_args(const aq_solver* s, bool a_is_src)
     a.inv_sf = 1.0 / s->sf;
     a.st = s->st;
     a.inv_st = 1.0 / s->st;
+    a.omega_f32 = (float)a.omega_f;
+    a.omega_t32 = (float)a.omega_t;
+    a.w0T32 = (float)a.w0T;
+    a.wT32 = (float)a.wT;
+    a.inv_cs2T32 = (float)a.inv_cs2T;
+    a.nuK32 = (float)a.nuK;
+    a.drag_den32 = (float)a.drag_den;
+    a.bx32 = (float)a.bx;
+    a.by32 = (float)a.by;
+    a.dT032 = (float)a.dT0;
+    a.T_ref32 = (float)a.T_ref;
+    a.sf32 = (float)a.sf;
+    a.inv_sf32 = (float)a.inv_sf;
+    a.st32 = (float)a.st;
+    a.inv_st32 = (float)a.inv_st;
     char* b = s->base;
     a.partials = (double*)(b + s->L.off_partials);
     a.obs_count = (unsigned int*)(b + s->L.off_counters + 64);
@@ -153,6 +168,12 @@ int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls,
     if (P->nx < 4 || P->ny < 4) return fail(AQ_EINVAL, "nx and ny must be >= 4");
     if ((long long)P->nx * P->ny > (1LL << 30)) return fail(AQ_EINVAL, "lattice too large");
     if (!(P->tau_f > 0.5) || !(P->tau_t > 0.5)) return fail(AQ_EINVAL, "tau_f and tau_t must exceed 1/2");
+    if (P->storage == AQ_F32 || P->storage == AQ_F16S) {
+        // the FP32-compute kernels address a population plane with 32-bit byte offsets
+        const long long elem = P->storage == AQ_F32 ? 4 : 2;
+        if (make_layout(*P, 0).qs * elem > (1LL << 32))
+            return fail(AQ_EINVAL, "lattice too large for the storage: a population plane must stay within 4 GiB");
+    }
     if (!(P->w0 >= 0.0 && P->w0 < 1.0)) return fail(AQ_EINVAL, "w0 must be in [0, 1)");
     if (!(P->K > 0.0)) return fail(AQ_EINVAL, "K must be positive");
     if (P->storage < AQ_F64 || P->storage > AQ_F16S) return fail(AQ_EINVAL, "unknown storage");
