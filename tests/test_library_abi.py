@@ -115,3 +115,15 @@ def test_required_bytes(aq):
     m = C.c_size_t()
     assert aq._lib.aq_required_bytes(C.byref(ap), mask.ctypes.data, C.byref(m)) == 0
     assert m.value < n.value
+
+
+def test_f32_plane_limit(aq):
+    """F32 kernels address a population plane with 32-bit byte offsets: a lattice whose
+    padded plane (ny x nx rounded up to 64 columns, 4 bytes each) passes 4 GiB is rejected
+    in F32 storage, although it has no more than 2^30 nodes."""
+    nx, ny = 32769, 32767                      # nx * ny <= 2^30, ny * 32832 * 4 > 2^32
+    assert nx * ny <= 1 << 30
+    mask = np.zeros((ny, nx), np.uint8)        # never touched: the size check comes first
+    p = A.Params(nx=nx, ny=ny, storage=A.F32)
+    rc, err = _create(aq, p, mask)
+    assert rc == aq.AQ_EINVAL and "4 GiB" in err
