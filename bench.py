@@ -102,7 +102,8 @@ def batched_vs_one_at_a_time(n, cap=200000, tol=1e-6):
 def batch_sweep(n=512, intervals=10, storages=("f32", "f16s")):
     """The batched parameter sweep: n instances of the sweep distribution (lattices
     256x128 .. 1024x512, per-instance tau, Da, inflow, angle, Ra, gravity orientation) resident
-    in one batch and stepped together, per storage.  Aggregate active-node MLUPS over
+    in one batch and stepped together, per storage, with the single-step tile of each size
+    class from the autotuner (two-step launches use the fixed 64x8 tiles).  Aggregate active-node MLUPS over
     `intervals` check intervals (after two warm-up intervals; residual target 1e-30 so no
     instance retires) and its fraction of the HBM roofline for the algorithmic bytes."""
     import torch
@@ -114,10 +115,14 @@ def batch_sweep(n=512, intervals=10, storages=("f32", "f16s")):
     out = {"workload": f"{n} sweep requests (seeds 0..{n - 1}), {act} active nodes, "
                        f"{intervals} check intervals of 100 time steps"}
     for st in storages:
+        cache = S.ShapeCache()
+        shapes = set()
         b = aq.Batch(budget_bytes=96 << 30, max_slots=n, max_tiles=1 << 21)
         for p, m, w in reqs:
-            b.admit(A.Params(**{**p.asdict(), "storage": STORAGES[st]}), m, w, tile=(64, 4), tol=1e-30,
-                    max_steps=10 ** 9)
+            p = A.Params(**{**p.asdict(), "storage": STORAGES[st]})
+            tile = S.autotune_shape(cache, p, m, w)       # single-step tile of the size class
+            shapes.add((p.nx, p.ny, tile))
+            b.admit(p, m, w, tile=tile, tol=1e-30, max_steps=10 ** 9)
         b.run(2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -129,7 +134,8 @@ def batch_sweep(n=512, intervals=10, storages=("f32", "f16s")):
         mlups = act * intervals * 100 / wall / 1e6
         bpu = {"f64": 209, "f32": 105, "f16s": 53}[st]
         out[st] = {"mlups": round(mlups, 1), "achieved_GBs": round(mlups * bpu / 1e3, 1),
-                   "frac": round(mlups * bpu / 1e3 / HBM_PEAK_GBS, 4), "running_after": info["running"]}
+                   "frac": round(mlups * bpu / 1e3 / HBM_PEAK_GBS, 4), "running_after": info["running"],
+                   "tiles": {f"{x}x{y}": f"{t[0]}x{t[1]}" for x, y, t in sorted(shapes)}}
     return out
 
 

@@ -499,23 +499,26 @@ __device__ __forceinline__ void conserve_encode(const typename Traits<MODE>::R* 
 {
     using T = Traits<MODE>;
     using Acc = typename T::Acc;
-    Acc target = 0, sum = 0, amin = 0;
+    using R = typename T::R;
+    Acc target = 0, sum = 0;
+    R amin = 0, dmin = 0;
     int kmin = 0;
 #pragma unroll
     for (int i = 0; i < N; i++) {
         target += (Acc)in[i];
         enc[i] = T::enc((Acc)out[i], sc);
-        const Acc d = T::dec(enc[i], inv);
-        sum += d;
-        if (i == 0 || fabs(d) < amin) {
-            amin = fabs(d);
-            kmin = i;
-        }
+        // the decoded value is exact in the compute type, so the search runs there
+        const R d = T::ldv(enc[i], inv);
+        sum += (Acc)d;
+        const bool lower = i == 0 || fabs(d) < amin;   // selects, not branches
+        amin = lower ? fabs(d) : amin;
+        dmin = lower ? d : dmin;
+        kmin = lower ? i : kmin;
     }
-    const Acc r = target - sum;
+    // the corrected value replaces the one at kmin (whose decoded value is dmin)
+    const typename T::S c = T::enc((Acc)dmin + (target - sum), sc);
 #pragma unroll
-    for (int i = 0; i < N; i++)
-        if (i == kmin) enc[i] = T::enc(T::dec(enc[i], inv) + r, sc);
+    for (int i = 0; i < N; i++) enc[i] = i == kmin ? c : enc[i];
 }
 
 template <int MODE, bool NT>
