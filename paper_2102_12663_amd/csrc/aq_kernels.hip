@@ -683,25 +683,61 @@ __device__ __forceinline__ int tile_of_block(const StepArgs& a)
     return xcd * q + min(xcd, r) + seq;
 }
 
-// Work items [w0, w1) of a batched launch over n items.  With a block per item (the
-// launch the library makes) the item follows the XCD-aware order of tile_of_block, so
-// neighbouring tiles of an instance share an L2; a smaller grid takes contiguous runs.
-__device__ __forceinline__ void batch_items(int n, int& w0, int& w1)
+// The instance table and the work list do not change during a launch: read them through
+// the constant address space so they land in scalar registers (the host compilation pass
+// only needs a declaration-compatible body).
+__device__ __forceinline__ StepArgs load_desc(const InstDesc* table, int i)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) InstDesc ConstDesc;
+    return ((ConstDesc*)table)[i].a;
+#else
+    return table[i].a;
+#endif
+}
+
+__device__ __forceinline__ StepArgs load_desc2(const InstDesc* table, int i)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) InstDesc ConstDesc;
+    return ((ConstDesc*)table)[i].a2;
+#else
+    return table[i].a2;
+#endif
+}
+
+__device__ __forceinline__ int2 load_item(const int2* work, int w)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) int2 ConstItem;
+    return ((ConstItem*)work)[w];
+#else
+    return work[w];
+#endif
+}
+
+// Work item of this block in a batched launch (one block per item): the XCD-aware order of
+// tile_of_block, so neighbouring tiles of an instance share an L2.
+__device__ __forceinline__ int batch_item()
 {
     const int G = gridDim.x, b = blockIdx.x;
-    if (G >= n) {
-        int w = b;
-        if (G >= 8) {
-            const int xcd = b & 7, seq = b >> 3, q = G >> 3, r = G & 7;
-            w = xcd * q + min(xcd, r) + seq;
-        }
-        w0 = w;
-        w1 = min(n, w + 1);
-        return;
+    if (G < 8) return b;
+    const int xcd = b & 7, seq = b >> 3, q = G >> 3, r = G & 7;
+    return xcd * q + min(xcd, r) + seq;
+}
+
+// The step arguments of the instance in `slot` (its descriptor in the instance table), with
+// the buffers swapped on odd launches.
+template <bool FUSED>
+__device__ __forceinline__ StepArgs batch_desc(const BatchArgs& b, int slot)
+{
+    StepArgs a = FUSED ? load_desc2(b.inst, slot) : load_desc(b.inst, slot);
+    if (b.parity) {
+        void* t = (void*)a.src;
+        a.src = a.dst;
+        a.dst = t;
     }
-    const int per = (n + G - 1) / G;
-    w0 = b * per;
-    w1 = min(n, w0 + per);
+    return a;
 }
 
 // One tile of one time step: pull, moments, forces, both collisions, store; on check
@@ -775,68 +811,16 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a)
     process_tile<MODE, REDUCE, NT, BC>(a, a.tiles[ti], a.partials + (long long)ti * NRED);
 }
 
-// The instance table and the work list do not change during a launch: read them through
-// the constant address space so they land in scalar registers (the host compilation pass
-// only needs a declaration-compatible body).
-__device__ __forceinline__ StepArgs load_desc(const InstDesc* table, int i)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    typedef const __attribute__((address_space(4))) InstDesc ConstDesc;
-    return ((ConstDesc*)table)[i].a;
-#else
-    return table[i].a;
-#endif
-}
-
-__device__ __forceinline__ StepArgs load_desc2(const InstDesc* table, int i)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    typedef const __attribute__((address_space(4))) InstDesc ConstDesc;
-    return ((ConstDesc*)table)[i].a2;
-#else
-    return table[i].a2;
-#endif
-}
-
-__device__ __forceinline__ int2 load_item(const int2* work, int w)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    typedef const __attribute__((address_space(4))) int2 ConstItem;
-    return ((ConstItem*)work)[w];
-#else
-    return work[w];
-#endif
-}
-
-// One time step of every running instance of a batch in kernel class b.kind.  The grid
-// covers the (slot, tile) work list, one block per item (batch_items); the block reads its
-// instance's arguments from the device instance table.  A grid smaller than the list
-// walks contiguous runs of items instead: the next item is fetched while the current
-// tile is processed, and the arguments are reloaded only when the slot changes.
+// One time step of every running instance of a batch in kernel class b.kind: one block per
+// (slot, tile) item of the work list (the grid is the list's length); the block reads its
+// instance's arguments from the device instance table.
 template <int MODE, bool REDUCE, bool NT, bool BC>
 __global__ __launch_bounds__(256) void batch_step_kernel(BatchArgs b)
 {
-    int w0, w1;
-    batch_items(*b.n_work, w0, w1);
-    if (w0 >= w1) return;
-    int2 nxt = load_item(b.work, w0);
-    int cur_slot = -1;
-    StepArgs a;
-    for (int w = w0; w < w1; w++) {
-        const int2 it = nxt;
-        if (w + 1 < w1) nxt = load_item(b.work, w + 1);
-        if (it.x != cur_slot) {
-            a = load_desc(b.inst, it.x);
-            if (b.parity) {
-                void* t = (void*)a.src;
-                a.src = a.dst;
-                a.dst = t;
-            }
-            cur_slot = it.x;
-        }
-        process_tile<MODE, REDUCE, NT, BC>(a, it.y, b.partials + (long long)w * NRED);
-        if (REDUCE) __syncthreads();
-    }
+    const int w = batch_item();
+    if (w >= *b.n_work) return;
+    const int2 it = load_item(b.work, w);
+    process_tile<MODE, REDUCE, NT, BC>(batch_desc<false>(b, it.x), it.y, b.partials + (long long)w * NRED);
 }
 
 // Per-instance fixed-order sums of the batch's check step (one block per instance).
@@ -860,9 +844,10 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(BatchArgs b)
 template <int MODE> struct Fuse {
     static constexpr int TY = 8;                              // output rows per tile
     static constexpr int THREADS = (MODE == 0) ? 512 : 256;   // threads per block
-    // the batched kernel keeps its instance descriptor in registers; there the FP32 and
-    // F16S forms run faster one step-A node at a time
-    static constexpr bool BATCH_PF = MODE == 0;
+    // step A of the batched kernel issues all of a thread's loads first in FP64 and FP32
+    // (FP32 512-instance sweep: 60.4 against 55.9 GLUPS one node at a time); F16S runs
+    // single steps in a batch
+    static constexpr bool BATCH_PF = MODE != 2;
     static constexpr int EW = 66, EH = TY + 2;        // tile plus a one-node halo
     static constexpr int EN = EW * EH;                // step-A nodes
     static constexpr int NA = (EN + THREADS - 1) / THREADS;   // step-A nodes per thread
@@ -1123,27 +1108,11 @@ template <int MODE, bool NT, bool BC>
 __global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void batch_step2_kernel(BatchArgs b)
 {
     __shared__ typename Traits<MODE>::R lds[Fuse<MODE>::WORDS];
-    int w0, w1;
-    batch_items(*b.n_work2, w0, w1);
-    if (w0 >= w1) return;
-    int2 nxt = load_item(b.work2, w0);
-    int cur_slot = -1;
-    StepArgs a;
-    for (int w = w0; w < w1; w++) {
-        const int2 it = nxt;
-        if (w + 1 < w1) nxt = load_item(b.work2, w + 1);
-        if (it.x != cur_slot) {
-            a = load_desc2(b.inst, it.x);
-            if (b.parity) {
-                void* t = (void*)a.src;
-                a.src = a.dst;
-                a.dst = t;
-            }
-            cur_slot = it.x;
-        }
-        process_tile2<MODE, NT, Fuse<MODE>::BATCH_PF, BC>(a, it.y, lds);
-        __syncthreads();   // the next tile overwrites the LDS image
-    }
+    const int w = batch_item();
+    if (w >= *b.n_work2) return;
+    const int2 it = load_item(b.work2, w);
+    // (the FP32 paper-scheme variant would spill with all loads first)
+    process_tile2<MODE, NT, Fuse<MODE>::BATCH_PF && !(MODE == 1 && BC), BC>(batch_desc<true>(b, it.x), it.y, lds);
 }
 
 template <int MODE, bool NT, bool BC>

@@ -58,6 +58,31 @@ def test_alone_vs_in_the_mix_bitwise(aq):
     b.close()
 
 
+def test_staggered_admission_and_retirement_bitwise(aq):
+    """Work lists that grow and shrink between runs (each change re-sizes the launches):
+    an instance admitted late and one that keeps running after another retires both match
+    their solo runs bitwise."""
+    insts = _instances()
+    b = aq.Batch(budget_bytes=1 << 30, max_slots=16)
+    first = b.admit(*insts[0], tile=(64, 4), tol=1e-12, max_steps=10 ** 6, keep=True)
+    short = b.admit(*insts[3], tile=(64, 4), tol=1e-12, max_steps=200, request_id=7)
+    b.run(3)                                      # `short` retires at its step cap
+    assert [r["request_id"] for r in b.poll()] == [7]
+    late = b.admit(*insts[2], tile=(64, 4), tol=1e-12, max_steps=10 ** 6, keep=True)
+    late2 = b.admit(*insts[1], tile=(64, 4), tol=1e-12, max_steps=10 ** 6, keep=True)
+    b.run(4)
+    for sl, (p, m, w), steps in ((first, insts[0], 700), (late, insts[2], 400), (late2, insts[1], 400)):
+        announce(f"[batch] staggered {p.nx}x{p.ny} storage {p.storage} after {steps} steps")
+        alone = aq.Solver(p, m, w)
+        alone.set_tile(64, 4)
+        alone.step(steps)
+        assert _fields_equal([b.read_field(sl, f) for f in ("p", "ux", "uy", "T")],
+                             [alone.read_field(f) for f in ("p", "ux", "uy", "T")])
+        assert b.observe(sl) == alone.observe()
+        alone.close()
+    b.close()
+
+
 def test_batch_fp64_matches_oracle(aq):
     p, mask, walls, geo = A.config0()
     b = aq.Batch(budget_bytes=256 << 20, max_slots=4)
