@@ -500,6 +500,31 @@ __device__ __forceinline__ void conserve_encode(const typename Traits<MODE>::R* 
     using T = Traits<MODE>;
     using Acc = typename T::Acc;
     using R = typename T::R;
+    if constexpr (MODE == 2) {
+        // F16S: the same arithmetic in units of the stored binary16 values.  Decoding scales
+        // by a power of two, which commutes exactly with every rounding below, so comparing
+        // and summing the undecoded values gives bit for bit the same result without a
+        // multiply per value: target * sc is the sum of the in[i] * sc, and the corrected
+        // value is the binary16 of dmin + r in these units.
+        Acc target = 0, sum = 0;
+        R amin = 0, dmin = 0;
+        int kmin = 0;
+#pragma unroll
+        for (int i = 0; i < N; i++) {
+            target += in[i];
+            enc[i] = T::enc(out[i], sc);
+            const R d = (R)enc[i];
+            sum += d;
+            const bool lower = i == 0 || fabs(d) < amin;   // selects, not branches
+            amin = lower ? fabs(d) : amin;
+            dmin = lower ? d : dmin;
+            kmin = lower ? i : kmin;
+        }
+        const typename T::S c = (typename T::S)(dmin + (target * sc - sum));
+#pragma unroll
+        for (int i = 0; i < N; i++) enc[i] = i == kmin ? c : enc[i];
+        return;
+    }
     Acc target = 0, sum = 0;
     R amin = 0, dmin = 0;
     int kmin = 0;
