@@ -482,8 +482,6 @@ int aq_batch_admit(aq_batch* b, const aq_params* P, const uint8_t* mask, const a
     aq_solver* s = nullptr;
     rc = create_common(P, mask, walls, n_walls, b->arena + off, L.total, b->stream, false, &s);
     if (rc == AQ_OK) rc = aq_set_tile(s, tile_x, tile_y);
-    int tiles_now = 0;
-    for (int m = 0; m < NKIND; m++) tiles_now += b->n_work[m];
     if (rc == AQ_OK && b->max_active && running_active(b) + s->n_active > b->max_active)
         rc = fail(AQ_EBUSY, "active-node cap reached");
     if (rc == AQ_OK && b->n_work[kind_of(s)] + s->n_tiles > b->max_tiles)
