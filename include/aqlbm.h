@@ -369,7 +369,9 @@ int aq_batch_admit(aq_batch* b, const aq_params* params, const uint8_t* mask, co
                    int64_t max_steps, int64_t request_id, int32_t keep, int32_t* slot);
 
 /* Run n_intervals check intervals of every running instance, then retire the instances
- * that converged, diverged or reached max_steps (synchronises the stream). */
+ * that converged, diverged or reached max_steps (synchronises the stream).  An interval is
+ * one HIP graph with one block per work item; admissions and retirements that change the
+ * work lists make the next run capture it again. */
 int aq_batch_run(aq_batch* b, int32_t n_intervals);
 
 /* Collect up to cap finished results not yet collected; their slots and memory are freed
