@@ -270,6 +270,8 @@ def main():
                     help="for hardware-counter runs: 10 launches of the plain step kernel of the workload "
                          "(two-step kernel when fusion is on), then "
                          "3 device copies of 256 MiB (a copy kernel of known size for calibration)")
+    ap.add_argument("--probe-single", action="store_true",
+                    help="with --probe: the single-step kernel even where the solver runs two steps per launch")
     ap.add_argument("--batch-sweep", action="store_true",
                     help="only the 512-instance batched sweep (FP32 and F16S storage); one JSON line")
     args = ap.parse_args()
@@ -293,10 +295,10 @@ def main():
         p, mask, walls, geo = A.sweep_instance(args.seed, args.nx, args.ny, storage=STORAGES[args.storage])
         s = aq.Solver(p, mask, walls)
         s.set_tile(tx, ty)
-        if s.info()["fusion"]:
-            s.time_fused_kernel(10)
-        else:
+        if args.probe_single or not s.info()["fusion"]:
             s.time_step_kernel(10)
+        else:
+            s.time_fused_kernel(10)
         x = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
         y = torch.empty_like(x)
         x.fill_(1)
