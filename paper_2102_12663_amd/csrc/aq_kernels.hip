@@ -507,7 +507,7 @@ __device__ __forceinline__ void conserve_encode(const typename Traits<MODE>::R* 
         // multiply per value: target * sc is the sum of the in[i] * sc, and the corrected
         // value is the binary16 of dmin + r in these units.
         Acc target = 0, sum = 0;
-        R amin = 0, dmin = 0;
+        R dmin = 0;
         int kmin = 0;
 #pragma unroll
         for (int i = 0; i < N; i++) {
@@ -515,8 +515,7 @@ __device__ __forceinline__ void conserve_encode(const typename Traits<MODE>::R* 
             enc[i] = T::enc(out[i], sc);
             const R d = (R)enc[i];
             sum += d;
-            const bool lower = i == 0 || fabs(d) < amin;   // selects, not branches
-            amin = lower ? fabs(d) : amin;
+            const bool lower = i == 0 || fabs(d) < fabs(dmin);   // selects, not branches
             dmin = lower ? d : dmin;
             kmin = lower ? i : kmin;
         }
@@ -526,7 +525,7 @@ __device__ __forceinline__ void conserve_encode(const typename Traits<MODE>::R* 
         return;
     }
     Acc target = 0, sum = 0;
-    R amin = 0, dmin = 0;
+    R dmin = 0;
     int kmin = 0;
 #pragma unroll
     for (int i = 0; i < N; i++) {
@@ -535,8 +534,7 @@ __device__ __forceinline__ void conserve_encode(const typename Traits<MODE>::R* 
         // the decoded value is exact in the compute type, so the search runs there
         const R d = T::ldv(enc[i], inv);
         sum += (Acc)d;
-        const bool lower = i == 0 || fabs(d) < amin;   // selects, not branches
-        amin = lower ? fabs(d) : amin;
+        const bool lower = i == 0 || fabs(d) < fabs(dmin);   // selects, not branches
         dmin = lower ? d : dmin;
         kmin = lower ? i : kmin;
     }
@@ -773,7 +771,8 @@ __device__ __forceinline__ void process_tile(const StepArgs& a, int tile, double
     using T = Traits<MODE>;
     using R = typename T::R;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int lx = threadIdx.x % a.tile_x, ly = threadIdx.x / a.tile_x;
+    // tile_x is 64, 128 or 256: a mask and a shift, not a division per thread
+    const int lx = threadIdx.x & (a.tile_x - 1), ly = threadIdx.x >> __builtin_ctz((unsigned)a.tile_x);
     const int x = tx * a.tile_x + lx, y = ty * a.tile_y + ly;
     const bool inb = x < a.nx && y < a.ny;
     const int k = y * a.pitch + x;
