@@ -99,6 +99,45 @@ def batched_vs_one_at_a_time(n, cap=200000, tol=1e-6):
                                   "p99_s": round(float(np.percentile(lat, 99)), 3), "converged": int(conv)}}
 
 
+def shard_slabs(n=8, nx=8192, ny=4096, seed=0, intervals=10):
+    """The design's decomposition of one large lattice over n GPUs, measured one slab at a time
+    on this GPU: the 8192x4096 eye (sweep draw seed 0) cut along x where the cumulative active
+    node count reaches k/n of the total (a cut along y would leave the GPUs above the chamber
+    idle).  Each slab runs alone as its own lattice (its cut columns closed by a solid column,
+    FP64, the benchmark's interval); the slowest slab sets the time step of the n-GPU run, whose
+    projected throughput ignores the face exchange (4 populations per face node per step)."""
+    import numpy as np
+    import aqinputs as A
+    import paper_2102_12663_amd as aq
+    p, mask, walls, geo = A.sweep_instance(seed, nx, ny)
+    act = A.active(mask)
+    total = int(act.sum())
+    c = np.cumsum(act.sum(axis=0))
+    cuts = [0] + [int(np.searchsorted(c, total * k / n)) for k in range(1, n)] + [nx]
+    slabs = []
+    for i in range(n):
+        x0, x1 = max(cuts[i] - 1, 0), min(cuts[i + 1] + 1, nx)   # one halo column each side
+        m = np.ascontiguousarray(mask[:, x0:x1])
+        m[:, 0] = A.encode(A.SOLID)
+        m[:, -1] = A.encode(A.SOLID)
+        q = A.Params(**{**p.asdict(), "nx": x1 - x0})
+        s = aq.Solver(q, m, A.no_walls())
+        s.run_intervals_timed(1)
+        t0 = time.perf_counter()
+        s.run_intervals_timed(intervals)
+        wall = time.perf_counter() - t0
+        a = s.info()["active_nodes"]
+        s.close()
+        slabs.append({"columns": [cuts[i], cuts[i + 1]], "active_nodes": a,
+                      "ms_per_interval": round(wall * 1e3 / intervals, 4)})
+    slowest = max(e["ms_per_interval"] for e in slabs)
+    return {"workload": f"{nx}x{ny} eye (sweep draw seed {seed}, {total} active nodes) in {n} x-slabs balanced "
+                        f"by active nodes, FP64, {intervals} check intervals of 100 time steps per slab",
+            "slabs": slabs, "slowest_ms_per_interval": slowest,
+            "projected_mlups": round(total * 100 / (slowest * 1e-3) / 1e6, 1),
+            "y_slab_imbalance": round(max(int(act[k * ny // n:(k + 1) * ny // n].sum()) for k in range(n)) * n / total, 3)}
+
+
 def batch_sweep(n=512, intervals=10, storages=("f32", "f16s")):
     """The batched parameter sweep: n instances of the sweep distribution (lattices
     256x128 .. 1024x512, per-instance tau, Da, inflow, angle, Ra, gravity orientation) resident
@@ -407,6 +446,7 @@ def main():
         out["paper_boundaries"] = {**brief(e), "iop_gauge": e["obs"]["iop_gauge"]}
         out["dense_box"] = dense_box(("f64", "f32", "f16s"))
         out["precision_sweep"] = precision_sweep()
+        out["shard_slabs"] = shard_slabs()
     if not args.no_batched:
         out["batch_sweep"] = batch_sweep()
         out["batched"] = batched_vs_one_at_a_time(args.batched_requests)
