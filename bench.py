@@ -266,8 +266,9 @@ def precision_sweep(steps=20000, nx=8192, ny=4096, seed=0):
     import paper_2102_12663_amd as aq
     out = {"workload": f"{nx}x{ny} eye section (sweep draw seed {seed}), {steps} time steps per storage"}
     ref = None
+    p0, mask, walls, geo = A.sweep_instance(seed, nx, ny)
     for st in ("f64", "f32", "f16s"):
-        p, mask, walls, geo = A.sweep_instance(seed, nx, ny, storage=STORAGES[st])
+        p = A.Params(**{**p0.asdict(), "storage": STORAGES[st]})
         s = aq.Solver(p, mask, walls)
         D = s.info()["check_interval"]
         t0 = time.perf_counter()
