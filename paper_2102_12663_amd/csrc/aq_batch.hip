@@ -1,12 +1,15 @@
 // Batched serving form of the aqlbm library: many independent lattices (parameter-sweep
 // solves of uneven sizes) resident in one HBM arena and stepped together by one
-// multi-instance kernel per storage mode, with a captured HIP graph per check interval.
+// multi-instance kernel per kernel class (storage x boundary scheme), with a captured HIP
+// graph per check interval.
 //
 // - Admission checks the free arena (first-fit pool), free slots, the work-list capacity
 //   and an active-node cap; each admitted instance is an ordinary single-lattice solver
 //   carved out of the arena, so its state, fields and checkpoints behave exactly as alone.
-// - The graph reads the instance table and the (slot, tile) work lists from device
-//   memory, so admissions and retirements between intervals need no re-capture.
+// - The kernels read the instance table and the (slot, tile) work lists from device
+//   memory; each launch has one block per work item, so the graph is captured again when
+//   admissions or retirements change a list's length (not when only instance arguments
+//   change, e.g. a new meshwork thickness).
 // - After each call to aq_batch_run the latest reductions of every running instance are
 //   read back in one copy; converged, diverged and capped instances are retired.
 // - An F16S instance whose residual falls below max(tol, 2e-5), or stops falling for 50
@@ -209,7 +212,7 @@ void drop_graph(aq_batch* b)
     std::fill(b->graph_items, b->graph_items + 2 * NKIND, 0);
 }
 
-// One check interval for every storage mode present: interval-1 plain steps, the
+// One check interval for every kernel class present: interval-1 plain steps, the
 // reducing step, and the per-instance finishing sums.  Every launch has one block per work
 // item (the hardware dispatcher then balances uneven tiles across the chip), so the graph
 // is captured again whenever admissions or retirements change a work list's length.
