@@ -99,6 +99,37 @@ def batched_vs_one_at_a_time(n, cap=200000, tol=1e-6):
                                   "p99_s": round(float(np.percentile(lat, 99)), 3), "converged": int(conv)}}
 
 
+def precision_steady(cases=((512, 256, 3), (512, 256, 5), (1024, 512, 6), (2048, 1024, 3)), tol=1e-9):
+    """The reduced-precision forms against FP64 at steady states: each sweep draw runs in FP64
+    to a residual of `tol`; FP32 and F16S storage then run the same number of steps from the
+    same initial state.  Velocity L2 error relative to FP64 over active nodes, IOP relative
+    error, max |T| error and the reduced form's own final residual."""
+    import numpy as np
+    import aqinputs as A
+    import paper_2102_12663_amd as aq
+    out = []
+    for nx, ny, seed in cases:
+        p0, mask, walls, geo = A.sweep_instance(seed, nx, ny)
+        act = A.active(mask)
+        s = aq.Solver(p0, mask, walls)
+        ok, ob64 = s.run_to_steady(tol, 4_000_000)
+        f64 = s.fields()
+        s.close()
+        den = np.sqrt(np.sum(f64[1][act] ** 2 + f64[2][act] ** 2))
+        row = {"case": f"{nx}x{ny} seed {seed}", "fp64_steps": ob64["step"], "fp64_converged": bool(ok)}
+        for st in ("f32", "f16s"):
+            s = aq.Solver(A.Params(**{**p0.asdict(), "storage": STORAGES[st]}), mask, walls)
+            s.step(ob64["step"])
+            ob, f = s.observe(), s.fields()
+            s.close()
+            du = np.sqrt(np.sum((f[1][act] - f64[1][act]) ** 2 + (f[2][act] - f64[2][act]) ** 2))
+            row[st] = {"velocity_l2_rel": float(du / den),
+                       "iop_rel": abs(ob["iop_gauge"] - ob64["iop_gauge"]) / abs(ob64["iop_gauge"]),
+                       "t_max_err": float(np.max(np.abs(f[3][act] - f64[3][act]))), "resid_u": ob["resid_u"]}
+        out.append(row)
+    return out
+
+
 def shard_slabs(n=8, nx=8192, ny=4096, seed=0, intervals=10):
     """The design's decomposition of one large lattice over n GPUs, measured one slab at a time
     on this GPU: the 8192x4096 eye (sweep draw seed 0) cut along x where the cumulative active
@@ -312,6 +343,9 @@ def main():
                          "3 device copies of 256 MiB (a copy kernel of known size for calibration)")
     ap.add_argument("--probe-single", action="store_true",
                     help="with --probe: the single-step kernel even where the solver runs two steps per launch")
+    ap.add_argument("--precision-steady", action="store_true",
+                    help="only the steady-state precision comparison of FP32 and F16S against FP64 "
+                         "(four sweep draws, 512x256 to 2048x1024); one JSON line")
     ap.add_argument("--batch-sweep", action="store_true",
                     help="only the 512-instance batched sweep (FP32 and F16S storage); one JSON line")
     args = ap.parse_args()
@@ -330,6 +364,9 @@ def main():
     tx, ty = (int(v) for v in args.tile.split("x"))
     if args.batch_sweep:
         print(json.dumps({"batch_sweep": batch_sweep()}), flush=True)
+        return
+    if args.precision_steady:
+        print(json.dumps({"precision_steady": precision_steady()}), flush=True)
         return
     if args.probe:
         p, mask, walls, geo = A.sweep_instance(args.seed, args.nx, args.ny, storage=STORAGES[args.storage])
