@@ -333,7 +333,7 @@ def no_walls():
 # ----------------------------------------------------------------------------------------
 # Lattice-unit parameter sets (the workload recipe)
 # ----------------------------------------------------------------------------------------
-F64, F32, F16S = 0, 1, 2
+F64, F32, F16S, F32X = 0, 1, 2, 3
 
 
 @dataclass

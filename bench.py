@@ -19,8 +19,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (flow+thermal) & HBM-roofline %; batched solves/s + p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-STORAGES = {"f64": 0, "f32": 1, "f16s": 2}
-DTYPE = {"f64": "f64", "f32": "f32", "f16s": "f16 storage / f32 compute"}
+STORAGES = {"f64": 0, "f32": 1, "f16s": 2, "f32x": 3}
+DTYPE = {"f64": "f64", "f32": "f32", "f16s": "f16 storage / f32 compute", "f32x": "f32 storage / f64 compute"}
 
 
 def kernel_source_hash():
@@ -117,7 +117,7 @@ def precision_steady(cases=((512, 256, 3), (512, 256, 5), (1024, 512, 6), (2048,
         s.close()
         den = np.sqrt(np.sum(f64[1][act] ** 2 + f64[2][act] ** 2))
         row = {"case": f"{nx}x{ny} seed {seed}", "fp64_steps": ob64["step"], "fp64_converged": bool(ok)}
-        for st in ("f32", "f16s"):
+        for st in ("f32", "f16s", "f32x"):
             s = aq.Solver(A.Params(**{**p0.asdict(), "storage": STORAGES[st]}), mask, walls)
             s.step(ob64["step"])
             ob, f = s.observe(), s.fields()
@@ -169,7 +169,7 @@ def shard_slabs(n=8, nx=8192, ny=4096, seed=0, intervals=10):
             "y_slab_imbalance": round(max(int(act[k * ny // n:(k + 1) * ny // n].sum()) for k in range(n)) * n / total, 3)}
 
 
-def batch_sweep(n=512, intervals=10, storages=("f32", "f16s")):
+def batch_sweep(n=512, intervals=10, storages=("f32", "f16s", "f32x")):
     """The batched parameter sweep: n instances of the sweep distribution (lattices
     256x128 .. 1024x512, per-instance tau, Da, inflow, angle, Ra, gravity orientation) resident
     in one batch and stepped together, per storage, with the single-step tile of each size
@@ -202,7 +202,7 @@ def batch_sweep(n=512, intervals=10, storages=("f32", "f16s")):
         info = b.info()
         b.close()
         mlups = act * intervals * 100 / wall / 1e6
-        bpu = {"f64": 209, "f32": 105, "f16s": 53}[st]
+        bpu = {"f64": 209, "f32": 105, "f16s": 53, "f32x": 105}[st]
         out[st] = {"mlups": round(mlups, 1), "achieved_GBs": round(mlups * bpu / 1e3, 1),
                    "frac": round(mlups * bpu / 1e3 / HBM_PEAK_GBS, 4), "running_after": info["running"],
                    "tiles": {f"{x}x{y}": f"{t[0]}x{t[1]}" for x, y, t in sorted(shapes)}}
@@ -298,7 +298,7 @@ def precision_sweep(steps=20000, nx=8192, ny=4096, seed=0):
     out = {"workload": f"{nx}x{ny} eye section (sweep draw seed {seed}), {steps} time steps per storage"}
     ref = None
     p0, mask, walls, geo = A.sweep_instance(seed, nx, ny)
-    for st in ("f64", "f32", "f16s"):
+    for st in ("f64", "f32", "f16s", "f32x"):
         p = A.Params(**{**p0.asdict(), "storage": STORAGES[st]})
         s = aq.Solver(p, mask, walls)
         D = s.info()["check_interval"]
@@ -347,7 +347,7 @@ def main():
                     help="only the steady-state precision comparison of FP32 and F16S against FP64 "
                          "(four sweep draws, 512x256 to 2048x1024); one JSON line")
     ap.add_argument("--batch-sweep", action="store_true",
-                    help="only the 512-instance batched sweep (FP32 and F16S storage); one JSON line")
+                    help="only the 512-instance batched sweep (FP32, F16S and F32X storage); one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
@@ -470,7 +470,7 @@ def main():
             return {"mlups": round(e["mlups"], 1), "kernel": e["kernel"], "kernel_ms": round(e["launch_ms"], 5),
                     "achieved_GBs": round(e["achieved"], 1), "frac": round(e["achieved"] / HBM_PEAK_GBS, 4)}
         extra = {}
-        for st in ("f32", "f16s", "f64"):
+        for st in ("f32", "f16s", "f32x", "f64"):
             if st != args.storage:
                 extra[st] = brief(run(st, args.steps, args.warmup))
         out["other_storages"] = extra
@@ -482,7 +482,7 @@ def main():
         # extrapolated inlet / outlet and thermal walls)
         e = run(args.storage, args.steps, args.warmup, bc=1)
         out["paper_boundaries"] = {**brief(e), "iop_gauge": e["obs"]["iop_gauge"]}
-        out["dense_box"] = dense_box(("f64", "f32", "f16s"))
+        out["dense_box"] = dense_box(("f64", "f32", "f16s", "f32x"))
         out["precision_sweep"] = precision_sweep()
         out["shard_slabs"] = shard_slabs()
     if not args.no_batched:

@@ -52,8 +52,10 @@ enum {
 
 /* Storage precision of the populations.  F64: stored and computed in double.  F32:
  * stored and computed in float.  F16S: stored as binary16 of (deviation * 2^s) with a
- * per-solver power-of-two scale, computed in float.  Reductions are always double. */
-enum { AQ_F64 = 0, AQ_F32 = 1, AQ_F16S = 2 };
+ * per-solver power-of-two scale, computed in float.  F32X: stored in float, computed in
+ * double (the float arithmetic's rounding, not the storage, sets F32's error against
+ * FP64 at buoyant steady states).  Reductions are always double. */
+enum { AQ_F64 = 0, AQ_F32 = 1, AQ_F16S = 2, AQ_F32X = 3 };
 
 /* Fields for aq_read_field. */
 enum {
@@ -100,7 +102,7 @@ enum { AQ_BC_LINKWISE = 0, AQ_BC_PAPER = 1 };
  *   gbeta             g*beta; buoyant force g*beta*(T - T0)*(sin phi, cos phi) (eq. 16-17)
  *   gravity_angle     phi in radians; 0 means gravity along -y
  *   K                 Darcy permeability of POROUS nodes (eq. 4), > 0
- *   storage           AQ_F64, AQ_F32 or AQ_F16S
+ *   storage           AQ_F64, AQ_F32, AQ_F16S or AQ_F32X
  *   check_interval    steps between reductions; even, >= 2
  *   fp16_exp_flow, fp16_exp_thermal
  *                     F16S scale exponents s (values stored as deviation * 2^s);
@@ -343,7 +345,7 @@ typedef struct aq_result {
 
 typedef struct aq_batch_info {
     int32_t max_slots, running, finished;
-    int32_t n_work[3];              /* tiles per storage mode in the work lists */
+    int32_t n_work[4];              /* tiles per storage mode (AQ_F64 .. AQ_F32X) in the work lists */
     int64_t active_nodes;           /* over running instances */
     size_t budget_bytes, used_bytes, largest_free_bytes;
     int64_t step;                   /* time steps run by the batch */

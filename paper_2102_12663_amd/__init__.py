@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libaqlbm.so")
 
 AQ_OK, AQ_EINVAL, AQ_ENOMEM, AQ_EDEVICE, AQ_EDIVERGED, AQ_ENOTCONVERGED, AQ_EBUSY, AQ_ESTATE = \
     0, -1, -2, -3, -4, -5, -6, -7
-F64, F32, F16S = 0, 1, 2
+F64, F32, F16S, F32X = 0, 1, 2, 3
 FIELDS = {"p": 0, "ux": 1, "uy": 2, "T": 3, "pop_flow": 4, "pop_heat": 5}
 
 # every symbol include/aqlbm.h declares
@@ -95,7 +95,7 @@ class AqResult(C.Structure):
 
 class AqBatchInfo(C.Structure):
     _fields_ = [("max_slots", C.c_int32), ("running", C.c_int32), ("finished", C.c_int32),
-                ("n_work", C.c_int32 * 3), ("active_nodes", C.c_int64), ("budget_bytes", C.c_size_t),
+                ("n_work", C.c_int32 * 4), ("active_nodes", C.c_int64), ("budget_bytes", C.c_size_t),
                 ("used_bytes", C.c_size_t), ("largest_free_bytes", C.c_size_t), ("step", C.c_int64)]
 
     def asdict(self):

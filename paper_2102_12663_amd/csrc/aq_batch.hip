@@ -119,9 +119,10 @@ bool resid_done(Slot& sl, int mode, int n_intervals)
 
 }  // namespace
 
-constexpr int NKIND = 6;
+constexpr int NMODE = 4;            // AQ_F64, AQ_F32, AQ_F16S, AQ_F32X
+constexpr int NKIND = 2 * NMODE;    // x boundary scheme
 
-inline int kind_of(const aq_solver* s) { return s->mode + (s->P.bc_scheme == AQ_BC_PAPER ? 3 : 0); }
+inline int kind_of(const aq_solver* s) { return s->mode + (s->P.bc_scheme == AQ_BC_PAPER ? NMODE : 0); }
 
 struct aq_batch {
     size_t budget = 0;
@@ -134,13 +135,14 @@ struct aq_batch {
     std::vector<Slot> slots;
     int64_t step = 0;
 
-    // Instances are grouped into kernel classes ("kinds"): storage mode + 3 * boundary
+    // Instances are grouped into kernel classes ("kinds"): storage mode + NMODE * boundary
     // scheme (the paper's schemes are a compile-time variant of the step kernels).
     InstDesc* d_inst = nullptr;
     int2* d_work[NKIND] = {};
     int2* d_work2[NKIND] = {};
     int* d_nwork = nullptr;         // [0, NKIND) single-step items, [NKIND, 2 NKIND) two-step items
-    int fuse[NKIND] = {1, 1, 0, 1, 1, 0};   // two steps per launch: F64 and F32 yes, F16S no
+    // two steps per launch: F64, F32 and F32X yes, F16S no
+    int fuse[NKIND] = {1, 1, 0, 1, 1, 1, 0, 1};
     double* d_partials[NKIND] = {};
     double* d_latest = nullptr;
     double* h_latest = nullptr;     // pinned
@@ -169,10 +171,10 @@ BatchArgs batch_args(const aq_batch* b, int kind, int parity)
     a.latest = b->d_latest;
     a.parity = parity;
     a.max_slots = b->max_slots;
-    a.mode = kind % 3;
+    a.mode = kind % NMODE;
     a.kind = kind;
     a.nt_store = b->nt_store;
-    a.bc = kind / 3;
+    a.bc = kind / NMODE;
     return a;
 }
 
@@ -235,10 +237,10 @@ int ensure_graph(aq_batch* b)
         const int F = b->fuse[m] ? (plain / 2) & ~1 : 0;
         int parity = 0;
         for (int j = 0; j < F && err == hipSuccess; j++, parity ^= 1)
-            err = launch_batch_step2(m % 3, batch_args(b, m, parity), b->n_work2[m], b->stream);
+            err = launch_batch_step2(m % NMODE, batch_args(b, m, parity), b->n_work2[m], b->stream);
         for (int j = 2 * F; j < plain && err == hipSuccess; j++, parity ^= 1)
-            err = launch_batch_step(m % 3, false, batch_args(b, m, parity), b->n_work[m], b->stream);
-        if (err == hipSuccess) err = launch_batch_step(m % 3, true, batch_args(b, m, parity), b->n_work[m], b->stream);
+            err = launch_batch_step(m % NMODE, false, batch_args(b, m, parity), b->n_work[m], b->stream);
+        if (err == hipSuccess) err = launch_batch_step(m % NMODE, true, batch_args(b, m, parity), b->n_work[m], b->stream);
     }
     for (int m = 0; m < NKIND && err == hipSuccess; m++)
         if (mask & (1 << m)) err = launch_batch_finish(batch_args(b, m, 0), b->stream);
@@ -433,7 +435,7 @@ int aq_batch_create(size_t budget_bytes, int32_t max_slots, int64_t max_active_n
         b->own_stream = true;
     }
     bool ok = hipMalloc((void**)&b->d_inst, (size_t)max_slots * sizeof(InstDesc)) == hipSuccess &&
-              hipMalloc((void**)&b->d_nwork, 64) == hipSuccess &&
+              hipMalloc((void**)&b->d_nwork, 2 * NKIND * sizeof(int)) == hipSuccess &&
               hipMalloc((void**)&b->d_latest, (size_t)max_slots * NRED * 8) == hipSuccess &&
               hipHostMalloc((void**)&b->h_latest, (size_t)max_slots * NRED * 8, hipHostMallocDefault) == hipSuccess;
     if (!ok) return cleanup(fail(AQ_ENOMEM, "cannot allocate the batch tables"));
@@ -666,7 +668,7 @@ int aq_batch_get_info(aq_batch* b, aq_batch_info* o)
         if (sl.running) o->running++;
         else o->finished++;
     }
-    for (int m = 0; m < NKIND; m++) o->n_work[m % 3] += b->n_work[m];
+    for (int m = 0; m < NKIND; m++) o->n_work[m % NMODE] += b->n_work[m];
     o->active_nodes = running_active(b);
     o->budget_bytes = b->budget;
     o->used_bytes = b->pool.used();

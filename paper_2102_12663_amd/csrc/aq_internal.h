@@ -24,7 +24,7 @@ int fail(int code, const std::string& msg);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-inline size_t storage_size(int mode) { return mode == AQ_F64 ? 8 : (mode == AQ_F32 ? 4 : 2); }
+inline size_t storage_size(int mode) { return mode == AQ_F64 ? 8 : (mode == AQ_F16S ? 2 : 4); }
 
 struct Layout {
     int pitch;

@@ -33,9 +33,12 @@ __device__ constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
 // Storage precision: how a population is stored and in which type it is computed.
 template <int MODE> struct Traits;
+// L is the element type of the two-step kernels' LDS image: it holds values decoded from the
+// storage, so single precision is exact for every storage but FP64.
 template <> struct Traits<0> {   // AQ_F64
     using S = double;
     using R = double;
+    using L = double;
     using Acc = double;      // exact-enough sums of a node's stored values
     __device__ static R ld(const S* p, R) { return *p; }
     __device__ static R ldv(S v, R) { return v; }
@@ -46,6 +49,7 @@ template <> struct Traits<0> {   // AQ_F64
 template <> struct Traits<1> {   // AQ_F32
     using S = float;
     using R = float;
+    using L = float;
     using Acc = double;
     __device__ static R ld(const S* p, R) { return *p; }
     __device__ static R ldv(S v, R) { return v; }
@@ -56,12 +60,24 @@ template <> struct Traits<1> {   // AQ_F32
 template <> struct Traits<2> {   // AQ_F16S: binary16 of (deviation * 2^s)
     using S = _Float16;
     using R = float;
+    using L = float;
     using Acc = float;       // float sums of binary16 values are far finer than their ulp
     __device__ static R ld(const S* p, R inv) { return (R)(*p) * inv; }
     __device__ static R ldv(S v, R inv) { return (R)v * inv; }
     __device__ static void st(S* p, R v, R sc) { *p = (S)(v * sc); }
     __device__ static S enc(Acc v, R sc) { return (S)(v * sc); }
     __device__ static Acc dec(S s, R inv) { return (R)s * inv; }
+};
+template <> struct Traits<3> {   // AQ_F32X: FP32 storage, FP64 arithmetic
+    using S = float;
+    using R = double;
+    using L = float;
+    using Acc = double;
+    __device__ static R ld(const S* p, R) { return *p; }
+    __device__ static R ldv(S v, R) { return v; }
+    __device__ static void st(S* p, R v, R) { *p = (S)v; }
+    __device__ static S enc(Acc v, R) { return (S)v; }
+    __device__ static Acc dec(S s, R) { return s; }
 };
 
 // A step constant in the compute type: the double itself, or its single-precision copy
@@ -867,7 +883,8 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(BatchArgs b)
 // travels to HBM.
 template <int MODE> struct Fuse {
     static constexpr int TY = 8;                              // output rows per tile
-    static constexpr int THREADS = (MODE == 0) ? 512 : 256;   // threads per block
+    // threads per block: the FP64-compute forms take two step-A nodes per thread
+    static constexpr int THREADS = (MODE == 0 || MODE == 3) ? 512 : 256;
     // step A of the batched kernel issues all of a thread's loads first in FP64 and FP32
     // (FP32 512-instance sweep: 60.4 against 55.9 GLUPS one node at a time); F16S runs
     // single steps in a batch
@@ -898,7 +915,7 @@ __device__ __forceinline__ int lds_g0(int ly, int lx)
 
 // Pull from the LDS image of step n+1 (E coordinates: the tile node is (ex, ey)).
 template <int MODE, bool BC>
-__device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Traits<MODE>::R* lds, int k, int ex,
+__device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Traits<MODE>::L* lds, int k, int ex,
                                          int ey, uint8_t t, Node<typename Traits<MODE>::R>& n)
 {
     using R = typename Traits<MODE>::R;
@@ -917,7 +934,7 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
 #pragma unroll
     for (int i = 1; i <= 8; i++)
         n.h[i] = up[i] ? lds[lds_at<MODE>(i - 1, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE>(OPP[i] - 1, ey, ex)];
-    n.g[0] = lds[lds_g0<MODE>(ey, ex)];
+    n.g[0] = R(lds[lds_g0<MODE>(ey, ex)]);
 #pragma unroll
     for (int i = 1; i <= 4; i++)
         n.g[i] = up[i] ? lds[lds_at<MODE>(7 + i, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE>(7 + OPP[i], ey, ex)];
@@ -946,9 +963,9 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
         } else if (BC && w >= 0) {                        // interpolated bounce-back
             const double q = wall_fraction(a, w, i);
             if (q >= 0.5)
-                n.h[i] = bouzidi(R(q), v, lds[lds_at<MODE>(i - 1, ey, ex)], R(0));
+                n.h[i] = bouzidi(R(q), v, R(lds[lds_at<MODE>(i - 1, ey, ex)]), R(0));
             else if (q > 0.0 && up[OPP[i]])
-                n.h[i] = bouzidi(R(q), v, R(0), lds[lds_at<MODE>(OPP[i] - 1, ey + EY[i], ex + EX[i])]);
+                n.h[i] = bouzidi(R(q), v, R(0), R(lds[lds_at<MODE>(OPP[i] - 1, ey + EY[i], ex + EX[i])]));
         }
     }
 #pragma unroll
@@ -965,10 +982,10 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
         if (!extra) return;
         Node<R> own;
 #pragma unroll
-        for (int i = 1; i <= 8; i++) own.h[i] = lds[lds_at<MODE>(i - 1, ey, ex)];
-        own.g[0] = lds[lds_g0<MODE>(ey, ex)];
+        for (int i = 1; i <= 8; i++) own.h[i] = R(lds[lds_at<MODE>(i - 1, ey, ex)]);
+        own.g[0] = R(lds[lds_g0<MODE>(ey, ex)]);
 #pragma unroll
-        for (int i = 1; i <= 4; i++) own.g[i] = lds[lds_at<MODE>(7 + i, ey, ex)];
+        for (int i = 1; i <= 4; i++) own.g[i] = R(lds[lds_at<MODE>(7 + i, ey, ex)]);
         const Moments<R> ms = moments(own);
         extrapolate_links(a, nt, own, ms, n);
     }
@@ -998,7 +1015,7 @@ __device__ __forceinline__ void encode_decoded(const StepArgs& a, const Node<typ
 // decoded values in LDS.
 template <int MODE>
 __device__ __forceinline__ void step_a_store(const StepArgs& a, const Node<typename Traits<MODE>::R>& n, bool porous,
-                                             int ex, int ey, typename Traits<MODE>::R* lds)
+                                             int ex, int ey, typename Traits<MODE>::L* lds)
 {
     using T = Traits<MODE>;
     using R = typename T::R;
@@ -1008,17 +1025,18 @@ __device__ __forceinline__ void step_a_store(const StepArgs& a, const Node<typen
     collide(a, porous, n, m, hs, gs);
     typename T::S enc[NPOP];
     encode_decoded<MODE>(a, n, hs, gs, enc);
+    using L = typename T::L;   // exact: the decoded values of the storage
 #pragma unroll
-    for (int q = 0; q < 8; q++) lds[lds_at<MODE>(q, ey, ex)] = T::ldv(enc[q], cst<R>(a.inv_sf, a.inv_sf32));
+    for (int q = 0; q < 8; q++) lds[lds_at<MODE>(q, ey, ex)] = (L)T::ldv(enc[q], cst<R>(a.inv_sf, a.inv_sf32));
 #pragma unroll
-    for (int i = 1; i <= 4; i++) lds[lds_at<MODE>(7 + i, ey, ex)] = T::ldv(enc[8 + i], cst<R>(a.inv_st, a.inv_st32));
-    if (ex >= 1 && ex <= 64 && ey >= 1 && ey <= F::TY) lds[lds_g0<MODE>(ey, ex)] = T::ldv(enc[8], cst<R>(a.inv_st, a.inv_st32));
+    for (int i = 1; i <= 4; i++) lds[lds_at<MODE>(7 + i, ey, ex)] = (L)T::ldv(enc[8 + i], cst<R>(a.inv_st, a.inv_st32));
+    if (ex >= 1 && ex <= 64 && ey >= 1 && ey <= F::TY) lds[lds_g0<MODE>(ey, ex)] = (L)T::ldv(enc[8], cst<R>(a.inv_st, a.inv_st32));
 }
 
 // PF: step A issues the loads of all of a thread's nodes before computing any (more bytes
 // in flight, more registers).
 template <int MODE, bool NT, bool PF, bool BC>
-__device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typename Traits<MODE>::R* lds)
+__device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typename Traits<MODE>::L* lds)
 {
     using T = Traits<MODE>;
     using R = typename T::R;
@@ -1093,7 +1111,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
 template <int MODE, bool NT, bool BC>
 __global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void step2_kernel(StepArgs a)
 {
-    __shared__ typename Traits<MODE>::R lds[Fuse<MODE>::WORDS];
+    __shared__ typename Traits<MODE>::L lds[Fuse<MODE>::WORDS];
     process_tile2<MODE, NT, true, BC>(a, a.tiles[tile_of_block(a)], lds);
 }
 
@@ -1120,23 +1138,28 @@ hipError_t launch_step2(int mode, const StepArgs& a, hipStream_t s)
     case 3: return launch_step2_bc<1, true>(a, s);
     case 4: return launch_step2_bc<2, false>(a, s);
     case 5: return launch_step2_bc<2, true>(a, s);
+    case 6: return launch_step2_bc<3, false>(a, s);
+    case 7: return launch_step2_bc<3, true>(a, s);
     }
     return hipErrorInvalidValue;
 }
 
-int fused_tile_rows(int mode) { return mode == 0 ? Fuse<0>::TY : mode == 1 ? Fuse<1>::TY : Fuse<2>::TY; }
+int fused_tile_rows(int mode)
+{
+    return mode == 0 ? Fuse<0>::TY : mode == 1 ? Fuse<1>::TY : mode == 2 ? Fuse<2>::TY : Fuse<3>::TY;
+}
 
 // Two time steps of every running instance of a batch in kernel class b.kind (fused tile
 // work list; the same item assignment and argument loads as batch_step_kernel).
 template <int MODE, bool NT, bool BC>
 __global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void batch_step2_kernel(BatchArgs b)
 {
-    __shared__ typename Traits<MODE>::R lds[Fuse<MODE>::WORDS];
+    __shared__ typename Traits<MODE>::L lds[Fuse<MODE>::WORDS];
     const int w = batch_item();
     if (w >= *b.n_work2) return;
     const int2 it = load_item(b.work2, w);
     // (the FP32 paper-scheme variant would spill with all loads first)
-    process_tile2<MODE, NT, Fuse<MODE>::BATCH_PF && !(MODE == 1 && BC), BC>(batch_desc<true>(b, it.x), it.y, lds);
+    process_tile2<MODE, NT, Fuse<MODE>::BATCH_PF && !(MODE != 0 && BC), BC>(batch_desc<true>(b, it.x), it.y, lds);
 }
 
 template <int MODE, bool NT, bool BC>
@@ -1162,6 +1185,8 @@ hipError_t launch_batch_step2(int mode, const BatchArgs& b, int grid, hipStream_
     case 3: return launch_batch2_t<1, true>(b, grid, s);
     case 4: return launch_batch2_t<2, false>(b, grid, s);
     case 5: return launch_batch2_t<2, true>(b, grid, s);
+    case 6: return launch_batch2_t<3, false>(b, grid, s);
+    case 7: return launch_batch2_t<3, true>(b, grid, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1320,6 +1345,8 @@ hipError_t launch_step(int mode, bool reduce, const StepArgs& a, hipStream_t s)
     case 3: return launch_step_t<1, true>(reduce, a, s);
     case 4: return launch_step_t<2, false>(reduce, a, s);
     case 5: return launch_step_t<2, true>(reduce, a, s);
+    case 6: return launch_step_t<3, false>(reduce, a, s);
+    case 7: return launch_step_t<3, true>(reduce, a, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1348,6 +1375,8 @@ hipError_t launch_batch_step(int mode, bool reduce, const BatchArgs& b, int grid
     case 3: return launch_batch_t<1, true>(reduce, b, grid, s);
     case 4: return launch_batch_t<2, false>(reduce, b, grid, s);
     case 5: return launch_batch_t<2, true>(reduce, b, grid, s);
+    case 6: return launch_batch_t<3, false>(reduce, b, grid, s);
+    case 7: return launch_batch_t<3, true>(reduce, b, grid, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1367,6 +1396,7 @@ hipError_t launch_scatter(int mode, const StepArgs& a, const double* pops, doubl
     case 0: hipLaunchKernelGGL(scatter_kernel<0>, lattice_grid(a), dim3(256), 0, s, a, pops, dp0, th0); break;
     case 1: hipLaunchKernelGGL(scatter_kernel<1>, lattice_grid(a), dim3(256), 0, s, a, pops, dp0, th0); break;
     case 2: hipLaunchKernelGGL(scatter_kernel<2>, lattice_grid(a), dim3(256), 0, s, a, pops, dp0, th0); break;
+    case 3: hipLaunchKernelGGL(scatter_kernel<3>, lattice_grid(a), dim3(256), 0, s, a, pops, dp0, th0); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1379,6 +1409,7 @@ hipError_t launch_unpack(int mode, const StepArgs& a, int field, int q, double p
     case 0: hipLaunchKernelGGL(unpack_kernel<0>, lattice_grid(a), dim3(256), 0, s, a, field, q, p_ref, out); break;
     case 1: hipLaunchKernelGGL(unpack_kernel<1>, lattice_grid(a), dim3(256), 0, s, a, field, q, p_ref, out); break;
     case 2: hipLaunchKernelGGL(unpack_kernel<2>, lattice_grid(a), dim3(256), 0, s, a, field, q, p_ref, out); break;
+    case 3: hipLaunchKernelGGL(unpack_kernel<3>, lattice_grid(a), dim3(256), 0, s, a, field, q, p_ref, out); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

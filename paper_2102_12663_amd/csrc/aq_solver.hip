@@ -168,15 +168,15 @@ int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls,
     if (P->nx < 4 || P->ny < 4) return fail(AQ_EINVAL, "nx and ny must be >= 4");
     if ((long long)P->nx * P->ny > (1LL << 30)) return fail(AQ_EINVAL, "lattice too large");
     if (!(P->tau_f > 0.5) || !(P->tau_t > 0.5)) return fail(AQ_EINVAL, "tau_f and tau_t must exceed 1/2");
-    if (P->storage == AQ_F32 || P->storage == AQ_F16S) {
-        // the FP32-compute kernels address a population plane with 32-bit byte offsets
-        const long long elem = P->storage == AQ_F32 ? 4 : 2;
+    if (P->storage == AQ_F32 || P->storage == AQ_F32X || P->storage == AQ_F16S) {
+        // the kernels of the reduced storages address a population plane with 32-bit offsets
+        const long long elem = P->storage == AQ_F16S ? 2 : 4;
         if (make_layout(*P, 0).qs * elem > (1LL << 32))
             return fail(AQ_EINVAL, "lattice too large for the storage: a population plane must stay within 4 GiB");
     }
     if (!(P->w0 >= 0.0 && P->w0 < 1.0)) return fail(AQ_EINVAL, "w0 must be in [0, 1)");
     if (!(P->K > 0.0)) return fail(AQ_EINVAL, "K must be positive");
-    if (P->storage < AQ_F64 || P->storage > AQ_F16S) return fail(AQ_EINVAL, "unknown storage");
+    if (P->storage < AQ_F64 || P->storage > AQ_F32X) return fail(AQ_EINVAL, "unknown storage");
     if (P->check_interval < 2 || (P->check_interval & 1)) return fail(AQ_EINVAL, "check_interval must be even and >= 2");
     if (P->fp16_exp_flow < -1 || P->fp16_exp_flow > 40 || P->fp16_exp_thermal < -1 || P->fp16_exp_thermal > 40)
         return fail(AQ_EINVAL, "fp16 exponents must be in [-1, 40]");
@@ -596,7 +596,7 @@ int aq_required_bytes(const aq_params* P, const uint8_t* mask, size_t* bytes)
 {
     if (!P || !bytes) return fail(AQ_EINVAL, "null argument");
     if (P->struct_size != sizeof(aq_params)) return fail(AQ_EINVAL, "aq_params.struct_size mismatch");
-    if (P->nx < 4 || P->ny < 4 || P->storage < 0 || P->storage > 2) return fail(AQ_EINVAL, "invalid size or storage");
+    if (P->nx < 4 || P->ny < 4 || P->storage < AQ_F64 || P->storage > AQ_F32X) return fail(AQ_EINVAL, "invalid size or storage");
     int n_walls = 0;
     if (mask) {
         // an upper bound on the wall list: every FLUID node

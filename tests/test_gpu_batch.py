@@ -28,7 +28,7 @@ def _instances():
     """Uneven sizes, storages, angles, orientations (the batched sweep's draws)."""
     out = []
     for seed, (nx, ny), st in ((3, (256, 128), A.F32), (5, (512, 256), A.F64), (6, (256, 128), A.F16S),
-                                (7, (384, 192), A.F32), (9, (320, 160), A.F64)):
+                                (7, (384, 192), A.F32), (9, (320, 160), A.F64), (11, (320, 160), A.F32X)):
         p, mask, walls, geo = A.sweep_instance(seed, nx, ny, tau_f="draw", phi_deg="draw", storage=st)
         out.append((p, mask, walls))
     return out

@@ -78,7 +78,7 @@ def test_bouzidi_offgrid_box_parity(aq):
     s.close()
 
 
-@pytest.mark.parametrize("storage", [A.F64, A.F32])
+@pytest.mark.parametrize("storage", [A.F64, A.F32, A.F32X])
 def test_bouzidi_two_step_launches_bitwise(aq, storage):
     p, mask, walls = _eye(storage=storage)
     out = []

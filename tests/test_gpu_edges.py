@@ -83,7 +83,7 @@ def test_config2_size_fp64_parity_100_steps(aq):
     assert all(v <= 1e-12 for v in err.values()), err
 
 
-@pytest.mark.parametrize("storage", [A.F64, A.F32, A.F16S])
+@pytest.mark.parametrize("storage", [A.F64, A.F32, A.F16S, A.F32X])
 def test_config2_size_mirror_symmetry(aq, storage):
     """Gravity along -y and a mirror-symmetric section: the state stays mirror symmetric
     at 8192x4096 (u_x odd, the rest even) in every storage."""
@@ -92,7 +92,7 @@ def test_config2_size_mirror_symmetry(aq, storage):
     s.step(600)
     act = A.active(mask)
     dp, ux, uy, T = s.fields()
-    tol = {A.F64: 1e-11, A.F32: 1e-5, A.F16S: 1e-2}[storage]
+    tol = {A.F64: 1e-11, A.F32: 1e-5, A.F16S: 1e-2, A.F32X: 1e-5}[storage]
     for F, sign in ((dp, 1), (ux, -1), (uy, 1), (T - p.T_ref, 1)):
         sc = np.max(np.abs(F[act]))
         assert np.max(np.abs(F[act] - sign * F[:, ::-1][act])) <= tol * sc

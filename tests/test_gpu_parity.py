@@ -184,9 +184,9 @@ def test_run_to_steady_matches_oracle_iop(aq):
     assert abs(ob["q_out"] / ob["q_in"] - 1) < 1e-6
 
 
-@pytest.mark.parametrize("storage,tol_u,tol_iop", [(A.F32, 1e-4, 1e-3), (A.F16S, 5e-2, 5e-2)])
+@pytest.mark.parametrize("storage,tol_u,tol_iop", [(A.F32, 1e-4, 1e-3), (A.F16S, 5e-2, 5e-2), (A.F32X, 1e-6, 1e-6)])
 def test_reduced_precision_close_to_fp64(aq, storage, tol_u, tol_iop):
-    """FP32 and F16S storage after 1000 steps of the 192x96 case stay near FP64."""
+    """FP32, F16S and F32X storage after 1000 steps of the 192x96 case stay near FP64."""
     p, mask, walls, geo = A.config0()
     ref = aq.Solver(p, mask, walls)
     ref.step(1000)
@@ -207,7 +207,8 @@ def test_steady_state_precision_bounds(aq):
     """The reduced-precision forms at a steady state (sweep draw 3 at 512x256, buoyant): FP64
     runs to a residual of 1e-9; FP32 and F16S storage run the same number of steps from the
     same state.  FP32: velocity L2 within 1e-4 and IOP within 0.1% of FP64; F16S: IOP within
-    0.1% (its velocities carry binary16 rounding)."""
+    0.1% (its velocities carry binary16 rounding); F32X (float storage, double arithmetic):
+    velocity within 1e-5."""
     p0, mask, walls, geo = A.sweep_instance(3, 512, 256)
     act = A.active(mask)
     ref = aq.Solver(p0, mask, walls)
@@ -216,7 +217,7 @@ def test_steady_state_precision_bounds(aq):
     f64 = ref.fields()
     ref.close()
     den = np.sqrt(np.sum(f64[1][act] ** 2 + f64[2][act] ** 2))
-    for storage, tol_u in ((A.F32, 1e-4), (A.F16S, None)):
+    for storage, tol_u in ((A.F32, 1e-4), (A.F16S, None), (A.F32X, 1e-5)):
         s = aq.Solver(A.Params(**{**p0.asdict(), "storage": storage}), mask, walls)
         s.step(ob64["step"])
         ob, f = s.observe(), s.fields()
@@ -242,7 +243,7 @@ def test_config1_size_fp64_parity(aq):
     assert not bad, bad
 
 
-@pytest.mark.parametrize("storage", [A.F64, A.F32, A.F16S])
+@pytest.mark.parametrize("storage", [A.F64, A.F32, A.F16S, A.F32X])
 @pytest.mark.parametrize("size", [(192, 96), (300, 150)])
 def test_two_step_fusion_bitwise(aq, storage, size):
     """Two steps per launch (temporal blocking through LDS) gives bitwise the same state
