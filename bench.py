@@ -169,7 +169,7 @@ def shard_slabs(n=8, nx=8192, ny=4096, seed=0, intervals=10):
             "y_slab_imbalance": round(max(int(act[k * ny // n:(k + 1) * ny // n].sum()) for k in range(n)) * n / total, 3)}
 
 
-def batch_sweep(n=512, intervals=10, storages=("f32", "f16s", "f32x")):
+def batch_sweep(n=512, intervals=10, storages=("f32", "f16s", "f32x", "f64")):
     """The batched parameter sweep: n instances of the sweep distribution (lattices
     256x128 .. 1024x512, per-instance tau, Da, inflow, angle, Ra, gravity orientation) resident
     in one batch and stepped together, per storage, with the single-step tile of each size

@@ -81,7 +81,7 @@ struct InstDesc {
     StepArgs a;
     StepArgs a2;                  // the same instance with its fused (two-step) tile list
     int work_start, work_count;   // this instance's run in its storage mode's work list
-    int running, mode;            // mode: the instance's kernel class (storage + 3 * paper scheme)
+    int running, mode;            // mode: the instance's kernel class (storage + 4 * paper scheme)
 };
 
 // Arguments of the batched kernels (one storage mode per launch).
