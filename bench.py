@@ -101,7 +101,7 @@ def batched_vs_one_at_a_time(n, cap=200000, tol=1e-6):
 
 def precision_steady(cases=((512, 256, 3), (512, 256, 5), (1024, 512, 6), (2048, 1024, 3)), tol=1e-9):
     """The reduced-precision forms against FP64 at steady states: each sweep draw runs in FP64
-    to a residual of `tol`; FP32 and F16S storage then run the same number of steps from the
+    to a residual of `tol`; FP32, F16S and F32X storage then run the same number of steps from the
     same initial state.  Velocity L2 error relative to FP64 over active nodes, IOP relative
     error, max |T| error and the reduced form's own final residual."""
     import numpy as np
@@ -290,8 +290,8 @@ def dense_box(storages, intervals=10, nx=8192, ny=4096):
 
 def precision_sweep(steps=20000, nx=8192, ny=4096, seed=0):
     """The 8192x4096 eye (sweep draw seed 0) for `steps` time steps in each storage, from
-    the same initial state: active MLUPS, and the IOP and velocity errors of FP32 and F16S
-    storage against the FP64 run on the GPU (velocity: L2 over active nodes, relative)."""
+    the same initial state: active MLUPS, and the IOP and velocity errors of FP32, F16S and
+    F32X storage against the FP64 run on the GPU (velocity: L2 over active nodes, relative)."""
     import numpy as np
     import aqinputs as A
     import paper_2102_12663_amd as aq
@@ -344,10 +344,10 @@ def main():
     ap.add_argument("--probe-single", action="store_true",
                     help="with --probe: the single-step kernel even where the solver runs two steps per launch")
     ap.add_argument("--precision-steady", action="store_true",
-                    help="only the steady-state precision comparison of FP32 and F16S against FP64 "
+                    help="only the steady-state precision comparison of FP32, F16S and F32X against FP64 "
                          "(four sweep draws, 512x256 to 2048x1024); one JSON line")
     ap.add_argument("--batch-sweep", action="store_true",
-                    help="only the 512-instance batched sweep (FP32, F16S and F32X storage); one JSON line")
+                    help="only the 512-instance batched sweep (FP32, F16S, F32X and FP64 storage); one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
