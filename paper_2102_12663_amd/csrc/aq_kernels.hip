@@ -127,8 +127,8 @@ __device__ __forceinline__ Moments<R> moments(const Node<R>& n)
 // thread of the block (a plane base shifted by a link): the base goes through a scalar
 // register, so a load or store takes it with the 32-bit per-node offset as its offset
 // operand and no thread does 64-bit address arithmetic.  The offsets stay below 4 GiB: the
-// node-type bytes (at most 2^30 nodes) and the F32 and F16S population planes (checked at
-// creation).
+// node-type bytes (at most 2^30 nodes) and the F32, F32X and F16S population planes (checked
+// at creation).
 __device__ __forceinline__ const char* uniform_base(const void* p)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -178,7 +178,8 @@ __device__ __forceinline__ void pull_types(const StepArgs& a, int k, bool bounda
 // link from upstream with one addressing form: a plane base shifted by the link (uniform,
 // scalar arithmetic) plus the node's own byte offset, the same for all 13 loads; that
 // saves the integer work of the compute-bound formats.  FP64 keeps one 64-bit address per
-// load (measured: the split costs the bandwidth-bound FP64 kernels about 1%).
+// load and the per-link selects: with this interior path, or one with 64-bit addresses, its
+// single step took 2-4% longer and its two-step launch 1-4%.
 template <int MODE>
 __device__ __forceinline__ void pull_loads(const StepArgs& a, const typename Traits<MODE>::S* src, int k,
                                            bool boundary, const uint8_t* nt, Node<typename Traits<MODE>::R>& n)

@@ -495,8 +495,9 @@ int setup(aq_solver* s, const uint8_t* mask, const aq_wall_node* walls, int32_t 
         }
     // the read and written populations of a step exceed the last-level cache: stream the writes
     s->nt_store = (double)s->n_active * bytes_per_update(s->mode) > kMallBytes ? 1 : 0;
-    // two steps per launch where it measured faster: FP64 always, the others past the cache
-    s->fuse = (s->mode == AQ_F64 || s->nt_store) ? 1 : 0;
+    // two steps per launch where it measured faster: the FP64-arithmetic storages always,
+    // FP32 and F16S past the cache
+    s->fuse = (s->mode == AQ_F64 || s->mode == AQ_F32X || s->nt_store) ? 1 : 0;
     s->n_walls = n_walls;
     s->hwall_node.resize(std::max(n_walls, 1));
     s->hwall_id.resize(std::max(n_walls, 1));
