@@ -562,15 +562,17 @@ __device__ __forceinline__ void conserve_encode(const typename Traits<MODE>::R* 
         for (int i = 0; i < N; i++) enc[i] = i == kmin ? c : enc[i];
         return;
     }
+    // F32 and F32X: the decoded value is exact in single precision (the LDS type L), so the
+    // search runs there, also where the arithmetic is FP64
+    using L = typename T::L;
     Acc target = 0, sum = 0;
-    R dmin = 0;
+    L dmin = 0;
     int kmin = 0;
 #pragma unroll
     for (int i = 0; i < N; i++) {
         target += (Acc)in[i];
         enc[i] = T::enc((Acc)out[i], sc);
-        // the decoded value is exact in the compute type, so the search runs there
-        const R d = T::ldv(enc[i], inv);
+        const L d = (L)T::ldv(enc[i], inv);
         sum += (Acc)d;
         const bool lower = i == 0 || fabs(d) < fabs(dmin);   // selects, not branches
         dmin = lower ? d : dmin;
