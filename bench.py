@@ -209,6 +209,28 @@ def batch_sweep(n=512, intervals=10, storages=("f32", "f16s", "f32x", "f64")):
     return out
 
 
+def serve_stream(rate=50.0, duration=60.0, time_limit=200.0):
+    """The serving stream: sweep requests (every 10th a 2048x1024 eye) arriving as a Poisson
+    stream of `rate` per second for `duration` seconds, served by one batch in F16S storage
+    with the FP32 hand-off, residual 1e-6, until every request has finished or `time_limit`
+    seconds have passed.  Progress lines go to stderr."""
+    import paper_2102_12663_amd as aq
+    from paper_2102_12663_amd import serve as S
+    done = [0]
+
+    def progress(r):
+        done[0] += 1
+        if done[0] % 25 == 1:
+            print(f"[serve] {done[0]} finished, {r['t_done']:.0f} s", file=sys.stderr, flush=True)
+
+    r = S.serve(rate=rate, duration=duration, storage=aq.F16S, tol=1e-6, budget_bytes=64 << 30,
+                max_steps=300000, intervals_per_call=5, time_limit=time_limit, log=progress)
+    r.pop("records")
+    r["workload"] = (f"Poisson stream of sweep requests, {rate:g}/s for {duration:g} s (every 10th 2048x1024), "
+                     f"F16S with the FP32 hand-off, residual 1e-6, stopped at {time_limit:g} s")
+    return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}
+
+
 def outflow_area(mask):
     """Outflow area of a lumped-meshwork mask: sum over links from active nodes into OUTLET
     nodes of 6 w_i (e_i . n), n the node's outward direction (mask bits 3-4)."""
@@ -346,6 +368,9 @@ def main():
     ap.add_argument("--precision-steady", action="store_true",
                     help="only the steady-state precision comparison of FP32, F16S and F32X against FP64 "
                          "(four sweep draws, 512x256 to 2048x1024); one JSON line")
+    ap.add_argument("--serve", action="store_true",
+                    help="only the Poisson serving stream (50 requests/s for 60 s, F16S with the FP32 hand-off, "
+                         "stopped at 200 s); one JSON line, progress on stderr")
     ap.add_argument("--batch-sweep", action="store_true",
                     help="only the 512-instance batched sweep (FP32, F16S, F32X and FP64 storage); one JSON line")
     args = ap.parse_args()
@@ -364,6 +389,9 @@ def main():
     tx, ty = (int(v) for v in args.tile.split("x"))
     if args.batch_sweep:
         print(json.dumps({"batch_sweep": batch_sweep()}), flush=True)
+        return
+    if args.serve:
+        print(json.dumps({"serve": serve_stream()}), flush=True)
         return
     if args.precision_steady:
         print(json.dumps({"precision_steady": precision_steady()}), flush=True)

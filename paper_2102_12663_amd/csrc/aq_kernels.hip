@@ -909,10 +909,6 @@ template <int MODE> struct Fuse {
     static constexpr int TY = 8;                              // output rows per tile
     // threads per block: the FP64-compute forms take two step-A nodes per thread
     static constexpr int THREADS = (MODE == 0 || MODE == 3) ? 512 : 256;
-    // step A of the batched kernel issues all of a thread's loads first in FP64 and FP32
-    // (FP32 512-instance sweep: 60.4 against 55.9 GLUPS one node at a time); F16S runs
-    // single steps in a batch
-    static constexpr bool BATCH_PF = MODE != 2;
     static constexpr int EW = 66, EH = TY + 2;        // tile plus a one-node halo
     static constexpr int EN = EW * EH;                // step-A nodes
     static constexpr int NA = (EN + THREADS - 1) / THREADS;   // step-A nodes per thread
@@ -1182,8 +1178,10 @@ __global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void batch_step2_kernel(Bat
     const int w = batch_item();
     if (w >= *b.n_work2) return;
     const int2 it = load_item(b.work2, w);
-    // (the FP32 paper-scheme variant would spill with all loads first)
-    process_tile2<MODE, NT, Fuse<MODE>::BATCH_PF && !(MODE != 0 && BC), BC>(batch_desc<true>(b, it.x), it.y, lds);
+    // step A issues all of a thread's loads first (512-instance sweep, FP32: 60.4 against 55.9
+    // GLUPS one node at a time; F16S: 69.3 against 61.2), except in the FP32-arithmetic
+    // paper-scheme variants, which would spill
+    process_tile2<MODE, NT, !(MODE != 0 && BC), BC>(batch_desc<true>(b, it.x), it.y, lds);
 }
 
 template <int MODE, bool NT, bool BC>

@@ -78,7 +78,7 @@ def test_bouzidi_offgrid_box_parity(aq):
     s.close()
 
 
-@pytest.mark.parametrize("storage", [A.F64, A.F32, A.F32X])
+@pytest.mark.parametrize("storage", [A.F64, A.F32, A.F16S, A.F32X])
 def test_bouzidi_two_step_launches_bitwise(aq, storage):
     p, mask, walls = _eye(storage=storage)
     out = []
@@ -99,11 +99,12 @@ def test_paper_scheme_in_a_batch_bitwise(aq):
     p1, m1, w1 = _eye()
     p2, m2, w2, geo2 = A.sweep_instance(3, 256, 128)
     p3 = A.Params(**{**p1.asdict(), "storage": A.F32})
+    p4 = A.Params(**{**p1.asdict(), "storage": A.F16S})
+    insts = ((p1, m1, w1), (p2, m2, w2), (p3, m1, w1), (p4, m1, w1))
     b = aq.Batch(budget_bytes=1 << 30, max_slots=8)
-    slots = [b.admit(p, m, w, tile=(64, 4), tol=1e-14, max_steps=10 ** 6, keep=True)
-             for p, m, w in ((p1, m1, w1), (p2, m2, w2), (p3, m1, w1))]
+    slots = [b.admit(p, m, w, tile=(64, 4), tol=1e-14, max_steps=10 ** 6, keep=True) for p, m, w in insts]
     b.run(5)
-    for sl, (p, m, w) in zip(slots, ((p1, m1, w1), (p2, m2, w2), (p3, m1, w1))):
+    for sl, (p, m, w) in zip(slots, insts):
         alone = aq.Solver(p, m, w)
         alone.set_tile(64, 4)
         alone.step(500)
