@@ -1179,8 +1179,8 @@ __global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void batch_step2_kernel(Bat
     if (w >= *b.n_work2) return;
     const int2 it = load_item(b.work2, w);
     // step A issues all of a thread's loads first (512-instance sweep, FP32: 60.4 against 55.9
-    // GLUPS one node at a time; F16S: 69.3 against 61.2), except in the FP32-arithmetic
-    // paper-scheme variants, which would spill
+    // GLUPS one node at a time; F16S: 69.3 against 61.2), except in the paper-scheme variants
+    // of the single-precision storages (F32, F16S, F32X), which would spill
     process_tile2<MODE, NT, !(MODE != 0 && BC), BC>(batch_desc<true>(b, it.x), it.y, lds);
 }
 
