@@ -182,3 +182,29 @@ def test_autotune_picks_a_valid_shape(aq):
     assert tx * ty == 256 and ms > 0
     assert (s.info()["tile_x"], s.info()["tile_y"]) == (tx, ty)
     s.close()
+
+
+def test_full_sweep_batch_sampled_oracle_parity(aq):
+    """The 512-instance sweep (every size class, per-instance tau, angle, Ra, Da, gravity
+    orientation) resident in one FP64 batch with the benchmark's launch configuration
+    (autotuned single-step tiles, 64x8 two-step tiles): after two check intervals one sampled
+    instance of each size class matches the oracle to 1e-12."""
+    from paper_2102_12663_amd import serve as S
+    reqs = [S.sweep_request(i, aq.F64) for i in range(512)]
+    cache = S.ShapeCache()
+    b = aq.Batch(budget_bytes=96 << 30, max_slots=512, max_tiles=1 << 21)
+    slots = []
+    for i, (p, m, w) in enumerate(reqs):
+        tile = S.autotune_shape(cache, p, m, w)
+        slots.append(b.admit(p, m, w, tile=tile, tol=1e-30, max_steps=10 ** 9, request_id=i, keep=True))
+    assert all(s is not None for s in slots)
+    b.run(2)
+    for seed in (3, 16, 13, 4):            # 256x128, 512x256, 768x384, 1024x512
+        p, m, w = reqs[seed]
+        announce(f"[batch] sweep instance {seed} {p.nx}x{p.ny} vs the oracle")
+        o = O.Oracle(p, m, w).step(200)
+        g = [b.read_field(slots[seed], f) for f in ("p", "ux", "uy", "T")]
+        g[0] = g[0] - p.p_ref
+        err = field_errors(g, o.fields(), m, p.T_ref)
+        assert all(v <= 1e-12 for v in err.values()), (seed, err)
+    b.close()
