@@ -263,8 +263,9 @@ int aq_set_tile(aq_solver* s, int32_t tile_x, int32_t tile_y);
 int aq_time_step_kernel(aq_solver* s, int32_t n_launch, double* ms_per_launch);
 
 /* Two-steps-per-launch (temporal blocking) on the plain steps of each check interval: on
- * (enable != 0) or off.  The default is on for F64 and F32X, and for F32 and F16S when a step's working set
- * exceeds the last-level cache.  Results are bitwise the same either way. */
+ * (enable != 0) or off.  The default is on for F64 and F32X, and for F32 and F16S when a
+ * step's working set exceeds the last-level cache.  Results are bitwise the same either way.
+ * Batched instances always run two steps per launch. */
 int aq_set_fusion(aq_solver* s, int32_t enable);
 
 /*
