@@ -209,12 +209,11 @@ def batch_sweep(n=512, intervals=10, storages=("f32", "f16s", "f32x", "f64")):
     return out
 
 
-def serve_stream(rate=50.0, duration=60.0, time_limit=200.0):
+def serve_stream(rate=50.0, duration=60.0, time_limit=200.0, storage="f16s"):
     """The serving stream: sweep requests (every 10th a 2048x1024 eye) arriving as a Poisson
-    stream of `rate` per second for `duration` seconds, served by one batch in F16S storage
-    with the FP32 hand-off, residual 1e-6, until every request has finished or `time_limit`
-    seconds have passed.  Progress lines go to stderr."""
-    import paper_2102_12663_amd as aq
+    stream of `rate` per second for `duration` seconds, served by one batch in `storage`
+    (F16S with the FP32 hand-off by default), residual 1e-6, until every request has finished
+    or `time_limit` seconds have passed.  Progress lines go to stderr."""
     from paper_2102_12663_amd import serve as S
     done = [0]
 
@@ -223,11 +222,12 @@ def serve_stream(rate=50.0, duration=60.0, time_limit=200.0):
         if done[0] % 25 == 1:
             print(f"[serve] {done[0]} finished, {r['t_done']:.0f} s", file=sys.stderr, flush=True)
 
-    r = S.serve(rate=rate, duration=duration, storage=aq.F16S, tol=1e-6, budget_bytes=64 << 30,
+    r = S.serve(rate=rate, duration=duration, storage=STORAGES[storage], tol=1e-6, budget_bytes=64 << 30,
                 max_steps=300000, intervals_per_call=5, time_limit=time_limit, log=progress)
     r.pop("records")
+    form = "F16S with the FP32 hand-off" if storage == "f16s" else storage.upper()
     r["workload"] = (f"Poisson stream of sweep requests, {rate:g}/s for {duration:g} s (every 10th 2048x1024), "
-                     f"F16S with the FP32 hand-off, residual 1e-6, stopped at {time_limit:g} s")
+                     f"{form}, residual 1e-6, stopped at {time_limit:g} s")
     return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}
 
 
@@ -371,6 +371,8 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="only the Poisson serving stream (50 requests/s for 60 s, F16S with the FP32 hand-off, "
                          "stopped at 200 s); one JSON line, progress on stderr")
+    ap.add_argument("--serve-storage", default="f16s", choices=sorted(STORAGES),
+                    help="storage of the served solves with --serve")
     ap.add_argument("--batch-sweep", action="store_true",
                     help="only the 512-instance batched sweep (FP32, F16S, F32X and FP64 storage); one JSON line")
     args = ap.parse_args()
@@ -391,7 +393,7 @@ def main():
         print(json.dumps({"batch_sweep": batch_sweep()}), flush=True)
         return
     if args.serve:
-        print(json.dumps({"serve": serve_stream()}), flush=True)
+        print(json.dumps({"serve": serve_stream(storage=args.serve_storage)}), flush=True)
         return
     if args.precision_steady:
         print(json.dumps({"precision_steady": precision_steady()}), flush=True)
