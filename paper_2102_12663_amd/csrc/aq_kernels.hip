@@ -913,8 +913,8 @@ template <int MODE> struct Fuse {
     static constexpr int EN = EW * EH;                // step-A nodes
     static constexpr int NA = (EN + THREADS - 1) / THREADS;   // step-A nodes per thread
     // LDS image: h_1..h_8 and g_1..g_4 over tile + halo (planes 0..11); g_0 is only read
-    // by its own node, so it is kept for the tile nodes alone.  FP64 at TY = 4 then fits
-    // four blocks per CU.
+    // by its own node, so it is kept for the tile nodes alone: 67 KB in FP64, two blocks
+    // (16 waves) per CU.
     static constexpr int PLANES = 12;
     static constexpr int WORDS = PLANES * EN + 64 * TY;
     static_assert((TY * 64) % THREADS == 0, "step B covers the tile in whole passes");
