@@ -9,8 +9,10 @@ Pinned by the `-m "not gpu"` tests: equilibrium moment identities (eq. 7-9, 12-1
 forcing moments (eq. 17), exact mass conservation in closed boxes, shear-wave and
 heat-mode decay rates (eq. 10, 14), plane Poiseuille (eq. 16), linear conduction (eq. 3),
 the Darcy pressure drop (eq. 4), the Brinkman profile, mirror symmetry, the steady mass
-balance, the wall-shear-stress momentum balance, and the deviation-form rewrite against a
-literal absolute-form transcription.
+balance, the wall-shear-stress momentum balance, invariance under a uniform shift of the
+outlet and initial pressure (the outlet's p_out term), a closed box held at the inlet
+temperature (the INLET thermal branch), and the deviation form against a literal
+absolute-form statement of eq. 6-13 (tests/test_oracle_literal.py).
 """
 from __future__ import annotations
 

@@ -272,7 +272,9 @@ static void step_once(or_state* s)
     }
 
     /* (2) stream: poison the targets so an unwritten slot shows as NaN */
+#pragma omp parallel for schedule(static)
     for (size_t k = 0; k < 8 * n; k++) s->hn[k] = NAN;
+#pragma omp parallel for schedule(static)
     for (size_t k = 0; k < 5 * n; k++) s->gn[k] = NAN;
 
     double q_out = 0.0, q_in = 0.0;
