@@ -1,11 +1,18 @@
 """Benchmark of the fused collide-and-stream hot path on one MI355X.
 
-Workload: the 2048x1024 synthetic eye section (parameter-sweep draw, seed 0), FP64
-populations.  One benchmark step = one check interval: 99 plain time steps replayed
-from a HIP graph plus the reducing time step (IOP, fluxes, wall shear stress, residuals),
-i.e. every part of the per-step method.  Prints one JSON line.
+Headline workload: the batched parameter sweep of 512 eye sections (lattices 256x128 to
+1024x512, per-instance relaxation time, permeability, inflow, chamber angle, Rayleigh
+number and gravity orientation, all seeded), FP32 populations, resident in one batch.  One
+benchmark step = one check interval of every instance: 98 time steps as 49 two-step
+launches, one single step and the reducing step (IOP, fluxes, wall shear stress,
+residuals).  The timed steps are taken inside the full sweep, which then continues until
+every instance has reached its steady residual of 1e-6 (solves/s, p50/p99 latency).
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f64|f32|f16s]
+Further fields: the 8192x4096 eye in FP64, the 8192x4096 precision sweep, the 2048x1024 eye
+per storage, the Poisson serving stream with the one-at-a-time FP64 path beside it, and the
+oracle on the host cores.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 """
 import argparse
 import hashlib
@@ -20,7 +27,15 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS (flow+thermal) & HBM-roofline %; batched solves/s + p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 STORAGES = {"f64": 0, "f32": 1, "f16s": 2, "f32x": 3}
+# algorithmic HBM bytes per active node and launch: one read and one write of the 13 live
+# populations plus the type byte, whether the launch advances one time step or two (the
+# two-step kernel keeps the intermediate step in LDS)
+BYTES_PER_NODE_LAUNCH = {"f64": 209, "f32": 105, "f16s": 53, "f32x": 105}
 DTYPE = {"f64": "f64", "f32": "f32", "f16s": "f16 storage / f32 compute", "f32x": "f32 storage / f64 compute"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -32,9 +47,9 @@ def kernel_source_hash():
 
 
 def measured_traffic(key, kernel):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 PMC
-    summary, if it was taken on the current kernel source and the same kernel; else None."""
-    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    """HBM bytes per launch of a kernel from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source and the same kernel; else None."""
+    path = os.path.join(ROOT, "profiles", "kernel_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -45,58 +60,197 @@ def measured_traffic(key, kernel):
     return e.get("bytes_per_launch")
 
 
-def workload_key_of(args):
-    return f"eye{args.nx}x{args.ny}s{args.seed}/{args.storage}"
+def roofline(key, kernel, storage, active_nodes, launch_ms):
+    """Roofline of a launch that moves every population of `active_nodes` nodes once in and
+    once out (single step or two steps): algorithmic bytes over the live launch time, and
+    beside it the bytes the HBM counters saw (when committed for this kernel source)."""
+    bpl = BYTES_PER_NODE_LAUNCH[storage] * active_nodes
+    achieved = bpl / (launch_ms * 1e-3) / 1e9
+    traffic = measured_traffic(key, kernel)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+            "kernel_ms": round(launch_ms, 5), "bytes_per_launch": bpl,
+            "bytes_per_active_node_launch": BYTES_PER_NODE_LAUNCH[storage],
+            "counter_GBs": round(traffic / (launch_ms * 1e-3) / 1e9, 1) if traffic else None}
 
 
-def cpu_baseline(p, mask, walls, budget_s=12.0):
-    """The oracle, as it stands, on the host cores: time a bounded number of steps of the
-    same workload and convert to active MLUPS."""
+# ---------------------------------------------------------------------------------- oracle
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n_inst=8, budget_s=2.5):
+    """The oracle, as it stands, on the host cores, on a bounded sample of the headline
+    workload: the first n_inst requests of the sweep (two per lattice size), each stepped
+    for the same number of time steps, at all OpenMP threads and at one thread, median of
+    three timed runs after one warm-up step.  Active-node MLUPS."""
+    import numpy as np
     import aqinputs as A
     import oracle as O
+    from paper_2102_12663_amd import serve as S
+    reqs = [S.sweep_request(i, 0) for i in range(n_inst)]
+    act = sum(int(A.active(m).sum()) for _, m, _ in reqs)
+    all_threads = O.max_threads()
+    out = {}
+    for threads in (all_threads, 1):
+        O.set_threads(threads)
+        orcs = [O.Oracle(p, m, w) for p, m, w in reqs]
+        for o in orcs:
+            o.step(1)                                  # first touch
+        t0 = time.perf_counter()
+        for o in orcs:
+            o.step(1)
+        per_step = time.perf_counter() - t0
+        n = max(1, int(budget_s / max(per_step, 1e-6)))
+        runs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            for o in orcs:
+                o.step(n)
+            runs.append(act * n / (time.perf_counter() - t0) / 1e6)
+        out[threads] = (float(np.median(runs)), n)
+        del orcs
+    O.set_threads(all_threads)
+    v_all, n_all = out[all_threads]
+    v_one, n_one = out[1]
+    sizes = sorted({f"{p.nx}x{p.ny}" for p, _, _ in reqs})
+    return {"value": round(v_all, 2), "unit": "MLUPS", "cores": all_threads, "kind": "oracle",
+            "sample": f"the first {n_inst} requests of the 512-instance sweep ({', '.join(sizes)}; {act} active "
+                      f"nodes), {n_all} time steps each at {all_threads} threads and {n_one} at 1 thread; "
+                      f"median of 3 runs",
+            "single_thread": round(v_one, 2), "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    o = O.Oracle(p, mask, walls)
-    o.step(1)                       # first-touch
-    t0 = time.perf_counter()
-    o.step(4)
-    dt = (time.perf_counter() - t0) / 4
-    n = max(2, int(budget_s / max(dt, 1e-6)))
-    t0 = time.perf_counter()
-    o.step(n)
-    dt = time.perf_counter() - t0
-    act = int(A.active(mask).sum())
-    return {"value": act * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{n} time steps of the same 2048x1024 lattice ({act} active nodes), {dt:.1f} s"}
 
-
-def batched_vs_one_at_a_time(n, cap=200000, tol=1e-6):
-    """Solves/s and latency (all requests submitted at t = 0) of n sweep requests
-    (lattices 256x128 .. 1024x512, per-request tau, Da, inflow, angle, Ra, orientation):
-    continuously batched in F32 storage, and the same requests one at a time through the
-    single-lattice FP64 solver.  Each runs to residual tol or cap time steps."""
-    import numpy as np
+# ------------------------------------------------------------------------- headline: sweep
+def sweep512(steps, warmup, n=512, tol=1e-6, max_steps=200000, time_limit=240.0, storage="f32"):
+    """The batched sweep (all n requests submitted at t = 0, FP32, residual tol, at most
+    max_steps time steps each, tile shapes of the single steps from the autotuner): the
+    first `warmup` intervals untimed, then `steps` intervals timed with HIP events around
+    their two-step launches (the headline throughput and roofline), then the run continues
+    until every solve has finished (or time_limit).  The clock of the latencies starts
+    when the batch is complete, after the synthetic inputs have been built."""
+    import torch
+    import aqinputs as A
     import paper_2102_12663_amd as aq
     from paper_2102_12663_amd import serve as S
+    t_build = time.perf_counter()
+    reqs = [S.sweep_request(i, STORAGES[storage]) for i in range(n)]
+    act_all = sum(int(A.active(m).sum()) for _, m, _ in reqs)
+    log(f"sweep: {n} requests built in {time.perf_counter() - t_build:.1f} s, {act_all} active nodes")
+    timed = {}
 
-    res = S.sweep(n=n, storage=aq.F32, tol=tol, budget_bytes=16 << 30, max_steps=cap, intervals_per_call=5)
-    recs = res.pop("records")
-    lat, t0 = [], time.perf_counter()
-    conv = 0
-    for i in range(n):
-        p, m, w = S.sweep_request(i, aq.F64)
-        s = aq.Solver(p, m, w)
-        ok, _ = s.run_to_steady(tol, cap)
-        s.close()
-        conv += ok
-        lat.append(time.perf_counter() - t0)
+    def on_start(b):
+        b.run(warmup)
+        torch.cuda.synchronize()
+        info = b.info()
+        t0 = time.perf_counter()
+        total_ms, fused_ms, n_fused = b.run_timed(steps)
+        wall = time.perf_counter() - t0
+        timed.update(info=info, wall=wall, total_ms=total_ms, fused_ms=fused_ms, n_fused=n_fused)
+        log(f"sweep: timed {steps} intervals, {info['active_nodes']} active nodes, {wall:.3f} s")
+        return info["active_nodes"] * (warmup + steps) * 100
+
+    shapes = {}
+    cache = S.ShapeCache()
+
+    def make(i):
+        p, m, w = reqs[i]
+        shapes[(p.nx, p.ny)] = None
+        return p, m, w
+
+    r = S.run_requests(make, [0.0] * n, budget_bytes=S.default_budget(), max_slots=n, tol=tol,
+                       max_steps=max_steps, intervals_per_call=5, cache=cache, time_limit=time_limit,
+                       on_start=on_start)
+    r.pop("records")
+    info = timed["info"]
+    act = info["active_nodes"]
+    mlups = act * steps * 100 / timed["wall"] / 1e6
+    launch_ms = timed["fused_ms"] / timed["n_fused"]
+    kernel = f"batch_step2_kernel<{STORAGES[storage]}, {'true' if info['active_nodes'] * 105 > 192 * 2 ** 20 else 'false'}, false>"
+    tiles = {k[len("gfx950/1/"):]: "x".join(map(str, v)) for k, v in cache.d.items()}
+    return {"mlups": mlups, "wall": timed["wall"], "active_nodes": act, "running": info["running"],
+            "roofline": roofline(f"sweep512/{storage}", kernel, storage, act, launch_ms),
+            "tiles": tiles, "solve": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()},
+            "active_nodes_all": act_all}
+
+
+# ------------------------------------------------------------------------- other workloads
+def eye_run(storage, nx, ny, seed, steps, warmup, tm="resolved", bc=0, tile=(64, 4)):
+    """One eye lattice: `steps` check intervals timed after `warmup`, with HIP events around
+    the graph part of each interval (two-step launches when fusion is on)."""
+    import torch
+    import aqinputs as A
+    import paper_2102_12663_amd as aq
+    p, mask, walls, geo = A.sweep_instance(seed, nx, ny, storage=STORAGES[storage], tm=tm)
+    p.bc_scheme = bc
+    s = aq.Solver(p, mask, walls)
+    s.set_tile(*tile)
+    info = s.info()
+    D = info["check_interval"]
+    if warmup:
+        s.run_intervals_timed(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total_ms, plain_ms = s.run_intervals_timed(steps)
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return {"workload": f"{n} sweep requests (seeds 0..{n - 1}), residual {tol}, cap {cap} time steps",
-            "batched_f32": {"solves_per_s": round(res["solves_per_s"], 3), "p50_s": round(res["latency_p50_s"], 3),
-                            "p99_s": round(res["latency_p99_s"], 3), "converged": res["converged"],
-                            "aggregate_active_mlups": round(res["aggregate_active_mlups"], 1)},
-            "one_at_a_time_f64": {"solves_per_s": round(n / wall, 3), "p50_s": round(float(np.percentile(lat, 50)), 3),
-                                  "p99_s": round(float(np.percentile(lat, 99)), 3), "converged": int(conv)}}
+    ob = s.observe()
+    s.close()
+    act = info["active_nodes"]
+    launch_ms = plain_ms / (steps * info["graph_launches"])
+    nt = "true" if info["nt_store"] else "false"
+    bcs = "true" if bc else "false"
+    kernel = (f"step2_kernel<{STORAGES[storage]}, {nt}, {bcs}>" if info["fusion"]
+              else f"step_kernel<{STORAGES[storage]}, false, {nt}, {bcs}>")
+    return {"mlups": act * steps * D / wall / 1e6, "wall": wall, "active_nodes": act, "launch_ms": launch_ms,
+            "kernel": kernel, "steps_per_launch": 2 if info["fusion"] else 1, "obs": ob, "geo": geo, "p": p}
+
+
+def brief(e, storage, key):
+    r = roofline(key, e["kernel"], storage, e["active_nodes"], e["launch_ms"])
+    return {"mlups": round(e["mlups"], 1), "kernel": e["kernel"], "time_steps_per_launch": e["steps_per_launch"],
+            "kernel_ms": r["kernel_ms"], "achieved_GBs": r["achieved"], "frac": r["frac"], "traffic": r["traffic"]}
+
+
+def precision_sweep(steps=20000, nx=8192, ny=4096, seed=0):
+    """The 8192x4096 eye (sweep draw seed 0) for `steps` time steps in each storage, from
+    the same initial state: active MLUPS, and the IOP and velocity errors of FP32, F16S and
+    F32X storage against the FP64 run on the GPU (velocity: L2 over active nodes, relative).
+    A transient: the slowest mode of this chamber needs ~1e7 steps."""
+    import numpy as np
+    import aqinputs as A
+    import paper_2102_12663_amd as aq
+    out = {"workload": f"{nx}x{ny} eye section (sweep draw seed {seed}), {steps} time steps per storage"}
+    ref = None
+    p0, mask, walls, geo = A.sweep_instance(seed, nx, ny)
+    on = A.active(mask)
+    for st in ("f64", "f32", "f16s", "f32x"):
+        p = A.Params(**{**p0.asdict(), "storage": STORAGES[st]})
+        s = aq.Solver(p, mask, walls)
+        D = s.info()["check_interval"]
+        t0 = time.perf_counter()
+        s.run_intervals_timed(steps // D)
+        wall = time.perf_counter() - t0
+        act = s.info()["active_nodes"]
+        ob = s.observe()
+        ux, uy = s.read_field("ux"), s.read_field("uy")
+        s.close()
+        e = {"mlups": round(act * steps / wall / 1e6, 1), "iop_gauge": ob["iop_gauge"]}
+        if ref is None:
+            ref = (ob["iop_gauge"], ux[on], uy[on])
+        else:
+            du = np.sqrt(np.sum((ux[on] - ref[1]) ** 2 + (uy[on] - ref[2]) ** 2))
+            e["velocity_l2_rel"] = float(du / np.sqrt(np.sum(ref[1] ** 2 + ref[2] ** 2)))
+            e["iop_rel"] = abs(ob["iop_gauge"] - ref[0]) / abs(ref[0])
+        out[st] = e
+    return out
 
 
 def precision_steady(cases=((512, 256, 3), (512, 256, 5), (1024, 512, 6), (2048, 1024, 3)), tol=1e-9):
@@ -130,105 +284,96 @@ def precision_steady(cases=((512, 256, 3), (512, 256, 5), (1024, 512, 6), (2048,
     return out
 
 
-def shard_slabs(n=8, nx=8192, ny=4096, seed=0, intervals=10):
-    """The design's decomposition of one large lattice over n GPUs, measured one slab at a time
-    on this GPU: the 8192x4096 eye (sweep draw seed 0) cut along x where the cumulative active
-    node count reaches k/n of the total (a cut along y would leave the GPUs above the chamber
-    idle).  Each slab runs alone as its own lattice (its cut columns closed by a solid column,
-    FP64, the benchmark's interval); the slowest slab sets the time step of the n-GPU run, whose
-    projected throughput ignores the face exchange (4 populations per face node per step)."""
+def config1_steady(seed=0, nx=2048, ny=1024):
+    """The 2048x1024 eye run to its steady state as the workload states it: FP64 to a
+    residual of 1e-8 and FP32 to 1e-6, each on its own; IOP, cornea and iris mean / max wall
+    shear stress (section 3.6), and the velocity L2 of the FP32 state against FP64."""
     import numpy as np
     import aqinputs as A
     import paper_2102_12663_amd as aq
-    p, mask, walls, geo = A.sweep_instance(seed, nx, ny)
+    p0, mask, walls, geo = A.sweep_instance(seed, nx, ny)
     act = A.active(mask)
-    total = int(act.sum())
-    c = np.cumsum(act.sum(axis=0))
-    cuts = [0] + [int(np.searchsorted(c, total * k / n)) for k in range(1, n)] + [nx]
-    slabs = []
-    for i in range(n):
-        x0, x1 = max(cuts[i] - 1, 0), min(cuts[i + 1] + 1, nx)   # one halo column each side
-        m = np.ascontiguousarray(mask[:, x0:x1])
-        m[:, 0] = A.encode(A.SOLID)
-        m[:, -1] = A.encode(A.SOLID)
-        q = A.Params(**{**p.asdict(), "nx": x1 - x0})
-        s = aq.Solver(q, m, A.no_walls())
-        s.run_intervals_timed(1)
+    out = {"workload": f"{nx}x{ny} eye (sweep draw seed {seed}), FP64 to 1e-8, FP32 to 1e-6"}
+    f64 = None
+    keys = ("iop_gauge", "wss_cornea_mean", "wss_cornea_max", "wss_iris_mean", "wss_iris_max", "u_max")
+    for st, tol in (("f64", 1e-8), ("f32", 1e-6)):
+        s = aq.Solver(A.Params(**{**p0.asdict(), "storage": STORAGES[st]}), mask, walls)
         t0 = time.perf_counter()
-        s.run_intervals_timed(intervals)
+        ok, ob = s.run_to_steady(tol, 6_000_000)
         wall = time.perf_counter() - t0
-        a = s.info()["active_nodes"]
+        f = s.fields()
         s.close()
-        slabs.append({"columns": [cuts[i], cuts[i + 1]], "active_nodes": a,
-                      "ms_per_interval": round(wall * 1e3 / intervals, 4)})
-    slowest = max(e["ms_per_interval"] for e in slabs)
-    return {"workload": f"{nx}x{ny} eye (sweep draw seed {seed}, {total} active nodes) in {n} x-slabs balanced "
-                        f"by active nodes, FP64, {intervals} check intervals of 100 time steps per slab",
-            "slabs": slabs, "slowest_ms_per_interval": slowest,
-            "projected_mlups": round(total * 100 / (slowest * 1e-3) / 1e6, 1),
-            "y_slab_imbalance": round(max(int(act[k * ny // n:(k + 1) * ny // n].sum()) for k in range(n)) * n / total, 3)}
-
-
-def batch_sweep(n=512, intervals=10, storages=("f32", "f16s", "f32x", "f64")):
-    """The batched parameter sweep: n instances of the sweep distribution (lattices
-    256x128 .. 1024x512, per-instance tau, Da, inflow, angle, Ra, gravity orientation) resident
-    in one batch and stepped together, per storage, with the single-step tile of each size
-    class from the autotuner (two-step launches use the fixed 64x8 tiles).  Aggregate active-node MLUPS over
-    `intervals` check intervals (after two warm-up intervals; residual target 1e-30 so no
-    instance retires) and its fraction of the HBM roofline for the algorithmic bytes."""
-    import torch
-    import aqinputs as A
-    import paper_2102_12663_amd as aq
-    from paper_2102_12663_amd import serve as S
-    reqs = [S.sweep_request(i, aq.F32) for i in range(n)]
-    act = sum(int(A.active(m).sum()) for _, m, _ in reqs)
-    out = {"workload": f"{n} sweep requests (seeds 0..{n - 1}), {act} active nodes, "
-                       f"{intervals} check intervals of 100 time steps"}
-    for st in storages:
-        cache = S.ShapeCache()
-        shapes = set()
-        b = aq.Batch(budget_bytes=96 << 30, max_slots=n, max_tiles=1 << 21)
-        for p, m, w in reqs:
-            p = A.Params(**{**p.asdict(), "storage": STORAGES[st]})
-            tile = S.autotune_shape(cache, p, m, w)       # single-step tile of the size class
-            shapes.add((p.nx, p.ny, tile))
-            b.admit(p, m, w, tile=tile, tol=1e-30, max_steps=10 ** 9)
-        b.run(2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        b.run(intervals)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        info = b.info()
-        b.close()
-        mlups = act * intervals * 100 / wall / 1e6
-        bpu = {"f64": 209, "f32": 105, "f16s": 53, "f32x": 105}[st]
-        out[st] = {"mlups": round(mlups, 1), "achieved_GBs": round(mlups * bpu / 1e3, 1),
-                   "frac": round(mlups * bpu / 1e3 / HBM_PEAK_GBS, 4), "running_after": info["running"],
-                   "tiles": {f"{x}x{y}": f"{t[0]}x{t[1]}" for x, y, t in sorted(shapes)}}
+        e = {"converged": bool(ok), "steps": ob["step"], "seconds": round(wall, 2), **{k: ob[k] for k in keys}}
+        if f64 is None:
+            f64 = (f, ob)
+        else:
+            den = np.sqrt(np.sum(f64[0][1][act] ** 2 + f64[0][2][act] ** 2))
+            e["velocity_l2_rel"] = float(np.sqrt(np.sum((f[1][act] - f64[0][1][act]) ** 2 +
+                                                       (f[2][act] - f64[0][2][act]) ** 2)) / den)
+            for k in keys:
+                e[k + "_rel"] = abs(ob[k] - f64[1][k]) / abs(f64[1][k])
+        out[st] = e
     return out
 
 
-def serve_stream(rate=50.0, duration=60.0, time_limit=200.0, storage="f16s"):
-    """The serving stream: sweep requests (every 10th a 2048x1024 eye) arriving as a Poisson
-    stream of `rate` per second for `duration` seconds, served by one batch in `storage`
-    (F16S with the FP32 hand-off by default), residual 1e-6, until every request has finished
-    or `time_limit` seconds have passed.  Progress lines go to stderr."""
+def serve_stream(rate=50.0, duration=60.0, time_limit=150.0, storage="f16s", max_active_nodes=8_000_000,
+                 n_sample=12, sample_steps=200000):
+    """The serving stream (Poisson arrivals, every 10th request a 2048x1024 eye, residual
+    1e-6, F16S with the IOP drift check and the F32 hand-off), the arena sized to the free
+    HBM, admission capped at max_active_nodes running active nodes, stopped at time_limit
+    seconds; beside it the one-at-a-time FP64 path on the same stream from n_sample
+    requests solved alone (evenly spaced over the stream)."""
     from paper_2102_12663_amd import serve as S
+    import paper_2102_12663_amd as aq
     done = [0]
 
     def progress(r):
         done[0] += 1
-        if done[0] % 25 == 1:
-            print(f"[serve] {done[0]} finished, {r['t_done']:.0f} s", file=sys.stderr, flush=True)
+        if done[0] % 50 == 1:
+            log(f"serve: {done[0]} finished, {r['t_done']:.0f} s")
 
-    r = S.serve(rate=rate, duration=duration, storage=STORAGES[storage], tol=1e-6, budget_bytes=64 << 30,
-                max_steps=300000, intervals_per_call=5, time_limit=time_limit, log=progress)
+    r = S.serve(rate=rate, duration=duration, storage=STORAGES[storage], tol=1e-6, max_steps=sample_steps,
+                intervals_per_call=5, time_limit=time_limit, max_active_nodes=max_active_nodes, log=progress)
     r.pop("records")
+    arr = S.stream_arrivals(rate, duration)
+    step = max(1, len(arr) // n_sample)
+    sample = list(range(0, len(arr), step))[:n_sample]
+    log(f"serve: one-at-a-time FP64 on {len(sample)} sampled requests")
+    base = S.one_at_a_time(lambda i: S.sweep_request(1000 + i, aq.F64, large_every=10), arr, sample,
+                           tol=1e-6, max_steps=sample_steps, storage=aq.F64, t_stop=time_limit)
     form = "F16S with the FP32 hand-off" if storage == "f16s" else storage.upper()
-    r["workload"] = (f"Poisson stream of sweep requests, {rate:g}/s for {duration:g} s (every 10th 2048x1024), "
-                     f"{form}, residual 1e-6, stopped at {time_limit:g} s")
-    return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}
+    out = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}
+    out["workload"] = (f"Poisson stream of sweep requests, {rate:g}/s for {duration:g} s (every 10th 2048x1024), "
+                       f"{form}, residual 1e-6, cap {sample_steps} steps, at most {max_active_nodes} active nodes "
+                       f"running, stopped at {time_limit:g} s")
+    out["one_at_a_time_f64"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in base.items()}
+    return out
+
+
+def dense_box(storages, intervals=10, nx=8192, ny=4096):
+    """An 8192x4096 closed box, every interior node active (heated floor, cooled lid,
+    buoyancy on), per storage: active MLUPS and the roofline of the graph-part launches."""
+    import aqinputs as A
+    import paper_2102_12663_amd as aq
+    mask = A.box_mask(nx, ny, wall_ids=(A.WALL_IRIS, A.WALL_CORNEA, A.WALL_BOX, A.WALL_BOX))
+    out = {"workload": f"{nx}x{ny} closed box, {(nx - 2) * (ny - 2)} active nodes, heated floor, "
+                       f"{intervals} check intervals of 100 time steps"}
+    for st in storages:
+        p = A.Params(nx=nx, ny=ny, gbeta=1e-6, storage=STORAGES[st], check_interval=100)
+        s = aq.Solver(p, mask, A.no_walls())
+        s.run_intervals_timed(1)
+        t0 = time.perf_counter()
+        total_ms, plain_ms = s.run_intervals_timed(intervals)
+        wall = time.perf_counter() - t0
+        info = s.info()
+        s.close()
+        act = info["active_nodes"]
+        launch_ms = plain_ms / (intervals * info["graph_launches"])
+        r = roofline(f"box{nx}x{ny}/{st}", "?", st, act, launch_ms)
+        out[st] = {"mlups": round(act * intervals * 100 / wall / 1e6, 1), "kernel_ms": r["kernel_ms"],
+                   "time_steps_per_launch": 2 if info["fusion"] else 1, "achieved_GBs": r["achieved"],
+                   "frac": r["frac"]}
+    return out
 
 
 def outflow_area(mask):
@@ -266,8 +411,6 @@ def calibration_workload(n=12, cap=400000):
         p.gbeta = 0.0                      # Ra = 0: the secretion-driven steady state
         nu = (2 * p.tau_f - 1) / 6
         area = outflow_area(mask)
-        # meshwork permeability for which the explicit coupling contracts the IOP error by
-        # 0.6 per check interval (D r = 0.4, r = 3 A K / (5 N nu h))
         p.K_tm = 0.4 * 5 * int(A.active(mask).sum()) * nu * p.h_tm / (3 * area * p.check_interval)
         q_in = p.u_in_y * (geo.inlet_cols[1] - geo.inlet_cols[0] + 1)
         targets.append(1.25 * nu * p.h_tm * q_in / (p.K_tm * area))
@@ -283,244 +426,144 @@ def calibration_workload(n=12, cap=400000):
     return out
 
 
-def dense_box(storages, intervals=10, nx=8192, ny=4096):
-    """The dense variant of the largest lattice: an 8192x4096 closed box, every interior node
-    active (heated floor, cooled lid, buoyancy on), per storage: active MLUPS and the
-    algorithmic bandwidth of the launches that make up the graph part of an interval."""
+def probe(kind, storage):
+    """Short program for hardware-counter runs: a few launches of one workload's dominant
+    kernel, then three device copies of 256 MiB (a copy kernel of known size, the
+    calibration of the byte counters)."""
+    import torch
     import aqinputs as A
     import paper_2102_12663_amd as aq
-    mask = A.box_mask(nx, ny, wall_ids=(A.WALL_IRIS, A.WALL_CORNEA, A.WALL_BOX, A.WALL_BOX))
-    out = {"workload": f"{nx}x{ny} closed box, {(nx - 2) * (ny - 2)} active nodes, heated floor, "
-                       f"{intervals} check intervals of 100 time steps"}
-    for st in storages:
-        p = A.Params(nx=nx, ny=ny, gbeta=1e-6, storage=STORAGES[st], check_interval=100)
-        s = aq.Solver(p, mask, A.no_walls())
-        s.run_intervals_timed(1)
-        t0 = time.perf_counter()
-        total_ms, plain_ms = s.run_intervals_timed(intervals)
-        wall = time.perf_counter() - t0
-        info = s.info()
-        s.close()
-        act = info["active_nodes"]
-        spl = 2 if info["fusion"] else 1
-        launch_ms = plain_ms / (intervals * info["graph_launches"])
-        gbs = info["bytes_per_node_update"] * act * spl / (launch_ms * 1e-3) / 1e9
-        out[st] = {"mlups": round(act * intervals * 100 / wall / 1e6, 1), "kernel_ms": round(launch_ms, 4),
-                   "time_steps_per_launch": spl, "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    return out
-
-
-def precision_sweep(steps=20000, nx=8192, ny=4096, seed=0):
-    """The 8192x4096 eye (sweep draw seed 0) for `steps` time steps in each storage, from
-    the same initial state: active MLUPS, and the IOP and velocity errors of FP32, F16S and
-    F32X storage against the FP64 run on the GPU (velocity: L2 over active nodes, relative)."""
-    import numpy as np
-    import aqinputs as A
-    import paper_2102_12663_amd as aq
-    out = {"workload": f"{nx}x{ny} eye section (sweep draw seed {seed}), {steps} time steps per storage"}
-    ref = None
-    p0, mask, walls, geo = A.sweep_instance(seed, nx, ny)
-    for st in ("f64", "f32", "f16s", "f32x"):
-        p = A.Params(**{**p0.asdict(), "storage": STORAGES[st]})
+    from paper_2102_12663_amd import serve as S
+    if kind == "sweep512":
+        reqs = [S.sweep_request(i, STORAGES[storage]) for i in range(512)]
+        b = aq.Batch(budget_bytes=S.default_budget(), max_slots=512, max_tiles=1 << 21)
+        cache = S.ShapeCache()
+        for p, m, w in reqs:
+            b.admit(p, m, w, tile=S.autotune_shape(cache, p, m, w), tol=1e-30, max_steps=10 ** 9)
+        b.run(1)
+        act = b.info()["active_nodes"]
+        b.close()
+    else:
+        nx, ny = (int(v) for v in kind[3:].split("x"))
+        p, mask, walls, geo = A.sweep_instance(0, nx, ny, storage=STORAGES[storage])
         s = aq.Solver(p, mask, walls)
-        D = s.info()["check_interval"]
-        t0 = time.perf_counter()
-        s.run_intervals_timed(steps // D)
-        wall = time.perf_counter() - t0
-        act = s.info()["active_nodes"]
-        ob = s.observe()
-        ux, uy = s.read_field("ux"), s.read_field("uy")
-        s.close()
-        on = A.active(mask)
-        e = {"mlups": round(act * steps / wall / 1e6, 1), "iop_gauge": ob["iop_gauge"]}
-        if ref is None:
-            ref = (ob["iop_gauge"], ux[on], uy[on])
+        if s.info()["fusion"]:
+            s.time_fused_kernel(10)
         else:
-            du = np.sqrt(np.sum((ux[on] - ref[1]) ** 2 + (uy[on] - ref[2]) ** 2))
-            e["velocity_l2_rel"] = float(du / np.sqrt(np.sum(ref[1] ** 2 + ref[2] ** 2)))
-            e["iop_rel"] = abs(ob["iop_gauge"] - ref[0]) / abs(ref[0])
-        out[st] = e
-    return out
+            s.time_step_kernel(10)
+        act = s.info()["active_nodes"]
+        s.close()
+    x = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": f"{kind}/{storage}", "active_nodes": act, "kernel_hash": kernel_source_hash(),
+                      "copy_bytes": 256 << 20}), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100, help="timed check intervals (100 time steps each)")
+    ap.add_argument("--steps", type=int, default=20, help="timed check intervals of the 512-instance batch")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--storage", default="f64", choices=sorted(STORAGES))
-    ap.add_argument("--nx", type=int, default=2048)
-    ap.add_argument("--ny", type=int, default=1024)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--tile", default="64x4")
+    ap.add_argument("--quick", action="store_true", help="only the headline (the batch throughput)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true",
-                    help="skip the other storages, the lumped-outlet and paper-boundary variants of the "
-                         "workload, the dense 8192x4096 box and the 8192x4096 precision sweep")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batched-requests", type=int, default=16)
-    ap.add_argument("--probe", action="store_true",
-                    help="for hardware-counter runs: 10 launches of the plain step kernel of the workload "
-                         "(two-step kernel when fusion is on), then "
-                         "3 device copies of 256 MiB (a copy kernel of known size for calibration)")
-    ap.add_argument("--probe-single", action="store_true",
-                    help="with --probe: the single-step kernel even where the solver runs two steps per launch")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--extra", action="store_true",
+                    help="also the dense 8192x4096 box, the lumped-outlet and paper-boundary variants of "
+                         "the 2048x1024 eye and the thickness calibration")
     ap.add_argument("--precision-steady", action="store_true",
-                    help="only the steady-state precision comparison of FP32, F16S and F32X against FP64 "
-                         "(four sweep draws, 512x256 to 2048x1024); one JSON line")
-    ap.add_argument("--serve", action="store_true",
-                    help="only the Poisson serving stream (50 requests/s for 60 s, F16S with the FP32 hand-off, "
-                         "stopped at 200 s); one JSON line, progress on stderr")
-    ap.add_argument("--serve-storage", default="f16s", choices=sorted(STORAGES),
-                    help="storage of the served solves with --serve")
-    ap.add_argument("--batch-sweep", action="store_true",
-                    help="only the 512-instance batched sweep (FP32, F16S, F32X and FP64 storage); one JSON line")
+                    help="only the steady-state precision comparison of FP32, F16S and F32X against FP64")
+    ap.add_argument("--config1-steady", action="store_true",
+                    help="only the 2048x1024 steady state (FP64 to 1e-8, FP32 to 1e-6) with IOP and WSS")
+    ap.add_argument("--serve", action="store_true", help="only the serving stream")
+    ap.add_argument("--probe", default=None, metavar="KIND",
+                    help="hardware-counter program: 'sweep512' or 'eyeNXxNY' (with --storage)")
+    ap.add_argument("--storage", default="f32", choices=sorted(STORAGES))
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
-              "decomposition is design-only", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): every workload here fits one "
+              "MI355X, and the multi-GPU decomposition is a design, not a measured path", file=sys.stderr)
         sys.exit(2)
 
     import torch
-    import aqinputs as A
-    import paper_2102_12663_amd as aq
-
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    tx, ty = (int(v) for v in args.tile.split("x"))
-    if args.batch_sweep:
-        print(json.dumps({"batch_sweep": batch_sweep()}), flush=True)
-        return
-    if args.serve:
-        print(json.dumps({"serve": serve_stream(storage=args.serve_storage)}), flush=True)
+    if args.probe:
+        probe(args.probe, args.storage)
         return
     if args.precision_steady:
         print(json.dumps({"precision_steady": precision_steady()}), flush=True)
         return
-    if args.probe:
-        p, mask, walls, geo = A.sweep_instance(args.seed, args.nx, args.ny, storage=STORAGES[args.storage])
-        s = aq.Solver(p, mask, walls)
-        s.set_tile(tx, ty)
-        if args.probe_single or not s.info()["fusion"]:
-            s.time_step_kernel(10)
-        else:
-            s.time_fused_kernel(10)
-        x = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
-        y = torch.empty_like(x)
-        x.fill_(1)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        info = s.info()
-        print(json.dumps({"probe": workload_key_of(args), "active_nodes": info["active_nodes"],
-                          "bytes_per_node_update": info["bytes_per_node_update"],
-                          "kernel_hash": kernel_source_hash(), "copy_bytes": 256 << 20}), flush=True)
+    if args.config1_steady:
+        print(json.dumps({"config1_steady": config1_steady()}), flush=True)
+        return
+    if args.serve:
+        print(json.dumps({"serve": serve_stream()}), flush=True)
         return
 
-    def run(storage_name, steps, warmup, tm="resolved", bc=0):
-        p, mask, walls, geo = A.sweep_instance(args.seed, args.nx, args.ny,
-                                               storage=STORAGES[storage_name], tm=tm)
-        p.bc_scheme = bc
-        s = aq.Solver(p, mask, walls)
-        s.set_tile(tx, ty)
-        info = s.info()
-        D = info["check_interval"]
-        if warmup:
-            s.run_intervals_timed(warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        total_ms, plain_ms = s.run_intervals_timed(steps)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ob = s.observe()
-        # vortex diagnostics (eq. 18) of the final state, on demand, outside the timed region
-        dg = s.diagnose()
-        t1 = time.perf_counter()
-        for _ in range(5):
-            dg = s.diagnose()
-        dg["ms_per_call"] = (time.perf_counter() - t1) * 1e3 / 5
-        s.close()
-        act = info["active_nodes"]
-        mlups = act * steps * D / wall / 1e6
-        # the graph part of every interval is graph_launches launches of one kernel: the
-        # two-step kernel when fusion is on (2 node updates per active node per launch)
-        launch_ms = plain_ms / (steps * info["graph_launches"])
-        steps_per_launch = 2 if info["fusion"] else 1
-        nt = "true" if info["nt_store"] else "false"
-        bcs = "true" if bc else "false"
-        kernel = (f"step2_kernel<{STORAGES[storage_name]}, {nt}, {bcs}> (two time steps per launch)" if info["fusion"]
-                  else f"step_kernel<{STORAGES[storage_name]}, false, {nt}, {bcs}>")
-        achieved = info["bytes_per_node_update"] * act * steps_per_launch / (launch_ms * 1e-3) / 1e9
-        return dict(p=p, mask=mask, walls=walls, geo=geo, info=info, wall=wall, total_ms=total_ms,
-                    launch_ms=launch_ms, steps_per_launch=steps_per_launch, kernel=kernel,
-                    achieved=achieved, mlups=mlups, obs=ob, D=D, diag=dg)
-
-    r = run(args.storage, args.steps, args.warmup)
-    info, D = r["info"], r["D"]
-    act = info["active_nodes"]
-    bpu = info["bytes_per_node_update"]
-    achieved = r["achieved"]
-    traffic = measured_traffic(workload_key_of(args), r["kernel"])
+    t_start = time.perf_counter()
+    sw = sweep512(args.steps, args.warmup, time_limit=20.0 if args.quick else 240.0)
+    log(f"sweep done at {time.perf_counter() - t_start:.0f} s")
+    solve = sw["solve"]
     out = {
         "metric": METRIC,
-        "value": round(r["mlups"], 2),
+        "value": round(sw["mlups"], 2),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(r["wall"] * 1e3 / args.steps, 4),
+        "ms_per_step": round(sw["wall"] * 1e3 / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": DTYPE[args.storage],
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"synthetic eye section {args.nx}x{args.ny} (sweep draw seed {args.seed}: "
-                               f"alpha {r['geo'].alpha_deg:.2f} deg, u_in {r['p'].u_in_y:.3e}), "
-                               f"{args.storage} populations, one step = {D} time steps incl. the reducing step",
-                   "nx": args.nx, "ny": args.ny, "active_nodes": act, "lattice_nodes": info["lattice_nodes"],
-                   "time_steps_per_step": D, "tile": f"{info['tile_x']}x{info['tile_y']}",
-                   "storage": args.storage, "parallelism": "single GPU"},
-        "lattice_mlups": round(info["lattice_nodes"] * args.steps * D / r["wall"] / 1e6, 2),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "kernel": r["kernel"],
-                     "kernel_ms": round(r["launch_ms"], 5),
-                     "bytes_per_launch": bpu * act * r["steps_per_launch"],
-                     "bytes_per_active_node_update": bpu,
-                     # what the counters say the launch really moves, at the live launch time
-                     "measured_hbm_GBs": (round(traffic / (r["launch_ms"] * 1e-3) / 1e9, 1)
-                                          if traffic else None)},
-        "observables": {k: r["obs"][k] for k in ("step", "iop_gauge", "q_in", "q_out", "resid_u", "u_max")},
-        "diagnostics": {k: (round(v, 4) if k == "ms_per_call" else v) for k, v in r["diag"].items()},
+        "config": {"workload": f"batched parameter sweep: 512 synthetic eye sections (seeds 0..511, lattices "
+                               f"256x128 to 1024x512, per-instance tau, Da, inflow, chamber angle, Ra and gravity "
+                               f"orientation) resident in one batch, f32 populations; one step = one check interval "
+                               f"(100 time steps incl. the reducing step) of every instance",
+                   "instances": sw["running"], "active_nodes": sw["active_nodes"], "time_steps_per_step": 100,
+                   "storage": "f32", "single_step_tiles": sw["tiles"], "parallelism": "single GPU"},
+        "roofline": sw["roofline"],
+        "sweep512": {"workload": "the same 512 requests, each to a steady residual of 1e-6 (cap 200000 steps), "
+                                 "all submitted at t = 0, continuously batched",
+                     "solves_per_s": solve["solves_per_s"], "finished_per_s": solve["finished_per_s"],
+                     "p50_s": solve["latency_p50_s"], "p99_s": solve["latency_p99_s"],
+                     "latency_is_lower_bound": solve["latency_is_lower_bound"],
+                     "converged": solve["converged"], "not_converged": solve["not_converged"],
+                     "diverged": solve["diverged"], "unfinished": solve["unfinished"], "wall_s": solve["wall_s"],
+                     "aggregate_active_mlups": solve["aggregate_active_mlups"]},
     }
-    if not args.no_extra:
-        def brief(e):
-            return {"mlups": round(e["mlups"], 1), "kernel": e["kernel"], "kernel_ms": round(e["launch_ms"], 5),
-                    "achieved_GBs": round(e["achieved"], 1), "frac": round(e["achieved"] / HBM_PEAK_GBS, 4)}
-        extra = {}
-        for st in ("f32", "f16s", "f32x", "f64"):
-            if st != args.storage:
-                extra[st] = brief(run(st, args.steps, args.warmup))
-        out["other_storages"] = extra
-        # the same section with the lumped meshwork outlet (seepage speed re-evaluated at
-        # every check step by the finish kernel)
-        e = run(args.storage, args.steps, args.warmup, tm="lumped")
-        out["lumped_outlet"] = {**brief(e), "iop_gauge": e["obs"]["iop_gauge"], "u_seep": e["obs"]["u_seep"]}
-        # the same section with the paper's boundary schemes (interpolated bounce-back,
-        # extrapolated inlet / outlet and thermal walls)
-        e = run(args.storage, args.steps, args.warmup, bc=1)
-        out["paper_boundaries"] = {**brief(e), "iop_gauge": e["obs"]["iop_gauge"]}
-        out["dense_box"] = dense_box(("f64", "f32", "f16s", "f32x"))
+    if not args.quick:
+        log("fp64 8192x4096")
+        e = eye_run("f64", 8192, 4096, 0, 10, 2)
+        r = roofline("eye8192x4096s0/f64", e["kernel"], "f64", e["active_nodes"], e["launch_ms"])
+        out["fp64_8192x4096"] = {"workload": "8192x4096 eye section (sweep draw seed 0), f64, 10 check intervals",
+                                 "mlups": round(e["mlups"], 1), "active_nodes": e["active_nodes"], "roofline": r}
+        log("2048x1024 per storage")
+        out["eye2048x1024"] = {st: brief(eye_run(st, 2048, 1024, 0, 20, 2), st, f"eye2048x1024s0/{st}")
+                               for st in ("f64", "f32", "f16s", "f32x")}
+        log("precision sweep")
         out["precision_sweep"] = precision_sweep()
-        out["shard_slabs"] = shard_slabs()
-    if not args.no_batched:
-        out["batch_sweep"] = batch_sweep()
-        out["batched"] = batched_vs_one_at_a_time(args.batched_requests)
-        out["calibration"] = calibration_workload()
+        if not args.no_serve:
+            log("serving stream")
+            out["serve"] = serve_stream()
+        if args.extra:
+            out["dense_box"] = dense_box(("f64", "f32", "f16s", "f32x"))
+            e = eye_run("f64", 2048, 1024, 0, 20, 2, tm="lumped")
+            out["lumped_outlet"] = {**brief(e, "f64", "eye2048x1024s0/f64-lumped"), "iop_gauge": e["obs"]["iop_gauge"],
+                                    "u_seep": e["obs"]["u_seep"]}
+            e = eye_run("f64", 2048, 1024, 0, 20, 2, bc=1)
+            out["paper_boundaries"] = {**brief(e, "f64", "eye2048x1024s0/f64-paper"), "iop_gauge": e["obs"]["iop_gauge"]}
+            out["calibration"] = calibration_workload()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(r["p"], r["mask"], r["walls"])
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline()
+    out["bench_seconds"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out), flush=True)
 
 

@@ -332,11 +332,17 @@ int aq_run_intervals_timed(aq_solver* s, int32_t n_intervals, double* total_ms,
  * ------------------------------------------------------------------------------------ */
 typedef struct aq_batch aq_batch;
 
-/* A finished request.  status: AQ_OK (residual below tol), AQ_ENOTCONVERGED (max_steps),
- * AQ_EDIVERGED (non-finite moments), or AQ_ENOMEM when an F16S solve failed the drift
- * check and no memory was free for its F32 continuation.  storage: the storage the final
- * state is held in; fallback: 1 when an F16S solve failed the IOP drift check and was
- * continued in F32 storage. */
+/* Result status of an F16S solve accepted at binary16's rounding floor (not an error
+ * code; only aq_result.status takes it): its residual stopped above tol, and its IOP
+ * (iop_gauge) moved by at most drift_tol, relative, against the IOP at least 1000 steps
+ * earlier (the IOP drift check). */
+enum { AQ_RESULT_FLOOR = 1 };
+
+/* A finished request.  status: AQ_OK (residual below tol), AQ_RESULT_FLOOR (F16S, above),
+ * AQ_ENOTCONVERGED (max_steps), AQ_EDIVERGED (non-finite moments), or AQ_EDEVICE if the
+ * F16S -> F32 hand-off failed on the device.  storage: the storage the final state is held
+ * in; fallback: 1 when an F16S solve failed the IOP drift check and was continued in F32
+ * storage. */
 typedef struct aq_result {
     int64_t request_id;
     int32_t slot, status, storage, fallback;
@@ -362,20 +368,31 @@ int aq_batch_create(size_t budget_bytes, int32_t max_slots, int64_t max_active_n
 /* Admit one solve.  Parameters, mask and walls as for aq_create; tile_x * tile_y must be
  * 256.  tol: residual at which the solve is done (an F16S solve first runs to
  * max(tol, 2e-5), or until its residual stops falling by 10% over 50 check intervals:
- * binary16 rounding noise sets a floor); drift_tol: for F16S storage, the largest
- * |Q_out/Q_in - 1| at that point accepted without continuing in F32 to tol; max_steps:
- * step cap; request_id: returned with the result; keep != 0 keeps the finished state
- * readable (aq_batch_read_field) until aq_batch_release.  *slot receives the slot.
- * AQ_EBUSY when no slot, arena space, active-node or work-list capacity is free. */
+ * binary16 rounding noise sets a floor; if that floor is above tol, the IOP drift check
+ * decides: an IOP within drift_tol, relative, of the IOP at least 1000 steps earlier
+ * finishes it with AQ_RESULT_FLOOR, otherwise it continues in F32 storage to tol);
+ * max_steps: step cap; request_id: returned with the result; keep != 0 keeps the finished
+ * state readable (aq_batch_read_field) until aq_batch_release.  An F16S instance takes
+ * arena space for its F32 continuation as well (the F32 layout and a 104-byte-per-node
+ * conversion image), so the hand-off needs nothing beyond its admission.  *slot receives
+ * the slot.  AQ_EBUSY when no slot, arena space, active-node or work-list capacity is free. */
 int aq_batch_admit(aq_batch* b, const aq_params* params, const uint8_t* mask, const aq_wall_node* walls,
                    int32_t n_walls, int32_t tile_x, int32_t tile_y, double tol, double drift_tol,
                    int64_t max_steps, int64_t request_id, int32_t keep, int32_t* slot);
 
 /* Run n_intervals check intervals of every running instance, then retire the instances
  * that converged, diverged or reached max_steps (synchronises the stream).  An interval is
- * one HIP graph with one block per work item; admissions and retirements that change the
- * work lists make the next run capture it again. */
+ * two HIP graphs (the two-step launches of every kernel class, then the rest) with one
+ * block per work item; admissions and retirements that change the work lists make the
+ * next run capture them again. */
 int aq_batch_run(aq_batch* b, int32_t n_intervals);
+
+/* As aq_batch_run, with HIP events on the batch stream: *total_ms receives the elapsed
+ * time of the n_intervals intervals, *fused_ms the time spent in their two-step launches
+ * (two time steps of every running instance per launch, all kernel classes), and
+ * *fused_launches the number of those launches.  AQ_ESTATE if nothing is running. */
+int aq_batch_run_timed(aq_batch* b, int32_t n_intervals, double* total_ms, double* fused_ms,
+                       int32_t* fused_launches);
 
 /* Collect up to cap finished results not yet collected; their slots and memory are freed
  * unless they were admitted with keep. */

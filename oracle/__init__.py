@@ -86,6 +86,8 @@ def lib():
         L.or_equilibrium.argtypes = [C.POINTER(OrParams), C.c_double, C.c_double, C.c_double,
                                      C.c_double, dp, dp]
         L.or_moments.argtypes = [C.POINTER(OrParams), dp, dp, dp]
+        L.or_set_threads.argtypes = [C.c_int]
+        L.or_max_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -104,9 +106,13 @@ def make_params(p) -> OrParams:
     return op
 
 
-def set_threads(n: int | None):
-    if n is not None:
-        os.environ["OMP_NUM_THREADS"] = str(n)
+def set_threads(n: int):
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().or_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return lib().or_max_threads()
 
 
 class Oracle:

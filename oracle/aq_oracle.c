@@ -77,11 +77,19 @@
  * the written order).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include "aq_oracle.h"
+
+/* Threads of the OpenMP loops (timing of the oracle at a chosen thread count). */
+void or_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+}
+int or_max_threads(void) { return omp_get_max_threads(); }
 
 /* ---------------------------------------------------------------- lattice (section 2.3) */
 /* D2Q9 velocities: e_0 rest, e_1..e_4 axis, e_5..e_8 diagonal; e_2 and e_4 are the

@@ -51,4 +51,6 @@ void or_collide_node(const or_params* P, int porous, const double* h8, const dou
                      double* h8s, double* g5s);
 void or_equilibrium(const or_params* P, double p, double ux, double uy, double T, double* h8, double* g5);
 void or_moments(const or_params* P, const double* h8, const double* g5, double* out4);
+void or_set_threads(int n);
+int or_max_threads(void);
 #endif

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libaqlbm.so")
 
 AQ_OK, AQ_EINVAL, AQ_ENOMEM, AQ_EDEVICE, AQ_EDIVERGED, AQ_ENOTCONVERGED, AQ_EBUSY, AQ_ESTATE = \
     0, -1, -2, -3, -4, -5, -6, -7
+AQ_RESULT_FLOOR = 1    # result status: F16S accepted at its rounding floor (IOP drift check passed)
 F64, F32, F16S, F32X = 0, 1, 2, 3
 FIELDS = {"p": 0, "ux": 1, "uy": 2, "T": 3, "pop_flow": 4, "pop_heat": 5}
 
@@ -30,7 +31,7 @@ EXPORTS = ("aq_version", "aq_last_error", "aq_required_bytes", "aq_create", "aq_
            "aq_batch_create", "aq_batch_admit", "aq_batch_run", "aq_batch_poll", "aq_batch_read_field",
            "aq_batch_observe", "aq_batch_release", "aq_batch_get_info", "aq_batch_destroy",
            "aq_batch_set_outlet", "aq_batch_resume", "aq_diagnostics_bytes", "aq_diagnose",
-           "aq_batch_diagnose")
+           "aq_batch_diagnose", "aq_batch_run_timed")
 
 
 class AqParams(C.Structure):
@@ -114,12 +115,19 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH):
-    """Load libaqlbm.so (raises if it has not been built)."""
+    """Load libaqlbm.so (raises if it has not been built).  torch, which provides the device
+    memory and streams, brings up the HIP runtime first when a GPU is visible."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library {path} is not built; run __graft_entry__.build()")
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     L = C.CDLL(path)
     vp, sz, i32, i64, dp = C.c_void_p, C.c_size_t, C.c_int32, C.c_int64, C.POINTER(C.c_double)
     L.aq_version.restype = C.c_char_p
@@ -153,6 +161,7 @@ def load_library(path: str = LIB_PATH):
     L.aq_batch_admit.argtypes = [vp, C.POINTER(AqParams), vp, vp, i32, i32, i32, C.c_double, C.c_double,
                                  i64, i64, i32, ip]
     L.aq_batch_run.argtypes = [vp, i32]
+    L.aq_batch_run_timed.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(i32)]
     L.aq_batch_poll.argtypes = [vp, C.POINTER(AqResult), i32, ip]
     L.aq_batch_read_field.argtypes = [vp, i32, i32, i32, dp, sz]
     L.aq_batch_observe.argtypes = [vp, i32, C.POINTER(AqObservables)]
@@ -391,6 +400,12 @@ class Batch:
 
     def run(self, n_intervals: int = 1):
         _check(_lib.aq_batch_run(self._h, int(n_intervals)))
+
+    def run_timed(self, n_intervals: int = 1):
+        """aq_batch_run_timed: (total ms, ms in the two-step launches, number of them)."""
+        tot, fused, nl = C.c_double(), C.c_double(), C.c_int32()
+        _check(_lib.aq_batch_run_timed(self._h, int(n_intervals), C.byref(tot), C.byref(fused), C.byref(nl)))
+        return tot.value, fused.value, nl.value
 
     def poll(self, cap: int = 4096):
         buf = (AqResult * cap)()

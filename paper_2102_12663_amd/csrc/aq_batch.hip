@@ -13,11 +13,13 @@
 // - After each call to aq_batch_run the latest reductions of every running instance are
 //   read back in one copy; converged, diverged and capped instances are retired.
 // - An F16S instance whose residual falls below max(tol, 2e-5), or stops falling for 50
-//   check intervals, passes the IOP drift check
-//   when its outflow balances its inflow (|Q_out/Q_in - 1| <= drift_tol: a steady
-//   pressure level needs exact mass balance, and rounding that does not conserve mass
-//   shows up first as this imbalance); otherwise its state is converted to F32 storage
-//   and the solve continues there until the residual falls below tol.
+//   check intervals, has reached binary16's rounding floor.  If its residual is below tol
+//   it is done (AQ_OK).  Otherwise the IOP drift check compares its IOP with the IOP at
+//   least kDriftSteps steps earlier: within drift_tol (relative) the state is accepted at
+//   the floor (AQ_RESULT_FLOOR); else its state is converted to F32 storage and the solve
+//   continues there until the residual falls below tol.  An F16S instance's arena block
+//   holds, besides its own layout, the F32 layout and the conversion scratch, so the
+//   hand-off never needs memory beyond what admission granted.
 #include "aq_internal.h"
 
 #include <map>
@@ -30,6 +32,9 @@ namespace {
 // ends at max(tol, this floor)
 constexpr double kF16ResidFloor = 2e-5;
 constexpr int kF16Stall = 50;
+// the IOP drift check compares the IOP with one taken at least this many steps earlier
+constexpr int64_t kDriftSteps = 1000;
+constexpr int kIopRing = 32;
 
 // First-fit allocator over [0, size) with coalescing free blocks (offsets in bytes).
 class Pool {
@@ -93,12 +98,45 @@ struct Slot {
     double best_resid = 1e300;   // F16S phase: smallest residual so far
     int since_best = 0;          // check intervals since it last fell by 10%
     aq_solver* s = nullptr;
-    size_t off = 0, bytes = 0;
+    size_t off = 0, bytes = 0;   // arena block; for F16S: [F16S layout | F32 layout | scratch]
+    size_t bytes16 = 0, bytes32 = 0;   // F16S: the first two parts (256-aligned)
     double tol = 0, drift_tol = 0;
     int64_t max_steps = 0, request_id = 0, steps = 0;
     int status = AQ_OK, fallback = 0;
     aq_observables obs;
+    int64_t iop_step[kIopRing];  // F16S phase: (step, IOP) at the last check of each run call
+    double iop_val[kIopRing];
+    int n_iop = 0;
 };
+
+// Bytes of the F32 continuation an F16S instance reserves: the F32 layout and the dense
+// FP64 image of the state the conversion passes through (13 populations per node).
+inline size_t f32_layout_bytes(const aq_params& P, int n_walls)
+{
+    aq_params Q = P;
+    Q.storage = AQ_F32;
+    return align_up(make_layout(Q, n_walls).total, 256);
+}
+inline size_t conversion_scratch_bytes(const aq_params& P)
+{
+    return align_up((size_t)NPOP * P.nx * P.ny * 8, 256);
+}
+
+// IOP drift of an F16S phase: relative change of the IOP against the newest recorded IOP
+// taken at least kDriftSteps steps before the current one; false if there is none yet.
+bool iop_drift(const Slot& sl, double* drift)
+{
+    const int64_t now = sl.obs.step;
+    for (int j = sl.n_iop - 2; j >= 0 && j >= sl.n_iop - kIopRing; j--) {
+        const int r = j % kIopRing;
+        if (now - sl.iop_step[r] >= kDriftSteps) {
+            const double a = sl.obs.iop_gauge, b0 = sl.iop_val[r];
+            *drift = a != 0 ? std::fabs(a - b0) / std::fabs(a) : std::fabs(a - b0);
+            return true;
+        }
+    }
+    return false;
+}
 
 // Has the current phase reached its residual?  F32/F64: max(resid_u, resid_T) < tol.
 // F16S: below max(tol, kF16ResidFloor), or stagnating (no 10% improvement over the last
@@ -151,8 +189,11 @@ struct aq_batch {
     int nt_store = 0;               // non-temporal stores for the current working set
     int graph_mask = -1;
     int graph_items[2 * NKIND] = {};   // work-list lengths the captured launches were sized for
-    hipGraph_t graph_src = nullptr;
-    hipGraphExec_t graph = nullptr;
+    // one check interval = graph[0] (the two-step launches of every kernel class) then
+    // graph[1] (the remaining single steps, the reducing step and the finishing sums)
+    hipGraph_t graph_src[2] = {nullptr, nullptr};
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int fused_launches = 0;         // two-step launches per kernel class and interval
 };
 
 namespace {
@@ -204,59 +245,82 @@ int ensure_kind(aq_batch* b, int k)
 
 void drop_graph(aq_batch* b)
 {
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
-    if (b->graph_src) (void)hipGraphDestroy(b->graph_src);
-    b->graph = nullptr;
-    b->graph_src = nullptr;
+    for (int g = 0; g < 2; g++) {
+        if (b->graph[g]) (void)hipGraphExecDestroy(b->graph[g]);
+        if (b->graph_src[g]) (void)hipGraphDestroy(b->graph_src[g]);
+        b->graph[g] = nullptr;
+        b->graph_src[g] = nullptr;
+    }
     b->graph_mask = -1;
     std::fill(b->graph_items, b->graph_items + 2 * NKIND, 0);
 }
 
+// End a capture on the batch stream and instantiate it into graph slot g.
+int finish_capture(aq_batch* b, int g, hipError_t err)
+{
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b->stream, &gr);
+    if (err != hipSuccess || e2 != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return fail(AQ_EDEVICE, std::string("batch graph capture: ") + hipGetErrorString(err != hipSuccess ? err : e2));
+    }
+    hipGraphExec_t ge = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        return fail(AQ_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+    }
+    b->graph_src[g] = gr;
+    b->graph[g] = ge;
+    return AQ_OK;
+}
+
 // One check interval for every kernel class present: interval-1 plain steps, the
 // reducing step, and the per-instance finishing sums.  Every launch has one block per work
-// item (the hardware dispatcher then balances uneven tiles across the chip), so the graph
-// is captured again whenever admissions or retirements change a work list's length.
+// item (the hardware dispatcher then balances uneven tiles across the chip), so the graphs
+// are captured again whenever admissions or retirements change a work list's length.  The
+// interval is two graphs replayed back to back: the two-step launches of every class, then
+// the rest (classes are independent, so their order across the two graphs is immaterial).
 int ensure_graph(aq_batch* b)
 {
     const int mask = active_mask(b);
-    bool same = b->graph && b->graph_mask == mask;
+    bool same = b->graph[0] && b->graph[1] && b->graph_mask == mask;
     for (int m = 0; m < NKIND && same; m++)
         same = b->graph_items[m] == b->n_work[m] && b->graph_items[NKIND + m] == b->n_work2[m];
     if (same) return AQ_OK;
     drop_graph(b);
+    // interval - 1 plain steps then the reducing one: an even number F of two-step launches
+    // (every storage; F16S: 69.3 against 67.3 GLUPS with single steps on the 512-instance
+    // sweep), so every interval swaps the buffers an even number of times and the batch is
+    // back at parity 0 (instances are admitted at parity 0)
+    const int plain = b->interval - 1;
+    const int F = (plain / 2) & ~1;
+    b->fused_launches = F;
     HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
     for (int m = 0; m < NKIND && err == hipSuccess; m++) {
         if (!(mask & (1 << m))) continue;
-        // interval - 1 plain steps then the reducing one: an even number F of two-step
-        // launches (every storage; F16S: 69.3 against 67.3 GLUPS with single steps on the
-        // 512-instance sweep), so every interval swaps the buffers an even number of times and
-        // the batch is back at parity 0 (instances are admitted at parity 0)
-        const int plain = b->interval - 1;
-        const int F = (plain / 2) & ~1;
         int parity = 0;
         for (int j = 0; j < F && err == hipSuccess; j++, parity ^= 1)
             err = launch_batch_step2(m % NMODE, batch_args(b, m, parity), b->n_work2[m], b->stream);
+    }
+    int rc = finish_capture(b, 0, err);
+    if (rc) return rc;
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    for (int m = 0; m < NKIND && err == hipSuccess; m++) {
+        if (!(mask & (1 << m))) continue;
+        int parity = 0;     // F is even
         for (int j = 2 * F; j < plain && err == hipSuccess; j++, parity ^= 1)
             err = launch_batch_step(m % NMODE, false, batch_args(b, m, parity), b->n_work[m], b->stream);
         if (err == hipSuccess) err = launch_batch_step(m % NMODE, true, batch_args(b, m, parity), b->n_work[m], b->stream);
     }
     for (int m = 0; m < NKIND && err == hipSuccess; m++)
         if (mask & (1 << m)) err = launch_batch_finish(batch_args(b, m, 0), b->stream);
-    hipGraph_t g = nullptr;
-    const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
-    if (err != hipSuccess || e2 != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return fail(AQ_EDEVICE, std::string("batch graph capture: ") + hipGetErrorString(err != hipSuccess ? err : e2));
+    rc = finish_capture(b, 1, err);
+    if (rc) {
+        drop_graph(b);
+        return rc;
     }
-    hipGraphExec_t ge = nullptr;
-    const hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    if (e3 != hipSuccess) {
-        (void)hipGraphDestroy(g);
-        return fail(AQ_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
-    }
-    b->graph_src = g;
-    b->graph = ge;
     b->graph_mask = mask;
     std::copy(b->n_work, b->n_work + NKIND, b->graph_items);
     std::copy(b->n_work2, b->n_work2 + NKIND, b->graph_items + NKIND);
@@ -334,7 +398,10 @@ void free_slot(aq_batch* b, int i)
     sl = Slot();
 }
 
-// Continue an F16S solve in F32 storage from its current state.
+// Continue an F16S solve in F32 storage from its current state, inside the instance's
+// arena block: the F32 solver goes to the block's second part, the state passes through
+// the scratch in its third part, then the first part (the F16S layout) and the scratch
+// return to the pool.
 int convert_to_f32(aq_batch* b, int i)
 {
     Slot& sl = b->slots[i];
@@ -342,6 +409,7 @@ int convert_to_f32(aq_batch* b, int i)
     const size_t n = (size_t)s16->P.nx * s16->P.ny;
     aq_params P = s16->P;
     P.storage = AQ_F32;
+    if (!sl.bytes16 || !sl.bytes32) return fail(AQ_ESTATE, "instance has no F32 reservation");
     // the new solver needs the mask and the wall list again: rebuild them from the old one
     std::vector<uint8_t> mask(n);
     for (int y = 0; y < P.ny; y++)
@@ -355,21 +423,15 @@ int convert_to_f32(aq_batch* b, int i)
         walls[w].n_y = s16->hwall_n[2 * w + 1];
         for (int i = 0; i < 8; i++) walls[w].q[i] = s16->hwall_q[8 * (size_t)w + i];
     }
-    const Layout L32 = make_layout(P, s16->n_walls);
-    size_t off = 0;
-    if (!b->pool.alloc(L32.total, &off)) return fail(AQ_ENOMEM, "no arena space for the F32 fallback");
-    double* dense = nullptr;
-    hipError_t e = hipMalloc((void**)&dense, NPOP * n * 8);
-    if (e != hipSuccess) {
-        b->pool.release(off, L32.total);
-        return fail(AQ_ENOMEM, "no device memory for the state conversion");
-    }
+    const size_t off32 = sl.off + sl.bytes16, off_scr = off32 + sl.bytes32;
+    const size_t scr_bytes = sl.bytes - sl.bytes16 - sl.bytes32;
+    double* dense = (double*)(b->arena + off_scr);
     StepArgs a = make_readout_args(s16);   // src = prev: pulls to the current state
-    e = launch_unpack(s16->mode, a, 7, 0, P.p_ref, dense, b->stream);
+    hipError_t e = launch_unpack(s16->mode, a, 7, 0, P.p_ref, dense, b->stream);
     aq_solver* s32 = nullptr;
     int rc = AQ_OK;
     if (e == hipSuccess) {
-        rc = create_common(&P, mask.data(), walls.data(), s16->n_walls, b->arena + off, L32.total, b->stream, false, &s32);
+        rc = create_common(&P, mask.data(), walls.data(), s16->n_walls, b->arena + off32, sl.bytes32, b->stream, false, &s32);
         if (rc == AQ_OK) rc = aq_set_tile(s32, s16->tile_x, s16->tile_y);
         if (rc == AQ_OK) {
             // lumped outlet: the seepage speeds carry over with the state
@@ -386,18 +448,98 @@ int convert_to_f32(aq_batch* b, int i)
         }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    (void)hipFree(dense);
     if (e != hipSuccess || rc != AQ_OK) {
         if (s32) aq_destroy(s32);
-        b->pool.release(off, L32.total);
         return rc != AQ_OK ? rc : fail(AQ_EDEVICE, std::string("state conversion: ") + hipGetErrorString(e));
     }
     aq_destroy(s16);
-    b->pool.release(sl.off, sl.bytes);
+    b->pool.release(sl.off, sl.bytes16);
+    if (scr_bytes) b->pool.release(off_scr, scr_bytes);
     sl.s = s32;
-    sl.off = off;
-    sl.bytes = L32.total;
+    sl.off = off32;
+    sl.bytes = sl.bytes32;
+    sl.bytes16 = sl.bytes32 = 0;
     sl.fallback = 1;
+    return AQ_OK;
+}
+
+// Enqueue n_intervals check intervals (both graphs of each); with events, ev[2i] and
+// ev[2i+1] bracket the two-step part of interval i and ev[2n] follows the last interval.
+int enqueue_intervals(aq_batch* b, int n_intervals, hipEvent_t* ev)
+{
+    int rc = ensure_graph(b);
+    if (rc) return rc;
+    for (int i = 0; i < n_intervals; i++) {
+        if (ev) HIPCHK(hipEventRecord(ev[2 * i], b->stream));
+        HIPCHK(hipGraphLaunch(b->graph[0], b->stream));
+        if (ev) HIPCHK(hipEventRecord(ev[2 * i + 1], b->stream));
+        HIPCHK(hipGraphLaunch(b->graph[1], b->stream));
+    }
+    if (ev) HIPCHK(hipEventRecord(ev[2 * n_intervals], b->stream));
+    return AQ_OK;
+}
+
+// After n_intervals have been enqueued: read back the latest reductions of every running
+// instance (synchronising the stream) and retire the finished ones.
+int after_intervals(aq_batch* b, int n_intervals)
+{
+    const int64_t dn = (int64_t)n_intervals * b->interval;
+    b->step += dn;
+    HIPCHK(hipMemcpyAsync(b->h_latest, b->d_latest, (size_t)b->max_slots * NRED * 8, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    bool changed = false;
+    int rc = AQ_OK;
+    for (int i = 0; i < b->max_slots; i++) {
+        Slot& sl = b->slots[i];
+        if (!sl.used || !sl.running) continue;
+        aq_solver* s = sl.s;
+        s->step += dn;
+        s->ro_slot = 1;   // every interval ends with a reducing step and its finish kernel
+        s->checks += n_intervals;
+        s->last_check_step = s->step;
+        sl.steps += dn;
+        raw_to_obs(s, b->h_latest + (size_t)i * NRED, s->step, &sl.obs);
+        if (s->mode == AQ_F16S) {
+            const int r = sl.n_iop % kIopRing;
+            sl.iop_step[r] = sl.obs.step;
+            sl.iop_val[r] = sl.obs.iop_gauge;
+            sl.n_iop++;
+        }
+        bool finish = false;
+        if (sl.obs.n_nonfinite > 0) {
+            sl.status = AQ_EDIVERGED;
+            s->diverged = true;
+            finish = true;
+        } else if (resid_done(sl, s->mode, n_intervals)) {
+            double drift = 0;
+            if (s->mode != AQ_F16S || std::max(sl.obs.resid_u, sl.obs.resid_T) < sl.tol) {
+                sl.status = AQ_OK;
+                finish = true;
+            } else if (iop_drift(sl, &drift) && drift <= sl.drift_tol) {
+                sl.status = AQ_RESULT_FLOOR;          // accepted at binary16's floor
+                finish = true;
+            } else if (sl.n_iop >= 2 && iop_drift(sl, &drift)) {
+                const int rc2 = convert_to_f32(b, i);  // the IOP still drifts: continue in F32
+                if (rc2 != AQ_OK) {
+                    sl.status = rc2;
+                    finish = true;
+                    rc = rc2;
+                }
+                changed = true;
+            }                                          // else: no IOP history yet, keep going
+        }
+        if (!finish && sl.running && sl.steps >= sl.max_steps) {
+            sl.status = AQ_ENOTCONVERGED;
+            finish = true;
+        }
+        if (finish) {
+            sl.running = false;
+            sl.done = true;
+            changed = true;
+        }
+    }
+    (void)rc;   // a failed hand-off is reported through that request's status
+    if (changed) return upload_tables(b);
     return AQ_OK;
 }
 
@@ -481,8 +623,12 @@ int aq_batch_admit(aq_batch* b, const aq_params* P, const uint8_t* mask, const a
         if (!b->slots[i].used) { free_i = i; break; }
     if (free_i < 0) return fail(AQ_EBUSY, "no free slot");
     const Layout L = make_layout(*P, n_walls);
+    // an F16S instance also reserves its F32 continuation (layout and conversion scratch)
+    const size_t b16 = align_up(L.total, 256);
+    const size_t b32 = P->storage == AQ_F16S ? f32_layout_bytes(*P, n_walls) : 0;
+    const size_t total = b16 + (P->storage == AQ_F16S ? b32 + conversion_scratch_bytes(*P) : 0);
     size_t off = 0;
-    if (!b->pool.alloc(L.total, &off)) return fail(AQ_EBUSY, "not enough free HBM in the batch arena");
+    if (!b->pool.alloc(total, &off)) return fail(AQ_EBUSY, "not enough free HBM in the batch arena");
     aq_solver* s = nullptr;
     rc = create_common(P, mask, walls, n_walls, b->arena + off, L.total, b->stream, false, &s);
     if (rc == AQ_OK) rc = aq_set_tile(s, tile_x, tile_y);
@@ -493,7 +639,7 @@ int aq_batch_admit(aq_batch* b, const aq_params* P, const uint8_t* mask, const a
     if (rc != AQ_OK) {
         std::string keep_err = aq_last_error();
         if (s) aq_destroy(s);
-        b->pool.release(off, L.total);
+        b->pool.release(off, total);
         g_err = keep_err;
         return rc;
     }
@@ -503,7 +649,11 @@ int aq_batch_admit(aq_batch* b, const aq_params* P, const uint8_t* mask, const a
     sl.keep = keep != 0;
     sl.s = s;
     sl.off = off;
-    sl.bytes = L.total;
+    sl.bytes = total;
+    if (P->storage == AQ_F16S) {
+        sl.bytes16 = b16;
+        sl.bytes32 = b32;
+    }
     sl.tol = tol;
     sl.drift_tol = drift_tol;
     sl.max_steps = max_steps;
@@ -525,57 +675,37 @@ int aq_batch_run(aq_batch* b, int32_t n_intervals)
 {
     if (!b || n_intervals < 1) return fail(AQ_EINVAL, "invalid arguments");
     if (active_mask(b) == 0) return AQ_OK;
-    int rc = ensure_graph(b);
+    int rc = enqueue_intervals(b, n_intervals, nullptr);
     if (rc) return rc;
-    for (int i = 0; i < n_intervals; i++) HIPCHK(hipGraphLaunch(b->graph, b->stream));
-    const int64_t dn = (int64_t)n_intervals * b->interval;
-    b->step += dn;
-    HIPCHK(hipMemcpyAsync(b->h_latest, b->d_latest, (size_t)b->max_slots * NRED * 8, hipMemcpyDeviceToHost, b->stream));
-    HIPCHK(hipStreamSynchronize(b->stream));
-    bool changed = false;
-    for (int i = 0; i < b->max_slots; i++) {
-        Slot& sl = b->slots[i];
-        if (!sl.used || !sl.running) continue;
-        aq_solver* s = sl.s;
-        s->step += dn;
-        s->ro_slot = 1;   // every interval ends with a reducing step and its finish kernel
-        s->checks += n_intervals;
-        s->last_check_step = s->step;
-        sl.steps += dn;
-        raw_to_obs(s, b->h_latest + (size_t)i * NRED, s->step, &sl.obs);
-        bool finish = false;
-        if (sl.obs.n_nonfinite > 0) {
-            sl.status = AQ_EDIVERGED;
-            s->diverged = true;
-            finish = true;
-        } else if (resid_done(sl, s->mode, n_intervals)) {
-            const double imbalance = sl.obs.q_in != 0 ? std::fabs(sl.obs.q_out / sl.obs.q_in - 1.0) : 0.0;
-            if (s->mode == AQ_F16S && !(imbalance <= sl.drift_tol)) {
-                rc = convert_to_f32(b, i);
-                if (rc != AQ_OK) {
-                    sl.status = rc;
-                    finish = true;
-                }
-                changed = true;
-            } else {
-                sl.status = AQ_OK;
-                finish = true;
-            }
-        } else if (sl.steps >= sl.max_steps) {
-            sl.status = AQ_ENOTCONVERGED;
-            finish = true;
+    return after_intervals(b, n_intervals);
+}
+
+int aq_batch_run_timed(aq_batch* b, int32_t n_intervals, double* total_ms, double* fused_ms, int32_t* fused_launches)
+{
+    if (!b || n_intervals < 1 || !total_ms || !fused_ms || !fused_launches) return fail(AQ_EINVAL, "invalid arguments");
+    if (active_mask(b) == 0) return fail(AQ_ESTATE, "no running instance");
+    std::vector<hipEvent_t> ev(2 * (size_t)n_intervals + 1, nullptr);
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    int rc = enqueue_intervals(b, n_intervals, ev.data());
+    if (rc == AQ_OK) {
+        HIPCHK(hipEventSynchronize(ev[2 * n_intervals]));
+        float t = 0;
+        double fused = 0;
+        for (int i = 0; i < n_intervals; i++) {
+            HIPCHK(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
+            fused += t;
         }
-        if (finish) {
-            sl.running = false;
-            sl.done = true;
-            changed = true;
-        }
+        HIPCHK(hipEventElapsedTime(&t, ev[0], ev[2 * n_intervals]));
+        *total_ms = t;
+        *fused_ms = fused;
+        int classes = 0;
+        for (int m = 0; m < NKIND; m++)
+            if (active_mask(b) & (1 << m)) classes++;
+        *fused_launches = b->fused_launches * classes * n_intervals;
+        rc = after_intervals(b, n_intervals);
     }
-    if (changed) {
-        rc = upload_tables(b);
-        if (rc) return rc;
-    }
-    return AQ_OK;
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return rc;
 }
 
 int aq_batch_poll(aq_batch* b, aq_result* done, int32_t cap, int32_t* n_done)
@@ -628,7 +758,8 @@ int aq_batch_resume(aq_batch* b, int32_t slot, double tol, int64_t max_steps)
     Slot& sl = b->slots[slot];
     if (!sl.keep || !sl.done || sl.running) return fail(AQ_ESTATE, "only a finished instance admitted with keep can resume");
     if (!(tol > 0) || max_steps < 1) return fail(AQ_EINVAL, "tol and max_steps must be positive");
-    if (sl.status != AQ_OK && sl.status != AQ_ENOTCONVERGED) return fail(AQ_ESTATE, "the instance failed");
+    if (sl.status != AQ_OK && sl.status != AQ_ENOTCONVERGED && sl.status != AQ_RESULT_FLOOR)
+        return fail(AQ_ESTATE, "the instance failed");
     if (b->max_active && running_active(b) + sl.s->n_active > b->max_active) return fail(AQ_EBUSY, "active-node cap reached");
     if (b->n_work[kind_of(sl.s)] + sl.s->n_tiles > b->max_tiles) return fail(AQ_EBUSY, "work list capacity reached");
     sl.running = true;
@@ -637,6 +768,7 @@ int aq_batch_resume(aq_batch* b, int32_t slot, double tol, int64_t max_steps)
     sl.max_steps = sl.steps + max_steps;
     sl.best_resid = 1e300;
     sl.since_best = 0;
+    sl.n_iop = 0;
     sl.status = AQ_OK;
     return upload_tables(b);
 }

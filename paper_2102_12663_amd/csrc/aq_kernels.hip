@@ -58,15 +58,20 @@ template <> struct Traits<1> {   // AQ_F32
     __device__ static Acc dec(S s, R) { return s; }
 };
 template <> struct Traits<2> {   // AQ_F16S: binary16 of (deviation * 2^s)
+    // The step computes in units of the stored values (deviation * 2^s, the flow and the
+    // thermal lattice each with its own power-of-two scale): loads and stores are bare
+    // conversions, and the few constants that carry physical units are scaled instead
+    // (see fscale / tscale).  Scaling by a power of two is exact, so every rounding is the
+    // physical-unit arithmetic's, scaled.  st() writes a physical value (state installation).
     using S = _Float16;
     using R = float;
     using L = float;
     using Acc = float;       // float sums of binary16 values are far finer than their ulp
-    __device__ static R ld(const S* p, R inv) { return (R)(*p) * inv; }
-    __device__ static R ldv(S v, R inv) { return (R)v * inv; }
+    __device__ static R ld(const S* p, R) { return (R)(*p); }
+    __device__ static R ldv(S v, R) { return (R)v; }
     __device__ static void st(S* p, R v, R sc) { *p = (S)(v * sc); }
-    __device__ static S enc(Acc v, R sc) { return (S)(v * sc); }
-    __device__ static Acc dec(S s, R inv) { return (R)s * inv; }
+    __device__ static S enc(Acc v, R) { return (S)v; }
+    __device__ static Acc dec(S s, R) { return (R)s; }
 };
 template <> struct Traits<3> {   // AQ_F32X: FP32 storage, FP64 arithmetic
     using S = float;
@@ -85,6 +90,20 @@ template <> struct Traits<3> {   // AQ_F32X: FP32 storage, FP64 arithmetic
 template <typename R> __device__ __forceinline__ R cst(double d, float f);
 template <> __device__ __forceinline__ double cst<double>(double d, float) { return d; }
 template <> __device__ __forceinline__ float cst<float>(double, float f) { return f; }
+
+// Compute units of a storage: F16S computes in stored units, so a physical flow quantity
+// enters multiplied by fscale and a physical thermal quantity by tscale (the per-solver
+// powers of two 2^s); the other storages compute in physical units (factor one, folded).
+template <int MODE, typename R> __device__ __forceinline__ R fscale(const StepArgs& a)
+{
+    if constexpr (MODE == 2) return R(a.sf32);
+    else return R(1);
+}
+template <int MODE, typename R> __device__ __forceinline__ R tscale(const StepArgs& a)
+{
+    if constexpr (MODE == 2) return R(a.st32);
+    else return R(1);
+}
 
 template <typename R> struct Node {
     R h[9];   // h[1..8] flow (h[0] unused)
@@ -112,14 +131,42 @@ __device__ __forceinline__ Moments<R> moments(const Node<R>& n)
 {
     Moments<R> m;
     const R* h = n.h;
-    m.sum = ((h[1] + h[2]) + (h[3] + h[4])) + ((h[5] + h[6]) + (h[7] + h[8]));
-    m.ux = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
-    m.uy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
+    if constexpr (sizeof(R) == 4) {
+        // single precision: the velocity from differences of opposite links, which near
+        // equilibrium hold nearly equal values (lambda_i (p - p_ref) dominates both), so
+        // each difference is exact and u carries no rounding of the pressure part
+        const R d13 = h[1] - h[3], d24 = h[2] - h[4], d57 = h[5] - h[7], d68 = h[6] - h[8];
+        m.ux = d13 + (d57 - d68);
+        m.uy = d24 + (d57 + d68);
+        m.sum = ((h[1] + h[3]) + (h[2] + h[4])) + ((h[5] + h[7]) + (h[6] + h[8]));
+    } else {
+        m.sum = ((h[1] + h[2]) + (h[3] + h[4])) + ((h[5] + h[6]) + (h[7] + h[8]));
+        m.ux = (h[1] - h[3]) + (h[5] - h[6]) + (h[8] - h[7]);
+        m.uy = (h[2] - h[4]) + (h[5] + h[6]) - (h[7] + h[8]);
+    }
     m.uu = fma(m.ux, m.ux, m.uy * m.uy);
     // p - p_ref = c^2/(4 sigma) [sum h_i + S_0(u)], S_0 = -(2/3)|u|^2, sigma = 5/12
     m.dp = R(0.6) * (m.sum - R(2.0 / 3.0) * m.uu);
     m.th = (n.g[0] + n.g[1]) + (n.g[2] + n.g[3]) + n.g[4];
     return m;
+}
+
+// The moments in double of a node held in the compute type R: the check-step reductions
+// and the field read-out of the single-precision forms widen the node's values (exactly)
+// and take the moments from them, so the reduced IOP, residuals and read-out fields carry
+// no single-precision rounding of their own.  In double this is `moments` itself.
+template <int MODE, typename R>
+__device__ __forceinline__ Moments<double> wide_moments(const StepArgs& a, const Node<R>& n, Node<double>& w)
+{
+    // back to physical units (F16S: exact division by the powers of two)
+    const double uf = MODE == 2 ? a.inv_sf : 1.0, ut = MODE == 2 ? a.inv_st : 1.0;
+#pragma unroll
+    for (int i = 1; i <= 8; i++) w.h[i] = (double)n.h[i] * uf;
+#pragma unroll
+    for (int i = 0; i <= 4; i++) w.g[i] = (double)n.g[i] * ut;
+    w.qin = (double)n.qin * uf;
+    w.qout = (double)n.qout * uf;
+    return moments(w);
 }
 
 // ------------------------------------------------------------------------------ addressing
@@ -299,6 +346,39 @@ __device__ __forceinline__ void extrapolate_links(const StepArgs& a, const uint8
     }
 }
 
+// extrapolate_links in physical units: F16S nodes (stored units) are scaled down, the
+// links extrapolated, and the node scaled back up (both exact).
+template <int MODE, typename R>
+__device__ __forceinline__ void extrapolate_physical(const StepArgs& a, const uint8_t* nt, Node<R> own, Node<R>& n)
+{
+    if constexpr (MODE == 2) {
+        const R uf = R(a.inv_sf32), ut = R(a.inv_st32), f = R(a.sf32), t = R(a.st32);
+#pragma unroll
+        for (int i = 1; i <= 8; i++) {
+            own.h[i] *= uf;
+            n.h[i] *= uf;
+        }
+#pragma unroll
+        for (int i = 0; i <= 4; i++) {
+            own.g[i] *= ut;
+            n.g[i] *= ut;
+        }
+        n.qin *= uf;
+        n.qout *= uf;
+        const Moments<R> ms = moments(own);
+        extrapolate_links(a, nt, own, ms, n);
+#pragma unroll
+        for (int i = 1; i <= 8; i++) n.h[i] *= f;
+#pragma unroll
+        for (int i = 0; i <= 4; i++) n.g[i] *= t;
+        n.qin *= f;
+        n.qout *= f;
+    } else {
+        const Moments<R> ms = moments(own);
+        extrapolate_links(a, nt, own, ms, n);
+    }
+}
+
 // Link fraction of the wall that link i's upstream solid presents to wall-list node w
 // (q of the link toward it, -1 if none).
 __device__ __forceinline__ double wall_fraction(const StepArgs& a, int w, int i)
@@ -327,17 +407,18 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Tra
         if (extra && (c == INLET || c == OUTLET)) {
             // extrapolated below
         } else if (c == INLET) {                               // moving wall at u_in
-            const R corr = R(6.0) * wflow<R>(i) * (R(EX[i]) * R(a.uin_x) + R(EY[i]) * R(a.uin_y));
+            const R corr = R(6.0) * wflow<R>(i) * (R(EX[i]) * R(a.uin_x) + R(EY[i]) * R(a.uin_y)) * fscale<MODE, R>(a);
             n.h[i] = v + corr;
             n.qin += corr;
         } else if (c == OUTLET) {
             if (a.lumped) {                                    // wall moving at u_s n (meshwork)
                 const int d = ((nt[i] >> WALL_SHIFT) & 3) + 1;
-                const R corr = R(6.0) * wflow<R>(i) * (R(EX[i] * EX[d] + EY[i] * EY[d]) * R(*a.useep));
+                const R corr = R(6.0) * wflow<R>(i) * (R(EX[i] * EX[d] + EY[i] * EY[d]) * R(*a.useep)) *
+                               fscale<MODE, R>(a);
                 n.h[i] = v + corr;
                 n.qout -= corr;
             } else {                                           // pressure anti-bounce-back
-                const R out = -v + R(2.0) * lam<R>(i) * R(a.dp_out);
+                const R out = -v + R(2.0) * lam<R>(i) * R(a.dp_out) * fscale<MODE, R>(a);
                 n.qout += v - out;
                 n.h[i] = out;
             }
@@ -359,7 +440,7 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Tra
         const uint8_t wall = (nt[i] >> WALL_SHIFT) & 3;
         if (c == INLET || (c == SOLID && wall != WALL_BOX)) {  // Dirichlet anti-bounce-back
             const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
-            n.g[i] = -n.g[i] + R(2.0) * cst<R>(a.wT, a.wT32) * R(tw);
+            n.g[i] = -n.g[i] + R(2.0) * cst<R>(a.wT, a.wT32) * R(tw) * tscale<MODE, R>(a);
         }                                                      // else adiabatic bounce-back
     }
     if constexpr (BC) {
@@ -371,8 +452,7 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Tra
         for (int i = 1; i <= 8; i++) own.h[i] = T::ld(src + (long long)(i - 1) * a.qs + k, inv_f);
 #pragma unroll
         for (int i = 0; i <= 4; i++) own.g[i] = T::ld(src + (8LL + i) * a.qs + k, inv_t);
-        const Moments<R> ms = moments(own);
-        extrapolate_links(a, nt, own, ms, n);
+        extrapolate_physical<MODE>(a, nt, own, n);
     }
 }
 
@@ -388,19 +468,6 @@ __device__ __forceinline__ void pull_all(const StepArgs& a, const typename Trait
 }
 
 // ------------------------------------------------------------------------------ collide
-// BGK relaxation (eq. 6) of link i and its opposite, with e_i.u = eu, c = omega w_i,
-// t = 3 omega w_i, E the even part of the equilibrium shared by all links and F the
-// force on link i (the opposite link takes -F):
-//   h*_i = (1 - omega) h_i + c (E + 4.5 eu^2) + (t eu + F), h*_opp the same with -eu, -F.
-template <typename R>
-__device__ __forceinline__ void relax_pair(R eu, R c, R t, R E, R F, R omc, R hi, R ho, R& si, R& so)
-{
-    const R even = c * fma(R(4.5), eu * eu, E);
-    const R odd = fma(t, eu, F);
-    si = fma(omc, hi, even + odd);
-    so = fma(omc, ho, even - odd);
-}
-
 // eq. 7-8 for one link: w_i [3 e_i.u + 4.5 (e_i.u)^2 - 1.5 |u|^2] + lambda_i (p - p_ref),
 // with u15 = 1.5 |u|^2 and l = lambda_i (p - p_ref)
 template <typename R>
@@ -414,9 +481,10 @@ __device__ __forceinline__ void collide(const StepArgs& a, bool porous, const No
                                         const Moments<R>& m, R* hs, R* gs)
 {
     const R om = cst<R>(a.omega_f, a.omega_f32), omc = R(1) - om;
-    // buoyancy, eq. 15-16
-    const R tm = m.th + cst<R>(a.dT0, a.dT032);              // T - T0
-    const R Bx = cst<R>(a.bx, a.bx32) * tm, By = cst<R>(a.by, a.by32) * tm;
+    // buoyancy, eq. 15-16 (F16S: th in thermal and the force in flow compute units)
+    const R th = MODE == 2 ? m.th * R(a.inv_st32) : m.th;  // T - T_ref
+    const R tm = th + cst<R>(a.dT0, a.dT032);                // T - T0
+    const R Bx = cst<R>(a.bx, a.bx32) * fscale<MODE, R>(a) * tm, By = cst<R>(a.by, a.by32) * fscale<MODE, R>(a) * tm;
     R Dx = R(0), Dy = R(0);
     if (porous) {                              // Darcy drag on the mid-step velocity, eq. 4
         const R dd = cst<R>(a.drag_den, a.drag_den32), nk = cst<R>(a.nuK, a.nuK32);
@@ -424,34 +492,53 @@ __device__ __forceinline__ void collide(const StepArgs& a, bool porous, const No
         Dy = -nk * ((m.uy + R(0.5) * By) * dd);
     }
     const R ux = m.ux, uy = m.uy;
-    if constexpr (MODE == 2) {
-        // F16S, whose step is bound by its arithmetic: the links in opposite pairs, fewer
-        // instructions.  (In FP32 storage this order doubled the steady-state velocity error
-        // against FP64, so the other storages keep the per-link order below.)
-        // Link forces: eq. 17 on the axis links, the drag with weights 3 w_i on every link.
-        const R Fx = fma(R(0.5), Bx, R(1.0 / 3.0) * Dx), Fy = fma(R(0.5), By, R(1.0 / 3.0) * Dy);
-        const R Fp = R(1.0 / 12.0) * (Dx + Dy), Fm = R(1.0 / 12.0) * (Dy - Dx);
-        // eq. 7-8 with lambda_i = 3 w_i: h^eq_i = w_i [E + 4.5 (e_i.u)^2 + 3 e_i.u] with
-        // E = 3 (p - p_ref) - 1.5 |u|^2, relaxed by eq. 6.  A link and its opposite share
-        // the even part, so each pair takes one square and one product with omega w_i.
-        const R E = fma(R(-1.5), m.uu, R(3) * m.dp);
-        const R c1 = om * R(1.0 / 9.0), c5 = om * R(1.0 / 36.0);
-        relax_pair(ux, c1, R(3) * c1, E, Fx, omc, n.h[1], n.h[3], hs[1], hs[3]);
-        relax_pair(uy, c1, R(3) * c1, E, Fy, omc, n.h[2], n.h[4], hs[2], hs[4]);
-        relax_pair(ux + uy, c5, R(3) * c5, E, Fp, omc, n.h[5], n.h[7], hs[5], hs[7]);
-        relax_pair(uy - ux, c5, R(3) * c5, E, Fm, omc, n.h[6], n.h[8], hs[6], hs[8]);
-        // eq. 11-12, axis links in opposite pairs:
-        // omega_T w^T_i (T - T_ref) +- omega_T w^T_i (T / c_sT^2) e_i.u
-        const R omT = cst<R>(a.omega_t, a.omega_t32), omTc = R(1) - omT;
-        const R T = cst<R>(a.T_ref, a.T_ref32) + m.th;
-        gs[0] = fma(omTc, n.g[0], omT * (cst<R>(a.w0T, a.w0T32) * m.th));
-        const R cT = omT * cst<R>(a.wT, a.wT32);
-        const R even = cT * m.th, k = cT * (cst<R>(a.inv_cs2T, a.inv_cs2T32) * T);
-        const R ox = k * ux, oy = k * uy;
-        gs[1] = fma(omTc, n.g[1], even + ox);
-        gs[3] = fma(omTc, n.g[3], even - ox);
-        gs[2] = fma(omTc, n.g[2], even + oy);
-        gs[4] = fma(omTc, n.g[4], even - oy);
+    if constexpr (MODE == 1 || MODE == 2) {
+        // FP32 arithmetic whose constants keep the collision's conservation laws exact.
+        // Rounded to single precision one by one, the weights of eq. 8 no longer satisfy
+        // the discrete identities: 9 fl(1/9) = 1 + 7.5e-9, so sum_i e_i h^eq_i = u (1 +
+        // 7.5e-9) and every collision adds omega 7.5e-9 u of momentum, an anti-friction
+        // that the chamber's slowest modes (damped by nu k^2 ~ 1e-5 per step) amplify to a
+        // ~1e-3 relative velocity error at steady state; the mass identity breaks the same
+        // way (by ~7e-8 of sum h per step).  Written out, eq. 7-9 give
+        //   h^eq_i = A_i S + B_i (e_i.u) + C_i (e_i.u)^2 - D_i |u|^2,  S = sum_{j>=1} h_j,
+        // with A = 3/5 lambda_i, B = 3 w_i, C = 9/2 w_i, D = 3/2 w_i + 2/5 lambda_i
+        // (A_1 = 1/5, B_1 = 1/3, C_1 = 1/2, D_1 = 3/10 on the axis links, a quarter of each
+        // on the diagonals).  The single-precision constants below satisfy, exactly in
+        // real arithmetic, sum_i A_i = 1 and 2 C_1 + 4 C_5 = 4 D_1 + 4 D_5 (mass) and
+        // 2 B_1 + 4 B_5 = 1 (momentum); each subtraction forming them is exact.  What is
+        // left is the rounding of individual operations, without a sign of its own.
+        constexpr float A1 = 0.2f, A5 = 0.25f - A1;
+        constexpr float B1 = 1.0f / 3.0f, B5 = (1.0f - 2.0f * B1) * 0.25f;
+        constexpr float D1 = 0.3f, D5 = 0.375f - D1;
+        // quadratic terms in compute units: F16S's u carries the scale, so C and D take
+        // its inverse (exact)
+        const float q = MODE == 2 ? a.inv_sf32 : 1.0f;
+        const float e1 = fma(A1, m.sum, -((D1 * q) * m.uu)), e5 = fma(A5, m.sum, -((D5 * q) * m.uu));
+        // link forces: eq. 17 buoyancy on the axis links, the drag with weights B_i
+        const float Fx = fma(0.5f, Bx, B1 * Dx), Fy = fma(0.5f, By, B1 * Dy);
+        const float Fp = B5 * (Dx + Dy), Fm = B5 * (Dy - Dx);
+        // eq. 6 as h + omega (h^eq - h) + F: near equilibrium h^eq - h is exact, and no
+        // rounded 1 - omega enters
+        auto pair = [&](float eu, float C, float B, float base, float F, float hi, float ho, float& si, float& so) {
+            const float even = fma(C * eu, eu, base), odd = B * eu;
+            si = hi + fma(om, (even + odd) - hi, F);
+            so = ho + fma(om, (even - odd) - ho, -F);
+        };
+        pair(ux, 0.5f * q, B1, e1, Fx, n.h[1], n.h[3], hs[1], hs[3]);
+        pair(uy, 0.5f * q, B1, e1, Fy, n.h[2], n.h[4], hs[2], hs[4]);
+        pair(ux + uy, 0.125f * q, B5, e5, Fp, n.h[5], n.h[7], hs[5], hs[7]);
+        pair(uy - ux, 0.125f * q, B5, e5, Fm, n.h[6], n.h[8], hs[6], hs[8]);
+        // eq. 11-12 with w0T + 4 wT = 1 exactly (set on the host) and the advective part
+        // w_i T (e_i.u)/c_sT^2 = T (e_i.u)/2 (c_sT^2 = 2 wT), whose sum is T u exactly
+        // (F16S: the advective part takes the thermal scale over the flow scale)
+        const float omT = a.omega_t32;
+        const float T = a.T_ref32 + th;
+        const float ev = a.wT32 * m.th, k = (MODE == 2 ? 0.5f * (a.st32 * a.inv_sf32) : 0.5f) * T;
+        gs[0] = n.g[0] + omT * (a.w0T32 * m.th - n.g[0]);
+        gs[1] = n.g[1] + omT * (fma(k, ux, ev) - n.g[1]);
+        gs[3] = n.g[3] + omT * (fma(-k, ux, ev) - n.g[3]);
+        gs[2] = n.g[2] + omT * (fma(k, uy, ev) - n.g[2]);
+        gs[4] = n.g[4] + omT * (fma(-k, uy, ev) - n.g[4]);
     } else {
         // each link on its own: in FP64 this order's rounding stays close to the plain
         // per-link definition (1e-12), in FP32 it keeps the steady-state error lower
@@ -526,9 +613,37 @@ __device__ __forceinline__ void store_all(const StepArgs& a, typename Traits<MOD
 // sum g, but rounding each post-collision value to the storage format does not, and at a
 // steady state the same rounding repeats every step: a persistent mass source that shifts
 // the pressure level (the IOP) by the source over the outflow resistance.  Here the
-// rounded values are decoded, their sum is compared (in double, exactly for these few
-// terms) with the sum of the node's incoming values, and the difference is added to the
-// value of smallest magnitude, where the format resolves finest.
+// rounded values are decoded, their sum is compared with the sum of the node's incoming
+// values (F32 and F32X: in double, exactly for these few terms; F16S: in single precision,
+// far finer than binary16's ulp, in stored units like the whole F16S step), and the
+// difference r is added to the value where the format resolves finest, which is rounded
+// again.  That value must be among the smallest: on a larger one a correction below half
+// its ulp rounds away (with the flow residual on the larger-valued h_2 or h_4 the steady
+// velocity error of F32X grew 40-fold; with the thermal residual on g_0 the F16S IOP error
+// 15-fold).  The flow search covers all eight links in F16S, where binary16's coarse ulp
+// makes the difference (on the smallest diagonal only, the F16S steady velocity error grew
+// 4-fold), and the four diagonals in single precision, whose pressure part is a quarter of
+// the axis links' (no measurable difference: F32X 9.1e-6 against 8.9e-6).  The
+// mirror x -> -x maps the links onto each other (flow 1 <-> 3, 5 <-> 6, 7 <-> 8; heat
+// 1 <-> 3; the others onto themselves); a mirror-symmetric state stays symmetric because
+// ties are never broken by link order between mirror images: the links that are their
+// own image come first (flow 2, 4; heat 0, 2, 4), then the pairs in a fixed order, and
+// when both links of the pair holding the minimum have it, the one with the larger
+// incoming (pre-collision) value takes r, a choice the mirror maps onto its image; only
+// when those are equal too (on a symmetry axis) does each take r/2.  (Splitting every tie
+// loses the correction at twice the threshold, and binary16 values tie often.)
+// Shares of the residual for the two links a, b of a mirror pair, `fa` / `fb`: the link
+// holds the minimum (and its pair was chosen); on a tie the larger incoming value ia / ib
+// decides, and equal incoming values split it.
+template <typename Acc, typename R>
+__device__ __forceinline__ void pair_weights(bool fa, bool fb, R ia, R ib, Acc& wa, Acc& wb)
+{
+    const bool tie = fa && fb;
+    const bool ta = ia > ib, tb = ib > ia;
+    wa = fa ? (tie ? (ta ? Acc(1) : (tb ? Acc(0) : Acc(0.5))) : Acc(1)) : Acc(0);
+    wb = fb ? (tie ? (tb ? Acc(1) : (ta ? Acc(0) : Acc(0.5))) : Acc(1)) : Acc(0);
+}
+
 template <int MODE, int N>
 __device__ __forceinline__ void conserve_encode(const typename Traits<MODE>::R* in,
                                                 const typename Traits<MODE>::R* out,
@@ -537,51 +652,71 @@ __device__ __forceinline__ void conserve_encode(const typename Traits<MODE>::R* 
 {
     using T = Traits<MODE>;
     using Acc = typename T::Acc;
-    using R = typename T::R;
-    if constexpr (MODE == 2) {
-        // F16S: the same arithmetic in units of the stored binary16 values.  Decoding scales
-        // by a power of two, which commutes exactly with every rounding below, so comparing
-        // and summing the undecoded values gives bit for bit the same result without a
-        // multiply per value: target * sc is the sum of the in[i] * sc, and the corrected
-        // value is the binary16 of dmin + r in these units.
-        Acc target = 0, sum = 0;
-        R dmin = 0;
-        int kmin = 0;
+    using L = typename T::L;   // exact for a decoded stored value
+    Acc target = (Acc)in[0];
 #pragma unroll
-        for (int i = 0; i < N; i++) {
-            target += in[i];
-            enc[i] = T::enc(out[i], sc);
-            const R d = (R)enc[i];
-            sum += d;
-            const bool lower = i == 0 || fabs(d) < fabs(dmin);   // selects, not branches
-            dmin = lower ? d : dmin;
-            kmin = lower ? i : kmin;
-        }
-        const typename T::S c = (typename T::S)(dmin + (target * sc - sum));
-#pragma unroll
-        for (int i = 0; i < N; i++) enc[i] = i == kmin ? c : enc[i];
-        return;
-    }
-    // F32 and F32X: the decoded value is exact in single precision (the LDS type L), so the
-    // search runs there, also where the arithmetic is FP64
-    using L = typename T::L;
-    Acc target = 0, sum = 0;
-    L dmin = 0;
-    int kmin = 0;
+    for (int i = 1; i < N; i++) target += (Acc)in[i];
+    L d[N];
+    Acc sum = 0;
 #pragma unroll
     for (int i = 0; i < N; i++) {
-        target += (Acc)in[i];
         enc[i] = T::enc((Acc)out[i], sc);
-        const L d = (L)T::ldv(enc[i], inv);
-        sum += (Acc)d;
-        const bool lower = i == 0 || fabs(d) < fabs(dmin);   // selects, not branches
-        dmin = lower ? d : dmin;
-        kmin = lower ? i : kmin;
+        d[i] = (L)T::ldv(enc[i], inv);
+        sum = i == 0 ? (Acc)d[0] : sum + (Acc)d[i];
     }
-    // the corrected value replaces the one at kmin (whose decoded value is dmin)
-    const typename T::S c = T::enc((Acc)dmin + (target - sum), sc);
+    const Acc r = target - sum;
+    if constexpr (N == 5) {
+        const L a0 = fabs(d[0]), a1 = fabs(d[1]), a2 = fabs(d[2]), a3 = fabs(d[3]), a4 = fabs(d[4]);
+        const L mn = fmin(fmin(fmin(a0, a2), a4), fmin(a1, a3));
+        const bool f0 = a0 == mn, f1 = a1 == mn, f2 = a2 == mn, f3 = a3 == mn, f4 = a4 == mn;
+        const bool self = f0 || f2 || f4;
+        const Acc w0 = f0 ? Acc(1) : Acc(0);
+        const Acc w2 = !f0 && f2 ? Acc(1) : Acc(0);
+        const Acc w4 = !f0 && !f2 && f4 ? Acc(1) : Acc(0);
+        Acc w1, w3;
+        pair_weights(!self && f1, !self && f3, in[1], in[3], w1, w3);
+        enc[0] = T::enc(fma(w0, r, (Acc)d[0]), sc);
+        enc[1] = T::enc(fma(w1, r, (Acc)d[1]), sc);
+        enc[2] = T::enc(fma(w2, r, (Acc)d[2]), sc);
+        enc[3] = T::enc(fma(w3, r, (Acc)d[3]), sc);
+        enc[4] = T::enc(fma(w4, r, (Acc)d[4]), sc);
+        return;
+    }
+    if constexpr (MODE == 2) {
+        // links 1..8 are entries 0..7: h_2, h_4 first, then the pairs (1,3), (5,6), (7,8)
+        L m[8];
 #pragma unroll
-    for (int i = 0; i < N; i++) enc[i] = i == kmin ? c : enc[i];
+        for (int i = 0; i < 8; i++) m[i] = fabs(d[i]);
+        const L mn = fmin(fmin(fmin(m[1], m[3]), fmin(m[0], m[2])), fmin(fmin(m[4], m[5]), fmin(m[6], m[7])));
+        bool f[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) f[i] = m[i] == mn;
+        const bool self = f[1] || f[3];
+        const bool p13 = !self && (f[0] || f[2]);
+        const bool p56 = !self && !p13 && (f[4] || f[5]);
+        const bool p78 = !self && !p13 && !p56;
+        Acc w[8];
+        w[1] = f[1] ? Acc(1) : Acc(0);
+        w[3] = !f[1] && f[3] ? Acc(1) : Acc(0);
+        pair_weights(p13 && f[0], p13 && f[2], in[0], in[2], w[0], w[2]);
+        pair_weights(p56 && f[4], p56 && f[5], in[4], in[5], w[4], w[5]);
+        pair_weights(p78 && f[6], p78 && f[7], in[6], in[7], w[6], w[7]);
+#pragma unroll
+        for (int i = 0; i < 8; i++) enc[i] = T::enc(fma(w[i], r, (Acc)d[i]), sc);
+    } else {
+        // the diagonals 5..8 (entries 4..7): the pair (5, 6) first, then (7, 8)
+        const L a5 = fabs(d[4]), a6 = fabs(d[5]), a7 = fabs(d[6]), a8 = fabs(d[7]);
+        const L mn = fmin(fmin(a5, a6), fmin(a7, a8));
+        const bool f5 = a5 == mn, f6 = a6 == mn, f7 = a7 == mn, f8 = a8 == mn;
+        const bool p56 = f5 || f6;
+        Acc w5, w6, w7, w8;
+        pair_weights(p56 && f5, p56 && f6, in[4], in[5], w5, w6);
+        pair_weights(!p56 && f7, !p56 && f8, in[6], in[7], w7, w8);
+        enc[4] = T::enc(fma(w5, r, (Acc)d[4]), sc);
+        enc[5] = T::enc(fma(w6, r, (Acc)d[5]), sc);
+        enc[6] = T::enc(fma(w7, r, (Acc)d[6]), sc);
+        enc[7] = T::enc(fma(w8, r, (Acc)d[7]), sc);
+    }
 }
 
 template <int MODE, bool NT>
@@ -835,15 +970,17 @@ __device__ __forceinline__ void process_tile(const StepArgs& a, int tile, double
         collide<MODE>(a, (t & CLS_MASK) == POROUS, n, m, hs, gs);
         store_conserving<MODE, NT>(a, dst, k, n, hs, gs);
         if (REDUCE) {
-            const double ux = m.ux, uy = m.uy, th = m.th, dp = m.dp;
+            Node<double> nw;
+            const Moments<double> mw = wide_moments<MODE>(a, n, nw);
+            const double ux = mw.ux, uy = mw.uy, th = mw.th, dp = mw.dp;
             const double Tabs = a.T_ref + th;
             if ((t & CLS_MASK) == FLUID) r[R_DP_FLUID] = dp;
-            r[R_QOUT] = n.qout;
-            r[R_QIN] = n.qin;
+            r[R_QOUT] = nw.qout;
+            r[R_QIN] = nw.qin;
             if (t & F_WSS) {
                 const int wi = a.widx[k];
                 if (wi >= 0) {
-                    const double tw = wall_stress(a, n, m, a.wall_n[2 * wi], a.wall_n[2 * wi + 1]);
+                    const double tw = wall_stress(a, nw, mw, a.wall_n[2 * wi], a.wall_n[2 * wi + 1]);
                     if (a.wall_id[wi] == WALL_CORNEA) { r[R_WSS_C_SUM] = tw; r[R_WSS_C_MAX] = tw; }
                     else { r[R_WSS_I_SUM] = tw; r[R_WSS_I_MAX] = tw; }
                 }
@@ -857,7 +994,7 @@ __device__ __forceinline__ void process_tile(const StepArgs& a, int tile, double
             up[k] = ux;
             up[a.qs + k] = uy;
             up[2 * a.qs + k] = Tabs;
-            r[R_MASS_F] = m.sum;
+            r[R_MASS_F] = mw.sum;
             r[R_MASS_T] = th;
             r[R_UMAX] = sqrt(ux * ux + uy * uy);
             r[R_NONFINITE] = (isfinite(dp) && isfinite(ux) && isfinite(uy) && isfinite(th)) ? 0.0 : 1.0;
@@ -971,14 +1108,14 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
         if (extra && (c == INLET || c == OUTLET)) {
             // extrapolated below
         } else if (c == INLET) {
-            const R corr = R(6.0) * wflow<R>(i) * (R(EX[i]) * R(a.uin_x) + R(EY[i]) * R(a.uin_y));
+            const R corr = R(6.0) * wflow<R>(i) * (R(EX[i]) * R(a.uin_x) + R(EY[i]) * R(a.uin_y)) * fscale<MODE, R>(a);
             n.h[i] = v + corr;
         } else if (c == OUTLET) {
             if (a.lumped) {
                 const int d = ((nt[i] >> WALL_SHIFT) & 3) + 1;
-                n.h[i] = v + R(6.0) * wflow<R>(i) * (R(EX[i] * EX[d] + EY[i] * EY[d]) * R(*a.useep));
+                n.h[i] = v + R(6.0) * wflow<R>(i) * (R(EX[i] * EX[d] + EY[i] * EY[d]) * R(*a.useep)) * fscale<MODE, R>(a);
             } else {
-                n.h[i] = -v + R(2.0) * lam<R>(i) * R(a.dp_out);
+                n.h[i] = -v + R(2.0) * lam<R>(i) * R(a.dp_out) * fscale<MODE, R>(a);
             }
         } else if (BC && w >= 0) {                        // interpolated bounce-back
             const double q = wall_fraction(a, w, i);
@@ -995,7 +1132,7 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
         const uint8_t wall = (nt[i] >> WALL_SHIFT) & 3;
         if (c == INLET || (c == SOLID && wall != WALL_BOX)) {
             const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
-            n.g[i] = -n.g[i] + R(2.0) * cst<R>(a.wT, a.wT32) * R(tw);
+            n.g[i] = -n.g[i] + R(2.0) * cst<R>(a.wT, a.wT32) * R(tw) * tscale<MODE, R>(a);
         }
     }
     if constexpr (BC) {
@@ -1006,8 +1143,7 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
         own.g[0] = R(lds[lds_g0<MODE>(ey, ex)]);
 #pragma unroll
         for (int i = 1; i <= 4; i++) own.g[i] = R(lds[lds_at<MODE>(7 + i, ey, ex)]);
-        const Moments<R> ms = moments(own);
-        extrapolate_links(a, nt, own, ms, n);
+        extrapolate_physical<MODE>(a, nt, own, n);
     }
 }
 
@@ -1308,11 +1444,12 @@ __global__ __launch_bounds__(256) void unpack_kernel(StepArgs a, int field, int 
     Node<R> n;
     if (a.bc_paper) pull_all<MODE, true>(a, (const typename T::S*)a.src, k, t, n);
     else pull_all<MODE, false>(a, (const typename T::S*)a.src, k, t, n);
-    const Moments<R> m = moments(n);
+    Node<double> nw;
+    const Moments<double> m = wide_moments<MODE>(a, n, nw);
     if (field == 7) {                        // all 13 populations, dense [13][ny][nx]
         const long long n2 = (long long)a.nx * a.ny;
-        for (int i = 1; i <= 8; i++) out[(i - 1) * n2 + d] = n.h[i];
-        for (int i = 0; i <= 4; i++) out[(8 + i) * n2 + d] = n.g[i];
+        for (int i = 1; i <= 8; i++) out[(i - 1) * n2 + d] = nw.h[i];
+        for (int i = 0; i <= 4; i++) out[(8 + i) * n2 + d] = nw.g[i];
         return;
     }
     if (field == 8) {                        // u_x then u_y, dense [2][ny][nx]
@@ -1333,8 +1470,8 @@ __global__ __launch_bounds__(256) void unpack_kernel(StepArgs a, int field, int 
     case 1: v = m.ux; break;
     case 2: v = m.uy; break;
     case 3: v = a.T_ref + (double)m.th; break;
-    case 4: v = n.h[q < 1 ? 1 : (q > 8 ? 8 : q)]; break;
-    default: v = n.g[q < 0 ? 0 : (q > 4 ? 4 : q)]; break;
+    case 4: v = nw.h[q < 1 ? 1 : (q > 8 ? 8 : q)]; break;
+    default: v = nw.g[q < 0 ? 0 : (q > 4 ? 4 : q)]; break;
     }
     out[d] = v;
 }

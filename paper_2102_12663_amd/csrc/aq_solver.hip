@@ -64,8 +64,16 @@ StepArgs make_args(const aq_solver* s, bool a_is_src)
     a.inv_st = 1.0 / s->st;
     a.omega_f32 = (float)a.omega_f;
     a.omega_t32 = (float)a.omega_t;
-    a.w0T32 = (float)a.w0T;
-    a.wT32 = (float)a.wT;
+    // thermal weights whose single-precision values sum to one exactly (w0T + 4 wT = 1 in
+    // real arithmetic), so the float collision conserves the thermal populations' sum:
+    // round the larger of the two groups and take the other as the exact remainder
+    if (P.w0 <= 0.5) {
+        a.wT32 = (float)a.wT;
+        a.w0T32 = 1.0f - 4.0f * a.wT32;           // 4 wT in [1/2, 1]: exact
+    } else {
+        a.w0T32 = (float)a.w0T;
+        a.wT32 = (1.0f - a.w0T32) * 0.25f;        // w0T in (1/2, 1): exact
+    }
     a.inv_cs2T32 = (float)a.inv_cs2T;
     a.nuK32 = (float)a.nuK;
     a.drag_den32 = (float)a.drag_den;
@@ -585,6 +593,27 @@ int create_common(const aq_params* P, const uint8_t* mask, const aq_wall_node* w
     return AQ_OK;
 }
 
+// The diagnostics of the state into workspace w (diagnostics_words doubles): the kernels
+// write every word they later read, so w needs no clearing.  Synchronises the stream.
+int diagnose_into(aq_solver* s, double* w, aq_diagnostics* out)
+{
+    const size_t words = diagnostics_words(s->P.nx, s->P.ny);
+    HIPCHK(launch_diagnostics(s->mode, make_readout_args(s), w, s->stream));
+    HIPCHK(hipMemcpyAsync(s->obs_pinned, w + words - 8, 8 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const double* r = s->obs_pinned;
+    out->step = s->step;
+    out->vortex_intensity = r[0];
+    out->u_max_fluid = r[1];
+    out->psi_max = r[2];
+    out->psi_max_x = (int32_t)r[3];
+    out->psi_max_y = (int32_t)r[4];
+    out->psi_min = r[5];
+    out->psi_min_x = (int32_t)r[6];
+    out->psi_min_y = (int32_t)r[7];
+    return AQ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -858,21 +887,7 @@ int aq_diagnose(aq_solver* s, void* ws, size_t ws_bytes, aq_diagnostics* out)
     if (!s || !ws || !out) return fail(AQ_EINVAL, "null argument");
     const size_t words = diagnostics_words(s->P.nx, s->P.ny);
     if (ws_bytes < words * sizeof(double) || ((uintptr_t)ws & 7)) return fail(AQ_EINVAL, "workspace too small or misaligned");
-    double* w = (double*)ws;
-    HIPCHK(launch_diagnostics(s->mode, make_readout_args(s), w, s->stream));
-    HIPCHK(hipMemcpyAsync(s->obs_pinned, w + words - 8, 8 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
-    const double* r = s->obs_pinned;
-    out->step = s->step;
-    out->vortex_intensity = r[0];
-    out->u_max_fluid = r[1];
-    out->psi_max = r[2];
-    out->psi_max_x = (int32_t)r[3];
-    out->psi_max_y = (int32_t)r[4];
-    out->psi_min = r[5];
-    out->psi_min_x = (int32_t)r[6];
-    out->psi_min_y = (int32_t)r[7];
-    return AQ_OK;
+    return diagnose_into(s, (double*)ws, out);
 }
 
 int aq_set_fusion(aq_solver* s, int32_t enable)

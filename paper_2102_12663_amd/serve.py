@@ -25,7 +25,11 @@ import numpy as np
 
 import aqinputs as A
 
-from . import Batch, Solver, F16S, F32, F64, AQ_OK
+from . import Batch, Solver, F16S, F32, F64, AQ_OK, AQ_RESULT_FLOOR
+
+# statuses of a finished request that count as a solve: residual below tol, or (F16S) the
+# state accepted at binary16's rounding floor by the IOP drift check
+SOLVED = (AQ_OK, AQ_RESULT_FLOOR)
 
 
 class ShapeCache:
@@ -78,12 +82,35 @@ def _percentile(v, q):
     return float(np.percentile(np.asarray(v), q)) if len(v) else float("nan")
 
 
+def default_budget(reserve_bytes=12 << 30, cap_bytes=288 * 10 ** 9):
+    """Serving arena: the device's free HBM (at most 288 GB) minus a reserve for the
+    runtime and everything else the process holds."""
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    return max(1 << 30, min(free, cap_bytes) - reserve_bytes)
+
+
+def latency_summary(finished, arrivals, t_stop):
+    """p50 / p99 latency over every request that arrived before t_stop: finished ones
+    with finish - arrival, unfinished ones censored at t_stop - arrival (so the percentiles
+    are lower bounds whenever any request is censored)."""
+    lat = [r["t_done"] - r["t_arrival"] for r in finished.values()]
+    cens = [t_stop - a for i, a in enumerate(arrivals) if a <= t_stop and i not in finished]
+    allv = lat + cens
+    return {"latency_p50_s": _percentile(allv, 50), "latency_p99_s": _percentile(allv, 99),
+            "latency_censored": len(cens), "latency_is_lower_bound": bool(cens),
+            "finished_latency_p50_s": _percentile(lat, 50), "finished_latency_p99_s": _percentile(lat, 99)}
+
+
 def run_requests(make, arrivals, *, budget_bytes, max_slots=512, max_active_nodes=0, tol=1e-6,
-                 drift_tol=1e-3, max_steps=200000, intervals_per_call=1, cache=None, time_limit=None,
-                 check_interval=100, log=None):
+                 drift_tol=1e-5, max_steps=200000, intervals_per_call=1, cache=None, time_limit=None,
+                 check_interval=100, log=None, on_start=None):
     """Admit request i (built by make(i) -> (params, mask, walls) when it is first
     considered) at its arrival time (seconds after start) into one batch and run until all
-    finish or `time_limit`.  Returns summary statistics and per-request records."""
+    finish or `time_limit`.  Admission is first come, first served, as the arena, the slots
+    and the active-node cap (max_active_nodes, 0 = none) allow.  on_start(batch) is called
+    once, after the first admissions and before the first interval (timing hooks).
+    Returns summary statistics and per-request records."""
     cache = cache or ShapeCache()
     b = Batch(budget_bytes=budget_bytes, max_slots=max_slots, max_active_nodes=max_active_nodes,
               max_tiles=1 << 21, check_interval=check_interval)
@@ -96,6 +123,7 @@ def run_requests(make, arrivals, *, budget_bytes, max_slots=512, max_active_node
     active_of = {}
     t0 = time.perf_counter()
     node_updates = 0.0
+    started = False
     while len(finished) < n_req:
         now = time.perf_counter() - t0
         if time_limit is not None and now > time_limit:
@@ -125,6 +153,10 @@ def run_requests(make, arrivals, *, budget_bytes, max_slots=512, max_active_node
             if not queue:
                 break
         if info["running"]:
+            if not started and on_start is not None:
+                extra = on_start(b)
+                node_updates += extra
+            started = True
             b.run(intervals_per_call)
             node_updates += info["active_nodes"] * intervals_per_call * check_interval
         for r in b.poll():
@@ -137,18 +169,22 @@ def run_requests(make, arrivals, *, budget_bytes, max_slots=512, max_active_node
                 log(r)
     wall = time.perf_counter() - t0
     b.close()
-    lat = [r["t_done"] - r["t_arrival"] for r in finished.values()]
-    ok = [r for r in finished.values() if r["status"] == AQ_OK]
-    return {
-        "requests": n_req, "finished": len(finished), "converged": len(ok),
+    solved = [r for r in finished.values() if r["status"] in SOLVED]
+    arrived = sum(1 for a in arrivals if a <= wall)
+    out = {
+        "requests": n_req, "arrived": arrived, "finished": len(finished), "unfinished": arrived - len(finished),
+        "converged": sum(r["status"] == AQ_OK for r in finished.values()),
+        "accepted_at_floor": sum(r["status"] == AQ_RESULT_FLOOR for r in finished.values()),
         "not_converged": sum(r["status"] == -5 for r in finished.values()),
         "diverged": sum(r["status"] == -4 for r in finished.values()),
         "fallbacks": sum(r["fallback"] for r in finished.values()),
-        "wall_s": wall, "solves_per_s": len(finished) / wall if wall > 0 else 0.0,
-        "latency_p50_s": _percentile(lat, 50), "latency_p99_s": _percentile(lat, 99),
+        "wall_s": wall, "solves_per_s": len(solved) / wall if wall > 0 else 0.0,
+        "finished_per_s": len(finished) / wall if wall > 0 else 0.0,
         "aggregate_active_mlups": node_updates / wall / 1e6 if wall > 0 else 0.0,
         "records": finished,
     }
+    out.update(latency_summary(finished, arrivals, wall))
+    return out
 
 
 def sweep(n=512, storage=F32, tol=1e-6, budget_bytes=64 << 30, max_steps=200000, **kw):
@@ -166,12 +202,50 @@ def poisson_arrivals(n, rate, seed0=1000):
     return out
 
 
-def serve(rate=50.0, duration=60.0, storage=F16S, tol=1e-6, budget_bytes=64 << 30, max_steps=200000,
-          seed0=1000, large_every=10, **kw):
+def stream_arrivals(rate=50.0, duration=60.0, seed0=1000):
     n = int(rate * duration * 1.5) + 10
-    arr = [t for t in poisson_arrivals(n, rate, seed0) if t <= duration]
+    return [t for t in poisson_arrivals(n, rate, seed0) if t <= duration]
+
+
+def serve(rate=50.0, duration=60.0, storage=F16S, tol=1e-6, budget_bytes=None, max_steps=200000,
+          seed0=1000, large_every=10, **kw):
+    """The Poisson serving stream: request i (sweep draw seed0 + i, every large_every-th a
+    2048x1024 eye) arrives at the i-th arrival time.  budget_bytes None: default_budget()."""
+    arr = stream_arrivals(rate, duration, seed0)
+    if budget_bytes is None:
+        budget_bytes = default_budget()
     return run_requests(lambda i: sweep_request(seed0 + i, storage, large_every=large_every), arr,
                         budget_bytes=budget_bytes, tol=tol, max_steps=max_steps, **kw)
+
+
+def one_at_a_time(make, arrivals, sample, *, tol=1e-6, max_steps=200000, storage=F64, t_stop=None):
+    """The plain one-instance path on a stream: each sampled request (indices `sample`)
+    solved alone, one after another, in `storage` (the single-lattice solver).  Returns the
+    measured service times and the first-come-first-served latencies of the whole stream
+    with the sampled service times taken in turn (request i gets sample i mod n), censored
+    at t_stop like the batched loop's."""
+    svc, solved = [], 0
+    for i in sample:
+        p, mask, walls = make(i)
+        p = A.Params(**{**p.asdict(), "storage": storage})
+        t0 = time.perf_counter()
+        s = Solver(p, mask, walls)
+        ok, _ = s.run_to_steady(tol, max_steps)
+        s.close()
+        svc.append(time.perf_counter() - t0)
+        solved += int(ok)
+    finished, t_free = {}, 0.0
+    for i, a in enumerate(arrivals):
+        start = max(a, t_free)
+        t_free = start + svc[i % len(svc)]
+        if t_stop is None or t_free <= t_stop:
+            finished[i] = {"t_done": t_free, "t_arrival": a}
+    stop = t_stop if t_stop is not None else t_free
+    out = {"sampled": len(sample), "sampled_solved": solved, "service_s_mean": float(np.mean(svc)),
+           "service_s": [round(v, 3) for v in svc], "solves_per_s": len(svc) / float(np.sum(svc)),
+           "finished_by_stop": len(finished)}
+    out.update(latency_summary(finished, arrivals, stop))
+    return out
 
 
 def thickness_update(h, rise, target, history):

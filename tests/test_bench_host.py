@@ -27,7 +27,7 @@ def test_traffic_reported_only_for_the_measured_source_and_kernel(tmp_path, monk
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     h = bench.kernel_source_hash()
     (tmp_path / "profiles").mkdir()
-    (tmp_path / "profiles" / "step_kernel_traffic.json").write_text(json.dumps(
+    (tmp_path / "profiles" / "kernel_traffic.json").write_text(json.dumps(
         {"eye64x32s0/f64": {"kernel": "step2_kernel<0, false, false>", "bytes_per_launch": 1234, "kernel_hash": h}}))
     assert bench.measured_traffic("eye64x32s0/f64", "step2_kernel<0, false, false> (two time steps per launch)") == 1234
     assert bench.measured_traffic("eye64x32s0/f64", "step_kernel<0, false, false, false>") is None
