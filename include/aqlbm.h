@@ -298,6 +298,17 @@ int aq_diagnostics_bytes(const aq_params* params, size_t* bytes);
  * the solver's stream.  AQ_EINVAL for a null or too small workspace. */
 int aq_diagnose(aq_solver* s, void* workspace, size_t workspace_bytes, aq_diagnostics* out);
 
+/* aq_diagnose without a caller workspace and without any device allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The workspace is a fixed 64 MiB array in device
+ * memory, one per GPU, held from the first call on that GPU until the process ends; the
+ * lattice must need at most that much (aq_diagnostics_bytes <= 64 MiB, about 4 M nodes),
+ * else AQ_EINVAL and nothing is launched.  Results are identical to aq_diagnose's.  All
+ * calls on one GPU share its array and leave their contents in it (nothing in it needs
+ * to start cleared): calls that overlap on one GPU, from different threads or on
+ * different streams without ordering, race.  Synchronises the solver's stream. */
+int aq_diagnose_noalloc(aq_solver* s, aq_diagnostics* out);
+
 /* Lumped meshwork outlet (AQ_OUTLET_LUMPED only): replace K_tm, h_tm and p_sc of a live
  * solve (the calibration loop of section 3.1 adjusts the meshwork thickness until the
  * steady IOP is the healthy one).  The seepage speed in effect becomes that of the new

@@ -31,7 +31,7 @@ EXPORTS = ("aq_version", "aq_last_error", "aq_required_bytes", "aq_create", "aq_
            "aq_batch_create", "aq_batch_admit", "aq_batch_run", "aq_batch_poll", "aq_batch_read_field",
            "aq_batch_observe", "aq_batch_release", "aq_batch_get_info", "aq_batch_destroy",
            "aq_batch_set_outlet", "aq_batch_resume", "aq_diagnostics_bytes", "aq_diagnose",
-           "aq_batch_diagnose", "aq_batch_run_timed")
+           "aq_batch_diagnose", "aq_diagnose_noalloc", "aq_batch_run_timed")
 
 
 class AqParams(C.Structure):
@@ -152,6 +152,7 @@ def load_library(path: str = LIB_PATH):
     L.aq_set_outlet.argtypes = [vp, C.c_double, C.c_double, C.c_double]
     L.aq_diagnostics_bytes.argtypes = [C.POINTER(AqParams), C.POINTER(sz)]
     L.aq_diagnose.argtypes = [vp, vp, sz, C.POINTER(AqDiagnostics)]
+    L.aq_diagnose_noalloc.argtypes = [vp, C.POINTER(AqDiagnostics)]
     L.aq_batch_diagnose.argtypes = [vp, i32, vp, sz, C.POINTER(AqDiagnostics)]
     L.aq_batch_set_outlet.argtypes = [vp, i32, C.c_double, C.c_double, C.c_double]
     L.aq_batch_resume.argtypes = [vp, i32, C.c_double, i64]
@@ -318,6 +319,13 @@ class Solver:
             torch.cuda.synchronize(self.device)
         d = AqDiagnostics()
         _check(_lib.aq_diagnose(self._h, C.c_void_p(self._diag_ws.data_ptr()), nb.value, C.byref(d)))
+        return d.asdict()
+
+    def diagnose_noalloc(self) -> dict:
+        """The same diagnostics through aq_diagnose_noalloc: the library's fixed per-GPU
+        workspace, no allocation (lattices up to 64 MiB of workspace)."""
+        d = AqDiagnostics()
+        _check(_lib.aq_diagnose_noalloc(self._h, C.byref(d)))
         return d.asdict()
 
     def set_outlet(self, K_tm: float, h_tm: float, p_sc: float):

@@ -86,6 +86,7 @@ struct aq_solver {
     bool own_mem = false;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int device = -1;              // HIP device current at creation (-1: not yet known)
 
     std::vector<uint8_t> htype;   // [ny][pitch]
     int64_t n_active = 0, n_fluid = 0, n_cornea = 0, n_iris = 0;

@@ -1,11 +1,13 @@
 // Host side of the aqlbm C-ABI (include/aqlbm.h): solver creation, device layout,
-// tile lists, HIP-graph chunks, observables and checkpoints.  No kernels live here.
+// tile lists, HIP-graph chunks, observables and checkpoints.  No kernels live here; the
+// only device object is the fixed diagnostics workspace of aq_diagnose_noalloc.
 #include "aq_internal.h"
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -554,6 +556,7 @@ int create_common(const aq_params* P, const uint8_t* mask, const aq_wall_node* w
     s->P = *P;
     s->mode = P->storage;
     s->L = make_layout(*P, n_walls);
+    if (hipGetDevice(&s->device) != hipSuccess) s->device = -1;   // resolved where it is needed
     if (own) {
         hipError_t e = hipMalloc((void**)&s->base, s->L.total);
         if (e != hipSuccess) {
@@ -611,6 +614,35 @@ int diagnose_into(aq_solver* s, double* w, aq_diagnostics* out)
     out->psi_min = r[5];
     out->psi_min_x = (int32_t)r[6];
     out->psi_min_y = (int32_t)r[7];
+    return AQ_OK;
+}
+
+// Fixed workspace of aq_diagnose_noalloc, for callers that cannot allocate device memory.
+// Every GPU the library runs on holds its own copy until the process ends.  In host code
+// `scratch` names a host-side stand-in, not device memory: its device address on each GPU
+// comes from hipGetSymbolAddress (with that GPU current), taken once per device and kept.
+constexpr size_t kDiagScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) double scratch[kDiagScratchBytes / sizeof(double)];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+int diag_scratch(int device, double** out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return fail(AQ_EDEVICE, "device index out of range");
+    if (!g_scratch_ptr[device]) {
+        int prev = 0;
+        HIPCHK(hipGetDevice(&prev));
+        if (prev != device) HIPCHK(hipSetDevice(device));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev != device) HIPCHK(hipSetDevice(prev));
+        if (e != hipSuccess) return fail(AQ_EDEVICE, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+        if (!p) return fail(AQ_EDEVICE, "hipGetSymbolAddress returned a null address");
+        g_scratch_ptr[device] = (double*)p;
+    }
+    *out = g_scratch_ptr[device];
     return AQ_OK;
 }
 
@@ -888,6 +920,23 @@ int aq_diagnose(aq_solver* s, void* ws, size_t ws_bytes, aq_diagnostics* out)
     const size_t words = diagnostics_words(s->P.nx, s->P.ny);
     if (ws_bytes < words * sizeof(double) || ((uintptr_t)ws & 7)) return fail(AQ_EINVAL, "workspace too small or misaligned");
     return diagnose_into(s, (double*)ws, out);
+}
+
+int aq_diagnose_noalloc(aq_solver* s, aq_diagnostics* out)
+{
+    if (!s || !out) return fail(AQ_EINVAL, "null argument");
+    const size_t need = diagnostics_words(s->P.nx, s->P.ny) * sizeof(double);
+    if (need > kDiagScratchBytes)
+        return fail(AQ_EINVAL, "lattice too large for the fixed diagnostics workspace: needs " + std::to_string(need) +
+                                   " bytes, " + std::to_string(kDiagScratchBytes) + " available (use aq_diagnose)");
+    if (s->device < 0 && hipGetDevice(&s->device) != hipSuccess) {
+        s->device = -1;
+        return fail(AQ_EDEVICE, "hipGetDevice failed");
+    }
+    double* w = nullptr;
+    const int rc = diag_scratch(s->device, &w);
+    if (rc) return rc;
+    return diagnose_into(s, w, out);
 }
 
 int aq_set_fusion(aq_solver* s, int32_t enable)
