@@ -1048,14 +1048,51 @@ template <int MODE> struct Fuse {
     static constexpr int THREADS = (MODE == 0 || MODE == 3) ? 512 : 256;
     static constexpr int EW = 66, EH = TY + 2;        // tile plus a one-node halo
     static constexpr int EN = EW * EH;                // step-A nodes
-    static constexpr int NA = (EN + THREADS - 1) / THREADS;   // step-A nodes per thread
-    // LDS image: h_1..h_8 and g_1..g_4 over tile + halo (planes 0..11); g_0 is only read
-    // by its own node, so it is kept for the tile nodes alone: 67 KB in FP64, two blocks
-    // (16 waves) per CU.
+    // Step A takes a thread's tile nodes first, each the node step B gives the same thread
+    // (NT passes), then the halo ring (NH nodes); so g_0, which only its own node reads, stays
+    // in the thread's registers between the steps and is not in the LDS image.
+    static constexpr int NT = TY * 64 / THREADS;
+    static constexpr int NH = 2 * EW + 2 * TY;
+    static constexpr int NA = NT + (NH + THREADS - 1) / THREADS;   // step-A nodes per thread
+    // LDS image: h_1..h_8 and g_1..g_4 over tile + halo (planes 0..11): 63 KB in FP64, two
+    // blocks (16 waves) per CU; 31 KB in the single-precision image, five blocks (20 waves).
     static constexpr int PLANES = 12;
-    static constexpr int WORDS = PLANES * EN + 64 * TY;
+    static constexpr int WORDS = PLANES * EN;
+    // resident blocks per CU the register budget is sized for (the LDS image allows it)
+    static constexpr int BLOCKS = (MODE == 0 || MODE == 3) ? 2 : 5;
     static_assert((TY * 64) % THREADS == 0, "step B covers the tile in whole passes");
+    static_assert(NT * THREADS + NH == EN, "the tile and its ring are the step-A nodes");
 };
+
+// Step-A node j of the calling thread in E coordinates (the tile is 1..64 x 1..TY);
+// false past the halo ring.
+template <int MODE>
+__device__ __forceinline__ bool step_a_node(int j, int& ex, int& ey)
+{
+    using F = Fuse<MODE>;
+    const int t = threadIdx.x;
+    if (j < F::NT) {
+        ex = (t & 63) + 1;
+        ey = (t >> 6) + (F::THREADS / 64) * j + 1;
+        return true;
+    }
+    const int h = t + F::THREADS * (j - F::NT);
+    if (h >= F::NH) return false;
+    if (h < F::EW) {
+        ex = h;
+        ey = 0;
+    } else if (h < 2 * F::EW) {
+        ex = h - F::EW;
+        ey = F::EH - 1;
+    } else if (h < 2 * F::EW + F::TY) {
+        ex = 0;
+        ey = h - 2 * F::EW + 1;
+    } else {
+        ex = F::EW - 1;
+        ey = h - 2 * F::EW - F::TY + 1;
+    }
+    return true;
+}
 
 template <int MODE>
 __device__ __forceinline__ int lds_at(int q, int ly, int lx)
@@ -1063,17 +1100,12 @@ __device__ __forceinline__ int lds_at(int q, int ly, int lx)
     return (q * Fuse<MODE>::EH + ly) * Fuse<MODE>::EW + lx;
 }
 
-// g_0 of tile node (lx, ly) in E coordinates (1 <= lx <= 64, 1 <= ly <= TY)
-template <int MODE>
-__device__ __forceinline__ int lds_g0(int ly, int lx)
-{
-    return Fuse<MODE>::PLANES * Fuse<MODE>::EN + (ly - 1) * 64 + (lx - 1);
-}
-
-// Pull from the LDS image of step n+1 (E coordinates: the tile node is (ex, ey)).
+// Pull from the LDS image of step n+1 (E coordinates: the tile node is (ex, ey)); g0 is
+// the node's own g_0 of step n+1, kept by the thread.
 template <int MODE, bool BC>
 __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Traits<MODE>::L* lds, int k, int ex,
-                                         int ey, uint8_t t, Node<typename Traits<MODE>::R>& n)
+                                         int ey, uint8_t t, typename Traits<MODE>::L g0,
+                                         Node<typename Traits<MODE>::R>& n)
 {
     using R = typename Traits<MODE>::R;
     const bool boundary = (t & F_BOUNDARY) != 0;
@@ -1091,7 +1123,7 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
 #pragma unroll
     for (int i = 1; i <= 8; i++)
         n.h[i] = up[i] ? lds[lds_at<MODE>(i - 1, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE>(OPP[i] - 1, ey, ex)];
-    n.g[0] = R(lds[lds_g0<MODE>(ey, ex)]);
+    n.g[0] = R(g0);
 #pragma unroll
     for (int i = 1; i <= 4; i++)
         n.g[i] = up[i] ? lds[lds_at<MODE>(7 + i, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE>(7 + OPP[i], ey, ex)];
@@ -1140,7 +1172,7 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
         Node<R> own;
 #pragma unroll
         for (int i = 1; i <= 8; i++) own.h[i] = R(lds[lds_at<MODE>(i - 1, ey, ex)]);
-        own.g[0] = R(lds[lds_g0<MODE>(ey, ex)]);
+        own.g[0] = R(g0);
 #pragma unroll
         for (int i = 1; i <= 4; i++) own.g[i] = R(lds[lds_at<MODE>(7 + i, ey, ex)]);
         extrapolate_physical<MODE>(a, nt, own, n);
@@ -1168,14 +1200,14 @@ __device__ __forceinline__ void encode_decoded(const StepArgs& a, const Node<typ
 }
 
 // Step A of one node (E coordinates ex, ey): collide, round as a store would, and keep the
-// decoded values in LDS.
+// decoded values in LDS; returns the decoded g_0, which only the node itself reads.
 template <int MODE>
-__device__ __forceinline__ void step_a_store(const StepArgs& a, const Node<typename Traits<MODE>::R>& n, bool porous,
-                                             int ex, int ey, typename Traits<MODE>::L* lds)
+__device__ __forceinline__ typename Traits<MODE>::L step_a_store(const StepArgs& a,
+                                                                 const Node<typename Traits<MODE>::R>& n, bool porous,
+                                                                 int ex, int ey, typename Traits<MODE>::L* lds)
 {
     using T = Traits<MODE>;
     using R = typename T::R;
-    using F = Fuse<MODE>;
     const Moments<R> m = moments(n);
     R hs[9], gs[5];
     collide<MODE>(a, porous, n, m, hs, gs);
@@ -1186,7 +1218,7 @@ __device__ __forceinline__ void step_a_store(const StepArgs& a, const Node<typen
     for (int q = 0; q < 8; q++) lds[lds_at<MODE>(q, ey, ex)] = (L)T::ldv(enc[q], cst<R>(a.inv_sf, a.inv_sf32));
 #pragma unroll
     for (int i = 1; i <= 4; i++) lds[lds_at<MODE>(7 + i, ey, ex)] = (L)T::ldv(enc[8 + i], cst<R>(a.inv_st, a.inv_st32));
-    if (ex >= 1 && ex <= 64 && ey >= 1 && ey <= F::TY) lds[lds_g0<MODE>(ey, ex)] = (L)T::ldv(enc[8], cst<R>(a.inv_st, a.inv_st32));
+    return (L)T::ldv(enc[8], cst<R>(a.inv_st, a.inv_st32));
 }
 
 // PF: step A issues the loads of all of a thread's nodes before computing any (more bytes
@@ -1201,17 +1233,23 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
     const int x0 = tx * 64, y0 = ty * F::TY;
     const typename T::S* src = (const typename T::S*)a.src;
     typename T::S* dst = (typename T::S*)a.dst;
-    // step A: step n+1 on the tile and its halo, into LDS
+    // step A: step n+1 on the tile and its halo, into LDS (g_0 of the tile nodes kept)
+    using L = typename T::L;
+    L g0A[F::NT];
+#pragma unroll
+    for (int j = 0; j < F::NT; j++) g0A[j] = L(0);
     if constexpr (PF) {
         // each thread owns NA nodes and issues the loads of all of them before computing
-        int kA[F::NA];
+        int kA[F::NA], exA[F::NA], eyA[F::NA];
         uint8_t tA[F::NA];
 #pragma unroll
         for (int j = 0; j < F::NA; j++) {
-            const int e = threadIdx.x + F::THREADS * j;
-            const int ex = e % F::EW, ey = e / F::EW;
+            int ex = 0, ey = 0;
+            const bool node = step_a_node<MODE>(j, ex, ey);
+            exA[j] = ex;
+            eyA[j] = ey;
             const int x = x0 - 1 + ex, y = y0 - 1 + ey;
-            const bool in = e < F::EN && x >= 0 && y >= 0 && x < a.nx && y < a.ny;
+            const bool in = node && x >= 0 && y >= 0 && x < a.nx && y < a.ny;
             kA[j] = in ? y * a.pitch + x : 0;
             tA[j] = in ? *at(a.type, 0, (unsigned)kA[j]) : (uint8_t)0;   // 0 = SOLID: not active
         }
@@ -1226,13 +1264,16 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
         for (int j = 0; j < F::NA; j++) pull_rules<MODE, BC>(a, src, kA[j], tA[j], ntA[j], nA[j]);
 #pragma unroll
         for (int j = 0; j < F::NA; j++) {
-            const int e = threadIdx.x + F::THREADS * j;
-            if (is_active(tA[j])) step_a_store<MODE>(a, nA[j], (tA[j] & CLS_MASK) == POROUS, e % F::EW, e / F::EW, lds);
+            if (!is_active(tA[j])) continue;
+            const L g0 = step_a_store<MODE>(a, nA[j], (tA[j] & CLS_MASK) == POROUS, exA[j], eyA[j], lds);
+            if (j < F::NT) g0A[j] = g0;
         }
     } else {
         // one node at a time (fewer registers)
-        for (int e = threadIdx.x; e < F::EN; e += F::THREADS) {
-            const int ex = e % F::EW, ey = e / F::EW;
+#pragma unroll
+        for (int j = 0; j < F::NA; j++) {
+            int ex = 0, ey = 0;
+            if (!step_a_node<MODE>(j, ex, ey)) continue;
             const int x = x0 - 1 + ex, y = y0 - 1 + ey;
             if (x < 0 || y < 0 || x >= a.nx || y >= a.ny) continue;
             const int k = y * a.pitch + x;
@@ -1240,7 +1281,8 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
             if (!is_active(t)) continue;
             Node<R> n;
             pull_all<MODE, BC>(a, src, k, t, n);
-            step_a_store<MODE>(a, n, (t & CLS_MASK) == POROUS, ex, ey, lds);
+            const L g0 = step_a_store<MODE>(a, n, (t & CLS_MASK) == POROUS, ex, ey, lds);
+            if (j < F::NT) g0A[j] = g0;
         }
     }
     __syncthreads();
@@ -1254,7 +1296,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
         const uint8_t t = *at(a.type, 0, (unsigned)k);
         if (!is_active(t)) continue;
         Node<R> n;
-        pull_lds<MODE, BC>(a, lds, k, lx + 1, ly + 1, t, n);
+        pull_lds<MODE, BC>(a, lds, k, lx + 1, ly + 1, t, g0A[r], n);
         const Moments<R> m = moments(n);
         R hs[9], gs[5];
         collide<MODE>(a, (t & CLS_MASK) == POROUS, n, m, hs, gs);
@@ -1265,7 +1307,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
 // Two time steps of one lattice; one block per active 64 x TY tile (tile list in
 // a.tiles, laid out with a.tiles_x = ceil(nx / 64) tiles per row).
 template <int MODE, bool NT, bool BC>
-__global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void step2_kernel(StepArgs a)
+__global__ __launch_bounds__(Fuse<MODE>::THREADS, Fuse<MODE>::BLOCKS) void step2_kernel(StepArgs a)
 {
     __shared__ typename Traits<MODE>::L lds[Fuse<MODE>::WORDS];
     process_tile2<MODE, NT, true, BC>(a, a.tiles[tile_of_block(a)], lds);
@@ -1308,7 +1350,7 @@ int fused_tile_rows(int mode)
 // Two time steps of every running instance of a batch in kernel class b.kind (fused tile
 // work list; the same item assignment and argument loads as batch_step_kernel).
 template <int MODE, bool NT, bool BC>
-__global__ __launch_bounds__(Fuse<MODE>::THREADS, 4) void batch_step2_kernel(BatchArgs b)
+__global__ __launch_bounds__(Fuse<MODE>::THREADS, Fuse<MODE>::BLOCKS) void batch_step2_kernel(BatchArgs b)
 {
     __shared__ typename Traits<MODE>::L lds[Fuse<MODE>::WORDS];
     const int w = batch_item();
