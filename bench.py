@@ -316,13 +316,14 @@ def config1_steady(seed=0, nx=2048, ny=1024):
     return out
 
 
-def serve_stream(rate=50.0, duration=60.0, time_limit=150.0, storage="f16s", max_active_nodes=8_000_000,
-                 n_sample=12, sample_steps=200000):
+def serve_stream(rate=50.0, duration=60.0, time_limit=150.0, storage="f16s", max_active_nodes=16_000_000,
+                 n_sample=20, sample_steps=200000):
     """The serving stream (Poisson arrivals, every 10th request a 2048x1024 eye, residual
     1e-6, F16S with the IOP drift check and the F32 hand-off), the arena sized to the free
     HBM, admission capped at max_active_nodes running active nodes, stopped at time_limit
     seconds; beside it the one-at-a-time FP64 path on the same stream from n_sample
-    requests solved alone (evenly spaced over the stream)."""
+    requests solved alone (spread over the stream and over its mix: request i is a
+    2048x1024 eye when i % 10 == 9, and the sample walks the residues 0..9)."""
     from paper_2102_12663_amd import serve as S
     import paper_2102_12663_amd as aq
     done = [0]
@@ -336,8 +337,8 @@ def serve_stream(rate=50.0, duration=60.0, time_limit=150.0, storage="f16s", max
                 intervals_per_call=5, time_limit=time_limit, max_active_nodes=max_active_nodes, log=progress)
     r.pop("records")
     arr = S.stream_arrivals(rate, duration)
-    step = max(1, len(arr) // n_sample)
-    sample = list(range(0, len(arr), step))[:n_sample]
+    stride = max(10, len(arr) // n_sample // 10 * 10)
+    sample = [min(len(arr) - 1, j * stride + j % 10) for j in range(n_sample)]
     log(f"serve: one-at-a-time FP64 on {len(sample)} sampled requests")
     base = S.one_at_a_time(lambda i: S.sweep_request(1000 + i, aq.F64, large_every=10), arr, sample,
                            tol=1e-6, max_steps=sample_steps, storage=aq.F64, t_stop=time_limit)
