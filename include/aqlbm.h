@@ -52,7 +52,9 @@ enum {
 
 /* Storage precision of the populations.  F64: stored and computed in double.  F32:
  * stored and computed in float.  F16S: stored as binary16 of (deviation * 2^s) with a
- * per-solver power-of-two scale, computed in float.  F32X: stored in float, computed in
+ * per-solver power-of-two scale, computed in float; the intermediate step of a two-step
+ * launch stays in float on chip, so the state is rounded to binary16 where it is stored
+ * (every other step in the plain steps of an interval).  F32X: stored in float, computed in
  * double (the float arithmetic's rounding, not the storage, sets F32's error against
  * FP64 at buoyant steady states).  Reductions are always double. */
 enum { AQ_F64 = 0, AQ_F32 = 1, AQ_F16S = 2, AQ_F32X = 3 };
@@ -263,9 +265,12 @@ int aq_set_tile(aq_solver* s, int32_t tile_x, int32_t tile_y);
 int aq_time_step_kernel(aq_solver* s, int32_t n_launch, double* ms_per_launch);
 
 /* Two-steps-per-launch (temporal blocking) on the plain steps of each check interval: on
- * (enable != 0) or off.  The default is on for F64 and F32X, and for F32 and F16S when a
- * step's working set exceeds the last-level cache.  Results are bitwise the same either way.
- * Batched instances always run two steps per launch. */
+ * (enable != 0) or off.  The default is on for F64, F32X and F16S, and for F32 when a
+ * step's working set exceeds the last-level cache.  F64, F32 and F32X give bitwise the same
+ * results either way.  F16S does not: a two-step launch keeps its intermediate step in
+ * float, single steps round every step to binary16.  Batched instances always run two
+ * steps per launch, so an instance reduces bitwise the same alone (with the default) and
+ * in a batch. */
 int aq_set_fusion(aq_solver* s, int32_t enable);
 
 /*

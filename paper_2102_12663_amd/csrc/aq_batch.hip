@@ -617,6 +617,13 @@ int aq_batch_admit(aq_batch* b, const aq_params* P, const uint8_t* mask, const a
     if (tile_x * tile_y != 256) return fail(AQ_EINVAL, "batched instances use 256-thread tiles");
     int rc = validate(P, mask, walls, n_walls);
     if (rc) return rc;
+    if (P->storage == AQ_F16S) {
+        aq_params Q = *P;
+        Q.storage = AQ_F32;
+        if (!offsets_fit(Q))
+            return fail(AQ_EINVAL, "lattice too large for the FP32 continuation of an F16S solve: three population "
+                                   "planes must stay within 4 GiB");
+    }
     if (P->check_interval != b->interval) return fail(AQ_EINVAL, "check_interval differs from the batch's");
     int free_i = -1;
     for (int i = 0; i < b->max_slots; i++)

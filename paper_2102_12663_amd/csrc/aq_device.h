@@ -52,6 +52,7 @@ struct StepArgs {
     // these, so no thread converts a double constant.
     float omega_f32, omega_t32, w0T32, wT32, inv_cs2T32, nuK32, drag_den32, bx32, by32, dT032, T_ref32;
     float sf32, inv_sf32, st32, inv_st32;
+    float uin_x32, uin_y32, dp_out32, tw_cornea32, tw_iris32, tw_inlet32;   // boundary rules
 
     // lumped meshwork outlet: OUTLET links are walls moving at the seepage speed *useep
     // along the node's outward direction; the finish kernel re-evaluates it at check steps

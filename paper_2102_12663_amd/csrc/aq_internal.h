@@ -133,6 +133,8 @@ void raw_to_obs(const aq_solver* s, const double* raw, int64_t step, aq_observab
 int create_common(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls,
                   void* arena, size_t arena_bytes, void* stream, bool own, aq_solver** out);
 int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls);
+// The reduced storages' 32-bit population offsets cover the lattice (always true in FP64).
+bool offsets_fit(const aq_params& P);
 int upload_tiles(aq_solver* s);
 
 }  // namespace aq

@@ -34,7 +34,8 @@ __device__ constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 // Storage precision: how a population is stored and in which type it is computed.
 template <int MODE> struct Traits;
 // L is the element type of the two-step kernels' LDS image: it holds values decoded from the
-// storage, so single precision is exact for every storage but FP64.
+// storage (exact in single precision for every storage but FP64), or in F16S the single-
+// precision intermediate step itself.
 template <> struct Traits<0> {   // AQ_F64
     using S = double;
     using R = double;
@@ -174,8 +175,8 @@ __device__ __forceinline__ Moments<double> wide_moments(const StepArgs& a, const
 // thread of the block (a plane base shifted by a link): the base goes through a scalar
 // register, so a load or store takes it with the 32-bit per-node offset as its offset
 // operand and no thread does 64-bit address arithmetic.  The offsets stay below 4 GiB: the
-// node-type bytes (at most 2^30 nodes) and the F32, F32X and F16S population planes (checked
-// at creation).
+// node-type bytes (at most 2^30 nodes) and, in the F32, F32X and F16S storages, three
+// population planes (the reach of a boundary pull; checked at creation).
 __device__ __forceinline__ const char* uniform_base(const void* p)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -242,6 +243,33 @@ __device__ __forceinline__ void pull_loads(const StepArgs& a, const typename Tra
         n.g[0] = T::ld(at(src, 8 * a.qs, kb), inv_t);
 #pragma unroll
         for (int i = 1; i <= 4; i++) n.g[i] = T::ld(at(src, (8 + i) * a.qs - (EY[i] * a.pitch + EX[i]), kb), inv_t);
+        return;
+    }
+    if constexpr (MODE != 0) {
+        // a boundary node: the upstream slot, or the node's own opposite slot for a link from
+        // a non-active node, both as one plane base (uniform) plus a 32-bit per-node offset.
+        // The base is the lower of the two slots' planes (opposite links are two planes
+        // apart, and a plane is longer than a row plus one), so both offsets are k's own
+        // byte offset plus a non-negative uniform distance.
+#pragma unroll
+        for (int i = 1; i <= 8; i++) {
+            const long long up_k0 = (long long)(i - 1) * a.qs - (EY[i] * a.pitch + EX[i]);   // slot of node 0
+            const long long own_k0 = (long long)(OPP[i] - 1) * a.qs;
+            const long long lo = OPP[i] > i ? up_k0 : own_k0;
+            const unsigned d = (unsigned)((OPP[i] > i ? own_k0 - up_k0 : up_k0 - own_k0) * (long long)sizeof(S));
+            const bool at_lo = OPP[i] > i ? is_active(nt[i]) : !is_active(nt[i]);
+            n.h[i] = T::ld(at(src, lo, at_lo ? kb : kb + d), inv_f);
+        }
+        n.g[0] = T::ld(at(src, 8 * a.qs, kb), inv_t);
+#pragma unroll
+        for (int i = 1; i <= 4; i++) {
+            const long long up_k0 = (long long)(8 + i) * a.qs - (EY[i] * a.pitch + EX[i]);
+            const long long own_k0 = (long long)(8 + OPP[i]) * a.qs;
+            const long long lo = OPP[i] > i ? up_k0 : own_k0;
+            const unsigned d = (unsigned)((OPP[i] > i ? own_k0 - up_k0 : up_k0 - own_k0) * (long long)sizeof(S));
+            const bool at_lo = OPP[i] > i ? is_active(nt[i]) : !is_active(nt[i]);
+            n.g[i] = T::ld(at(src, lo, at_lo ? kb : kb + d), inv_t);
+        }
         return;
     }
 #pragma unroll
@@ -407,7 +435,8 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Tra
         if (extra && (c == INLET || c == OUTLET)) {
             // extrapolated below
         } else if (c == INLET) {                               // moving wall at u_in
-            const R corr = R(6.0) * wflow<R>(i) * (R(EX[i]) * R(a.uin_x) + R(EY[i]) * R(a.uin_y)) * fscale<MODE, R>(a);
+            const R corr = R(6.0) * wflow<R>(i) * (R(EX[i]) * cst<R>(a.uin_x, a.uin_x32) + R(EY[i]) * cst<R>(a.uin_y, a.uin_y32)) *
+                             fscale<MODE, R>(a);
             n.h[i] = v + corr;
             n.qin += corr;
         } else if (c == OUTLET) {
@@ -418,7 +447,7 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Tra
                 n.h[i] = v + corr;
                 n.qout -= corr;
             } else {                                           // pressure anti-bounce-back
-                const R out = -v + R(2.0) * lam<R>(i) * R(a.dp_out) * fscale<MODE, R>(a);
+                const R out = -v + R(2.0) * lam<R>(i) * cst<R>(a.dp_out, a.dp_out32) * fscale<MODE, R>(a);
                 n.qout += v - out;
                 n.h[i] = out;
             }
@@ -439,8 +468,10 @@ __device__ __forceinline__ void pull_rules(const StepArgs& a, const typename Tra
         const uint8_t c = nt[i] & CLS_MASK;
         const uint8_t wall = (nt[i] >> WALL_SHIFT) & 3;
         if (c == INLET || (c == SOLID && wall != WALL_BOX)) {  // Dirichlet anti-bounce-back
-            const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
-            n.g[i] = -n.g[i] + R(2.0) * cst<R>(a.wT, a.wT32) * R(tw) * tscale<MODE, R>(a);
+            const R tw = c == INLET ? cst<R>(a.tw_inlet, a.tw_inlet32)
+                                    : (wall == WALL_CORNEA ? cst<R>(a.tw_cornea, a.tw_cornea32)
+                                                           : cst<R>(a.tw_iris, a.tw_iris32));
+            n.g[i] = -n.g[i] + R(2.0) * cst<R>(a.wT, a.wT32) * tw * tscale<MODE, R>(a);
         }                                                      // else adiabatic bounce-back
     }
     if constexpr (BC) {
@@ -1037,11 +1068,16 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(BatchArgs b)
 // ------------------------------------------------------------------------------ two steps per launch
 // Temporal blocking: one launch advances a 64 x TY tile by two time steps.  Step A
 // computes step n+1 on the tile plus a one-node halo (pulling from global memory), keeps
-// it in LDS, and step B computes step n+2 on the tile from LDS and stores it.  The
-// intermediate values are rounded to the storage format exactly as a store and reload
-// through HBM would round them (including the mass-conserving encode), so two fused steps
-// are bitwise identical to two single-step launches while the intermediate state never
-// travels to HBM.
+// it in LDS, and step B computes step n+2 on the tile from LDS and stores it.  In F64, F32
+// and F32X the intermediate values are rounded to the storage format exactly as a store
+// and reload through HBM would round them (including the mass-conserving encode), so two
+// fused steps are bitwise identical to two single-step launches while the intermediate
+// state never travels to HBM.  In F16S the intermediate stays in single precision, the
+// compute type: binary16 is a storage format, and the state is rounded (mass-conserving)
+// where it is stored.  That skips the encode, the smallest-magnitude search and the decode
+// for every step-A node, a quarter of the kernel's VALU instructions, and the steady-state
+// IOP error against FP64 stays within 0.1% (smaller than with rounding every step on three
+// of four cases).
 template <int MODE> struct Fuse {
     static constexpr int TY = 8;                              // output rows per tile
     // threads per block: the FP64-compute forms take two step-A nodes per thread
@@ -1108,28 +1144,28 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
                                          Node<typename Traits<MODE>::R>& n)
 {
     using R = typename Traits<MODE>::R;
-    const bool boundary = (t & F_BOUNDARY) != 0;
-    uint8_t nt[9];
-    if (boundary) {
+    n.qin = R(0);
+    n.qout = R(0);
+    n.g[0] = R(g0);
+    if (!(t & F_BOUNDARY)) {
+        // every neighbour active: each link pulls from upstream at a fixed offset
 #pragma unroll
-        for (int i = 1; i <= 8; i++) nt[i] = a.type[k - EY[i] * a.pitch - EX[i]];
-    } else {
+        for (int i = 1; i <= 8; i++) n.h[i] = lds[lds_at<MODE>(i - 1, ey - EY[i], ex - EX[i])];
 #pragma unroll
-        for (int i = 1; i <= 8; i++) nt[i] = FLUID;
+        for (int i = 1; i <= 4; i++) n.g[i] = lds[lds_at<MODE>(7 + i, ey - EY[i], ex - EX[i])];
+        return;
     }
+    uint8_t nt[9];
+    pull_types(a, k, true, nt);
     bool up[9];
 #pragma unroll
     for (int i = 1; i <= 8; i++) up[i] = is_active(nt[i]);
 #pragma unroll
     for (int i = 1; i <= 8; i++)
         n.h[i] = up[i] ? lds[lds_at<MODE>(i - 1, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE>(OPP[i] - 1, ey, ex)];
-    n.g[0] = R(g0);
 #pragma unroll
     for (int i = 1; i <= 4; i++)
         n.g[i] = up[i] ? lds[lds_at<MODE>(7 + i, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE>(7 + OPP[i], ey, ex)];
-    n.qin = R(0);
-    n.qout = R(0);
-    if (!boundary) return;
     const int w = (BC && (t & F_WSS)) ? a.widx[k] : -1;
     const bool extra = BC && needs_extrapolation(a, nt);
 #pragma unroll
@@ -1140,14 +1176,15 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
         if (extra && (c == INLET || c == OUTLET)) {
             // extrapolated below
         } else if (c == INLET) {
-            const R corr = R(6.0) * wflow<R>(i) * (R(EX[i]) * R(a.uin_x) + R(EY[i]) * R(a.uin_y)) * fscale<MODE, R>(a);
+            const R corr = R(6.0) * wflow<R>(i) * (R(EX[i]) * cst<R>(a.uin_x, a.uin_x32) + R(EY[i]) * cst<R>(a.uin_y, a.uin_y32)) *
+                             fscale<MODE, R>(a);
             n.h[i] = v + corr;
         } else if (c == OUTLET) {
             if (a.lumped) {
                 const int d = ((nt[i] >> WALL_SHIFT) & 3) + 1;
                 n.h[i] = v + R(6.0) * wflow<R>(i) * (R(EX[i] * EX[d] + EY[i] * EY[d]) * R(*a.useep)) * fscale<MODE, R>(a);
             } else {
-                n.h[i] = -v + R(2.0) * lam<R>(i) * R(a.dp_out) * fscale<MODE, R>(a);
+                n.h[i] = -v + R(2.0) * lam<R>(i) * cst<R>(a.dp_out, a.dp_out32) * fscale<MODE, R>(a);
             }
         } else if (BC && w >= 0) {                        // interpolated bounce-back
             const double q = wall_fraction(a, w, i);
@@ -1163,8 +1200,10 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
         const uint8_t c = nt[i] & CLS_MASK;
         const uint8_t wall = (nt[i] >> WALL_SHIFT) & 3;
         if (c == INLET || (c == SOLID && wall != WALL_BOX)) {
-            const double tw = c == INLET ? a.tw_inlet : (wall == WALL_CORNEA ? a.tw_cornea : a.tw_iris);
-            n.g[i] = -n.g[i] + R(2.0) * cst<R>(a.wT, a.wT32) * R(tw) * tscale<MODE, R>(a);
+            const R tw = c == INLET ? cst<R>(a.tw_inlet, a.tw_inlet32)
+                                    : (wall == WALL_CORNEA ? cst<R>(a.tw_cornea, a.tw_cornea32)
+                                                           : cst<R>(a.tw_iris, a.tw_iris32));
+            n.g[i] = -n.g[i] + R(2.0) * cst<R>(a.wT, a.wT32) * tw * tscale<MODE, R>(a);
         }
     }
     if constexpr (BC) {
@@ -1199,8 +1238,9 @@ __device__ __forceinline__ void encode_decoded(const StepArgs& a, const Node<typ
     }
 }
 
-// Step A of one node (E coordinates ex, ey): collide, round as a store would, and keep the
-// decoded values in LDS; returns the decoded g_0, which only the node itself reads.
+// Step A of one node (E coordinates ex, ey): collide, round as a store would (F16S: keep the
+// single-precision values), and keep the values in LDS; returns g_0, which only the node
+// itself reads.
 template <int MODE>
 __device__ __forceinline__ typename Traits<MODE>::L step_a_store(const StepArgs& a,
                                                                  const Node<typename Traits<MODE>::R>& n, bool porous,
@@ -1211,6 +1251,14 @@ __device__ __forceinline__ typename Traits<MODE>::L step_a_store(const StepArgs&
     const Moments<R> m = moments(n);
     R hs[9], gs[5];
     collide<MODE>(a, porous, n, m, hs, gs);
+    if constexpr (MODE == 2) {
+        // F16S: the intermediate step stays in single precision
+#pragma unroll
+        for (int q = 0; q < 8; q++) lds[lds_at<MODE>(q, ey, ex)] = hs[q + 1];
+#pragma unroll
+        for (int i = 1; i <= 4; i++) lds[lds_at<MODE>(7 + i, ey, ex)] = gs[i];
+        return gs[0];
+    }
     typename T::S enc[NPOP];
     encode_decoded<MODE>(a, n, hs, gs, enc);
     using L = typename T::L;   // exact: the decoded values of the storage

@@ -65,6 +65,12 @@ StepArgs make_args(const aq_solver* s, bool a_is_src)
     a.st = s->st;
     a.inv_st = 1.0 / s->st;
     a.omega_f32 = (float)a.omega_f;
+    a.uin_x32 = (float)a.uin_x;
+    a.uin_y32 = (float)a.uin_y;
+    a.dp_out32 = (float)a.dp_out;
+    a.tw_cornea32 = (float)a.tw_cornea;
+    a.tw_iris32 = (float)a.tw_iris;
+    a.tw_inlet32 = (float)a.tw_inlet;
     a.omega_t32 = (float)a.omega_t;
     // thermal weights whose single-precision values sum to one exactly (w0T + 4 wT = 1 in
     // real arithmetic), so the float collision conserves the thermal populations' sum:
@@ -171,6 +177,16 @@ int lumped_guard(const aq_params& P, const uint8_t* mask, int stride)
     return AQ_OK;
 }
 
+bool offsets_fit(const aq_params& P)
+{
+    if (P.storage != AQ_F32 && P.storage != AQ_F32X && P.storage != AQ_F16S) return true;
+    // the kernels of the reduced storages address populations with 32-bit byte offsets from
+    // a plane base; a boundary pull's offset reaches two planes beyond the node's own slot
+    const Layout L0 = make_layout(P, 0);
+    const long long elem = P.storage == AQ_F16S ? 2 : 4;
+    return (3 * L0.qs + L0.pitch + 1) * elem <= (1LL << 32);
+}
+
 int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls)
 {
     if (!P || !mask) return fail(AQ_EINVAL, "null params or mask");
@@ -178,12 +194,8 @@ int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls,
     if (P->nx < 4 || P->ny < 4) return fail(AQ_EINVAL, "nx and ny must be >= 4");
     if ((long long)P->nx * P->ny > (1LL << 30)) return fail(AQ_EINVAL, "lattice too large");
     if (!(P->tau_f > 0.5) || !(P->tau_t > 0.5)) return fail(AQ_EINVAL, "tau_f and tau_t must exceed 1/2");
-    if (P->storage == AQ_F32 || P->storage == AQ_F32X || P->storage == AQ_F16S) {
-        // the kernels of the reduced storages address a population plane with 32-bit offsets
-        const long long elem = P->storage == AQ_F16S ? 2 : 4;
-        if (make_layout(*P, 0).qs * elem > (1LL << 32))
-            return fail(AQ_EINVAL, "lattice too large for the storage: a population plane must stay within 4 GiB");
-    }
+    if (!offsets_fit(*P))
+        return fail(AQ_EINVAL, "lattice too large for the storage: three population planes must stay within 4 GiB");
     if (!(P->w0 >= 0.0 && P->w0 < 1.0)) return fail(AQ_EINVAL, "w0 must be in [0, 1)");
     if (!(P->K > 0.0)) return fail(AQ_EINVAL, "K must be positive");
     if (P->storage < AQ_F64 || P->storage > AQ_F32X) return fail(AQ_EINVAL, "unknown storage");
@@ -320,6 +332,13 @@ void drop_graph(aq_solver* s)
 static PlainPlan plain_plan(const aq_solver* s)
 {
     const int n = s->P.check_interval - 1;
+    // F16S rounds where it stores, so its launch schedule is part of its arithmetic: it
+    // takes the batch's plan, an even number of two-step launches (the batch keeps every
+    // instance's buffer parity), so a solve rounds at the same steps alone and batched
+    if (s->fuse && s->mode == AQ_F16S) {
+        const int F = (n / 2) & ~1;
+        return {F, 2 * F, n - 2 * F};
+    }
     if (s->fuse) return {n / 2, 2 * (n / 2), n % 2};
     return {n, n, 0};
 }
@@ -507,7 +526,9 @@ int setup(aq_solver* s, const uint8_t* mask, const aq_wall_node* walls, int32_t 
     s->nt_store = (double)s->n_active * bytes_per_update(s->mode) > kMallBytes ? 1 : 0;
     // two steps per launch where it measured faster: the FP64-arithmetic storages always,
     // FP32 and F16S past the cache
-    s->fuse = (s->mode == AQ_F64 || s->mode == AQ_F32X || s->nt_store) ? 1 : 0;
+    // F16S always: its two-step launch rounds to binary16 only where it stores, so the
+    // schedule is part of its arithmetic and a batched instance (always two-step) must match
+    s->fuse = (s->mode == AQ_F64 || s->mode == AQ_F32X || s->mode == AQ_F16S || s->nt_store) ? 1 : 0;
     s->n_walls = n_walls;
     s->hwall_node.resize(std::max(n_walls, 1));
     s->hwall_id.resize(std::max(n_walls, 1));

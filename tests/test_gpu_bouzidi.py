@@ -78,8 +78,11 @@ def test_bouzidi_offgrid_box_parity(aq):
     s.close()
 
 
-@pytest.mark.parametrize("storage", [A.F64, A.F32, A.F16S, A.F32X])
+@pytest.mark.parametrize("storage", [A.F64, A.F32, A.F32X])
 def test_bouzidi_two_step_launches_bitwise(aq, storage):
+    """Two steps per launch give bitwise the single-step result with the paper's schemes
+    (F16S rounds where it stores, so its schedule differs by design; its paper-scheme
+    solve is checked alone against batched in test_paper_scheme_in_a_batch_bitwise)."""
     p, mask, walls = _eye(storage=storage)
     out = []
     for fuse in (False, True):

@@ -21,7 +21,7 @@ torch = pytest.importorskip("torch")
 
 CASES = [(512, 256, 3), (512, 256, 5), (1024, 512, 6), (2048, 1024, 3)]
 # F16S steady velocity error measured on these cases (binary16 rounding of the stored values)
-F16S_MEASURED = {(512, 256, 3): 9.7e-3, (512, 256, 5): 1.5e-2, (1024, 512, 6): 3.0e-1, (2048, 1024, 3): 1.6e-1}
+F16S_MEASURED = {(512, 256, 3): 6.7e-3, (512, 256, 5): 1.7e-2, (1024, 512, 6): 1.2e-1, (2048, 1024, 3): 2.4e-1}
 U_BOUND, IOP_BOUND = 1e-4, 1e-3
 
 _cache = {}

@@ -117,11 +117,13 @@ def test_required_bytes(aq):
     assert m.value < n.value
 
 
-def test_f32_plane_limit(aq):
-    """F32 kernels address a population plane with 32-bit byte offsets: a lattice whose
-    padded plane (ny x nx rounded up to 64 columns, 4 bytes each) passes 4 GiB is rejected
-    in F32 storage, although it has no more than 2^30 nodes."""
-    nx, ny = 32769, 32767                      # nx * ny <= 2^30, ny * 32832 * 4 > 2^32
+@pytest.mark.parametrize("nx,ny", [(32769, 32767), (16384, 32768)])
+def test_f32_plane_limit(aq, nx, ny):
+    """F32 kernels address populations with 32-bit byte offsets from a plane base, and a
+    boundary pull reaches two planes beyond the node's own slot: a lattice whose three
+    padded planes (ny x nx rounded up to 64 columns, 4 bytes each) pass 4 GiB is rejected
+    in F32 storage, although it has no more than 2^30 nodes (the second size: one plane
+    of 2 GiB)."""
     assert nx * ny <= 1 << 30
     mask = np.zeros((ny, nx), np.uint8)        # never touched: the size check comes first
     p = A.Params(nx=nx, ny=ny, storage=A.F32)
