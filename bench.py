@@ -3,9 +3,9 @@
 Headline workload: the batched parameter sweep of 512 eye sections (lattices 256x128 to
 1024x512, per-instance relaxation time, permeability, inflow, chamber angle, Rayleigh
 number and gravity orientation, all seeded), FP32 populations, resident in one batch.  One
-benchmark step = one check interval of every instance: 98 time steps as 49 two-step
-launches, one single step and the reducing step (IOP, fluxes, wall shear stress,
-residuals).  The timed steps are taken inside the full sweep, which then continues until
+benchmark step = one check interval of every instance: 96 time steps as 48 two-step
+launches (an even number: the batch keeps every instance's buffer parity), three single
+steps and the reducing step (IOP, fluxes, wall shear stress, residuals).  The timed steps are taken inside the full sweep, which then continues until
 every instance has reached its steady residual of 1e-6 (solves/s, p50/p99 latency).
 
 Further fields: the 8192x4096 eye in FP64, the 8192x4096 precision sweep, the 2048x1024 eye
