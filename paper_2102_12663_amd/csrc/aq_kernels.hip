@@ -243,6 +243,9 @@ __device__ __forceinline__ void pull_loads(const StepArgs& a, const typename Tra
         n.g[0] = T::ld(at(src, 8 * a.qs, kb), inv_t);
 #pragma unroll
         for (int i = 1; i <= 4; i++) n.g[i] = T::ld(at(src, (8 + i) * a.qs - (EY[i] * a.pitch + EX[i]), kb), inv_t);
+        // keeps the compiler from merging these loads with the boundary path's into one set
+        // with per-lane 64-bit addresses (it waits for nothing: no loaded value is used)
+        __asm__ volatile("" ::: "memory");
         return;
     }
     if constexpr (MODE != 0) {
@@ -1299,7 +1302,10 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
             const int x = x0 - 1 + ex, y = y0 - 1 + ey;
             const bool in = node && x >= 0 && y >= 0 && x < a.nx && y < a.ny;
             kA[j] = in ? y * a.pitch + x : 0;
-            tA[j] = in ? *at(a.type, 0, (unsigned)kA[j]) : (uint8_t)0;   // 0 = SOLID: not active
+            // unconditional (node 0 when outside), so the node offset stays a plain 32-bit
+            // value and every load takes the scalar-base-plus-offset form
+            const uint8_t tk = *at(a.type, 0, (unsigned)kA[j]);
+            tA[j] = in ? tk : (uint8_t)0;   // 0 = SOLID: not active
         }
         Node<R> nA[F::NA];
         uint8_t ntA[F::NA][9];
