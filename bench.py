@@ -8,9 +8,10 @@ launches (an even number: the batch keeps every instance's buffer parity), three
 steps and the reducing step (IOP, fluxes, wall shear stress, residuals).  The timed steps are taken inside the full sweep, which then continues until
 every instance has reached its steady residual of 1e-6 (solves/s, p50/p99 latency).
 
-Further fields: the 8192x4096 eye in FP64, the 8192x4096 precision sweep, the 2048x1024 eye
-per storage, the Poisson serving stream with the one-at-a-time FP64 path beside it, and the
-oracle on the host cores.  Prints one JSON line.
+Further fields: the 8192x4096 eye in FP64 (active and lattice MLUPS), a plain device copy's
+bandwidth, the dense 8192x4096 box (every interior node active) in FP64, FP32 and F16S, the
+8192x4096 precision sweep, the 2048x1024 eye per storage, the Poisson serving stream with the
+one-at-a-time FP64 path beside it, and the oracle on the host cores.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 """
@@ -351,6 +352,11 @@ def serve_stream(rate=50.0, duration=60.0, time_limit=150.0, storage="f16s", max
     return out
 
 
+def aq_copy_GBs():
+    import paper_2102_12663_amd as aq
+    return aq.copy_bandwidth(1 << 30, 5)
+
+
 def dense_box(storages, intervals=10, nx=8192, ny=4096):
     """An 8192x4096 closed box, every interior node active (heated floor, cooled lid,
     buoyancy on), per storage: active MLUPS and the roofline of the graph-part launches."""
@@ -473,8 +479,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--extra", action="store_true",
-                    help="also the dense 8192x4096 box, the lumped-outlet and paper-boundary variants of "
-                         "the 2048x1024 eye and the thickness calibration")
+                    help="also the dense 8192x4096 box in F32X, the lumped-outlet and paper-boundary variants "
+                         "of the 2048x1024 eye and the thickness calibration")
     ap.add_argument("--precision-steady", action="store_true",
                     help="only the steady-state precision comparison of FP32, F16S and F32X against FP64")
     ap.add_argument("--config1-steady", action="store_true",
@@ -544,7 +550,15 @@ def main():
         e = eye_run("f64", 8192, 4096, 0, 10, 2)
         r = roofline("eye8192x4096s0/f64", e["kernel"], "f64", e["active_nodes"], e["launch_ms"])
         out["fp64_8192x4096"] = {"workload": "8192x4096 eye section (sweep draw seed 0), f64, 10 check intervals",
-                                 "mlups": round(e["mlups"], 1), "active_nodes": e["active_nodes"], "roofline": r}
+                                 "mlups": round(e["mlups"], 1), "active_nodes": e["active_nodes"],
+                                 "lattice_mlups": round(e["mlups"] * 8192 * 4096 / e["active_nodes"], 1),
+                                 "roofline": r}
+        log("copy bandwidth")
+        out["copy_kernel"] = {"GBs": round(aq_copy_GBs(), 1), "bytes": 1 << 30,
+                              "kernel": "copy_kernel: 16-byte words, four in flight per thread, grid-stride, 4096 blocks of 256; "
+                                        "(read + written bytes) / time, best of 5 after one warm-up"}
+        log("dense box")
+        out["dense_box"] = dense_box(("f64", "f32", "f16s"))
         log("2048x1024 per storage")
         out["eye2048x1024"] = {st: brief(eye_run(st, 2048, 1024, 0, 20, 2), st, f"eye2048x1024s0/{st}")
                                for st in ("f64", "f32", "f16s", "f32x")}
@@ -554,7 +568,7 @@ def main():
             log("serving stream")
             out["serve"] = serve_stream()
         if args.extra:
-            out["dense_box"] = dense_box(("f64", "f32", "f16s", "f32x"))
+            out["dense_box_f32x"] = dense_box(("f32x",))
             e = eye_run("f64", 2048, 1024, 0, 20, 2, tm="lumped")
             out["lumped_outlet"] = {**brief(e, "f64", "eye2048x1024s0/f64-lumped"), "iop_gauge": e["obs"]["iop_gauge"],
                                     "u_seep": e["obs"]["u_seep"]}

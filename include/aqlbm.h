@@ -331,11 +331,19 @@ int aq_time_fused_kernel(aq_solver* s, int32_t n_launch, double* ms_per_launch);
  * runs n_intervals * check_interval steps (the current step must be a multiple of
  * check_interval) and returns the total elapsed milliseconds and the milliseconds spent
  * in the graph part of every interval, i.e. aq_info.graph_launches launches per interval:
- * (check_interval - 2) / 2 two-step launches when fusion is on, else check_interval - 1
- * single steps.  The remaining single step (fusion on) and the reducing step are outside
- * the graph part. */
+ * (check_interval - 2) / 2 two-step launches when fusion is on (F16S: that number
+ * rounded down to even, as in a batch), else check_interval - 1 single steps.  The
+ * remaining single steps and the reducing step are outside the graph part. */
 int aq_run_intervals_timed(aq_solver* s, int32_t n_intervals, double* total_ms,
                            double* plain_ms);
+
+/* Bandwidth of a plain device copy on the current device (context for the step kernels'
+ * HBM rates): allocates two buffers of `bytes` bytes (a multiple of 16, at least 1 MiB),
+ * copies the first into the second `reps` times with a grid-stride kernel of 16-byte
+ * words (four in flight per thread) on 256 CUs x 16 blocks, and frees them.  *gbs receives the best rep's
+ * (read + written bytes) / time in GB/s, timed with HIP events.  AQ_EINVAL for invalid
+ * sizes, AQ_ENOMEM if the buffers do not fit, AQ_EDEVICE on a HIP error. */
+int aq_copy_bandwidth(size_t bytes, int32_t reps, double* gbs);
 
 /* ------------------------------------------------------------------------------------
  * Batched serving form: many independent solves (parameter sweeps of uneven lattice

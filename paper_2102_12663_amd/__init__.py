@@ -31,7 +31,7 @@ EXPORTS = ("aq_version", "aq_last_error", "aq_required_bytes", "aq_create", "aq_
            "aq_batch_create", "aq_batch_admit", "aq_batch_run", "aq_batch_poll", "aq_batch_read_field",
            "aq_batch_observe", "aq_batch_release", "aq_batch_get_info", "aq_batch_destroy",
            "aq_batch_set_outlet", "aq_batch_resume", "aq_diagnostics_bytes", "aq_diagnose",
-           "aq_batch_diagnose", "aq_diagnose_noalloc", "aq_batch_run_timed")
+           "aq_batch_diagnose", "aq_diagnose_noalloc", "aq_batch_run_timed", "aq_copy_bandwidth")
 
 
 class AqParams(C.Structure):
@@ -169,11 +169,20 @@ def load_library(path: str = LIB_PATH):
     L.aq_batch_release.argtypes = [vp, i32]
     L.aq_batch_get_info.argtypes = [vp, C.POINTER(AqBatchInfo)]
     L.aq_batch_destroy.argtypes = [vp]
+    L.aq_copy_bandwidth.argtypes = [sz, i32, C.POINTER(C.c_double)]
     for name in EXPORTS:
         if name not in ("aq_version", "aq_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
+
+
+def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """GB/s (read + written bytes over time) of a plain device copy of nbytes, best of reps."""
+    load_library()
+    g = C.c_double()
+    _check(_lib.aq_copy_bandwidth(nbytes, reps, C.byref(g)))
+    return g.value
 
 
 def _check(rc):

@@ -1055,6 +1055,70 @@ int aq_run_intervals_timed(aq_solver* s, int32_t n, double* total_ms, double* pl
     return AQ_OK;
 }
 
+// A plain device copy in 16-byte words, grid-stride with four words in flight per thread
+// (all four loads before the stores): the bandwidth a streaming kernel reaches on this
+// GPU, the context for the step kernels' moved bytes.
+__global__ __launch_bounds__(256) void copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
+static hipError_t launch_copy(const void* src, void* dst, size_t words16, int blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, words16);
+    return hipGetLastError();
+}
+
+int aq_copy_bandwidth(size_t bytes, int32_t reps, double* gbs)
+{
+    if (!gbs || reps < 1 || bytes < ((size_t)1 << 20) || (bytes & 15))
+        return fail(AQ_EINVAL, "bytes must be a multiple of 16 and at least 1 MiB, reps at least 1");
+    void* src = nullptr;
+    void* dst = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    auto release = [&]() {
+        if (ev[0]) (void)hipEventDestroy(ev[0]);
+        if (ev[1]) (void)hipEventDestroy(ev[1]);
+        if (st) (void)hipStreamDestroy(st);
+        if (src) (void)hipFree(src);
+        if (dst) (void)hipFree(dst);
+    };
+    hipError_t e = hipMalloc(&src, bytes);
+    if (e == hipSuccess) e = hipMalloc(&dst, bytes);
+    if (e == hipErrorOutOfMemory) {
+        release();
+        return fail(AQ_ENOMEM, "the copy buffers do not fit");
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e == hipSuccess) e = hipMemsetAsync(src, 0, bytes, st);
+    double best = 0;
+    for (int r = 0; r <= reps && e == hipSuccess; r++) {   // the first pass warms up
+        e = hipEventRecord(ev[0], st);
+        if (e == hipSuccess) e = launch_copy(src, dst, bytes / 16, 256 * 16, st);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (e == hipSuccess && r > 0 && ms > 0) best = std::max(best, 2.0 * (double)bytes / ((double)ms * 1e6));
+    }
+    release();
+    if (e != hipSuccess) return fail(AQ_EDEVICE, std::string("copy bandwidth: ") + hipGetErrorString(e));
+    *gbs = best;
+    return AQ_OK;
+}
+
 // Checkpoint file: magic, version, aq_params, step, last check step, exponents, then the
 // current and previous population buffers (storage precision) and the residual reference.
 int aq_save(aq_solver* s, const char* path)

@@ -40,3 +40,14 @@ def test_bench_line_contract():
     per_step_bytes = rf["bytes_per_active_node_launch"] * d["config"]["active_nodes"] / 2 * 100
     assert per_step_bytes / (d["ms_per_step"] * 1e-3) / 1e9 <= 8000.0
     assert d["sweep512"]["solves_per_s"] >= 0
+
+
+def test_copy_bandwidth_is_physical():
+    """The plain copy kernel over 1 GiB (2 GiB of traffic per pass, far past the 256 MB
+    last-level cache) reports a positive rate below the 8 TB/s HBM peak."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2102_12663_amd as aq
+    g = aq.copy_bandwidth(1 << 30, 3)
+    print(f"[bench] copy kernel {g:.0f} GB/s", flush=True)
+    assert 1000.0 < g < 8000.0

@@ -129,3 +129,12 @@ def test_f32_plane_limit(aq, nx, ny):
     p = A.Params(nx=nx, ny=ny, storage=A.F32)
     rc, err = _create(aq, p, mask)
     assert rc == aq.AQ_EINVAL and "4 GiB" in err
+
+
+@pytest.mark.parametrize("nbytes,reps", [(100, 1), (1 << 20, 0), ((1 << 20) + 8, 1)])
+def test_copy_bandwidth_rejects_invalid_sizes(aq, nbytes, reps):
+    """aq_copy_bandwidth checks its arguments before touching a device: sizes below 1 MiB
+    or not a multiple of 16 bytes, and no repetitions, are AQ_EINVAL."""
+    g = C.c_double(-1.0)
+    assert aq._lib.aq_copy_bandwidth(nbytes, reps, C.byref(g)) == aq.AQ_EINVAL
+    assert g.value == -1.0
