@@ -555,7 +555,7 @@ def main():
                                  "roofline": r}
         log("copy bandwidth")
         out["copy_kernel"] = {"GBs": round(aq_copy_GBs(), 1), "bytes": 1 << 30,
-                              "kernel": "copy_kernel: 16-byte words, four in flight per thread, grid-stride, 4096 blocks of 256; "
+                              "kernel": "copy_kernel: 16-byte words, non-temporal stores, grid-stride, 2048 blocks of 256; "
                                         "(read + written bytes) / time, best of 5 after one warm-up"}
         log("dense box")
         out["dense_box"] = dense_box(("f64", "f32", "f16s"))

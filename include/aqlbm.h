@@ -340,7 +340,7 @@ int aq_run_intervals_timed(aq_solver* s, int32_t n_intervals, double* total_ms,
 /* Bandwidth of a plain device copy on the current device (context for the step kernels'
  * HBM rates): allocates two buffers of `bytes` bytes (a multiple of 16, at least 1 MiB),
  * copies the first into the second `reps` times with a grid-stride kernel of 16-byte
- * words (four in flight per thread) on 256 CUs x 16 blocks, and frees them.  *gbs receives the best rep's
+ * words with non-temporal stores on 256 CUs x 8 blocks, and frees them.  *gbs receives the best rep's
  * (read + written bytes) / time in GB/s, timed with HIP events.  AQ_EINVAL for invalid
  * sizes, AQ_ENOMEM if the buffers do not fit, AQ_EDEVICE on a HIP error. */
 int aq_copy_bandwidth(size_t bytes, int32_t reps, double* gbs);

@@ -1055,26 +1055,20 @@ int aq_run_intervals_timed(aq_solver* s, int32_t n, double* total_ms, double* pl
     return AQ_OK;
 }
 
-// A plain device copy in 16-byte words, grid-stride with four words in flight per thread
-// (all four loads before the stores): the bandwidth a streaming kernel reaches on this
-// GPU, the context for the step kernels' moved bytes.
-__global__ __launch_bounds__(256) void copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n)
+// A plain device copy in 16-byte words, grid-stride, with non-temporal stores (the step
+// kernels' store form past the last-level cache): the bandwidth a streaming kernel reaches
+// on this GPU, the context for the step kernels' moved bytes.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void copy_kernel(const u32x4* __restrict__ src, u32x4* __restrict__ dst, size_t n)
 {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {
-        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-        dst[i] = a;
-        dst[i + stride] = b;
-        dst[i + 2 * stride] = c;
-        dst[i + 3 * stride] = d;
-    }
-    for (; i < n; i += stride) dst[i] = src[i];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        __builtin_nontemporal_store(src[i], &dst[i]);
 }
 
 static hipError_t launch_copy(const void* src, void* dst, size_t words16, int blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, words16);
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, s, (const u32x4*)src, (u32x4*)dst, words16);
     return hipGetLastError();
 }
 
@@ -1106,7 +1100,7 @@ int aq_copy_bandwidth(size_t bytes, int32_t reps, double* gbs)
     double best = 0;
     for (int r = 0; r <= reps && e == hipSuccess; r++) {   // the first pass warms up
         e = hipEventRecord(ev[0], st);
-        if (e == hipSuccess) e = launch_copy(src, dst, bytes / 16, 256 * 16, st);
+        if (e == hipSuccess) e = launch_copy(src, dst, bytes / 16, 256 * 8, st);
         if (e == hipSuccess) e = hipEventRecord(ev[1], st);
         if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
         float ms = 0;
