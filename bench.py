@@ -47,9 +47,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key, kernel):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source and the same kernel; else None."""
+def measured_entry(key, kernel):
+    """The committed rocprofv3 summary of a kernel (HBM bytes per launch, VALU figures), if
+    it was taken on the current kernel source and the same kernel; else None."""
     path = os.path.join(ROOT, "profiles", "kernel_traffic.json")
     if not os.path.exists(path):
         return None
@@ -58,7 +58,14 @@ def measured_traffic(key, kernel):
     e = d.get(key)
     if not e or e.get("kernel_hash") != kernel_source_hash() or not kernel.startswith(e.get("kernel", "?")):
         return None
-    return e.get("bytes_per_launch")
+    return e
+
+
+def measured_traffic(key, kernel):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source and the same kernel; else None."""
+    e = measured_entry(key, kernel)
+    return e.get("bytes_per_launch") if e else None
 
 
 def roofline(key, kernel, storage, active_nodes, launch_ms):
@@ -67,12 +74,17 @@ def roofline(key, kernel, storage, active_nodes, launch_ms):
     beside it the bytes the HBM counters saw (when committed for this kernel source)."""
     bpl = BYTES_PER_NODE_LAUNCH[storage] * active_nodes
     achieved = bpl / (launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic(key, kernel)
+    e = measured_entry(key, kernel)
+    traffic = e.get("bytes_per_launch") if e else None
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
             "kernel_ms": round(launch_ms, 5), "bytes_per_launch": bpl,
             "bytes_per_active_node_launch": BYTES_PER_NODE_LAUNCH[storage],
-            "counter_GBs": round(traffic / (launch_ms * 1e-3) / 1e9, 1) if traffic else None}
+            "counter_GBs": round(traffic / (launch_ms * 1e-3) / 1e9, 1) if traffic else None,
+            # from the same committed profile: VALU wave instructions per busy CU cycle (1.0 =
+            # the four 16-lane SIMDs' issue limit) and per wave
+            "valu_issue": e.get("valu_issue") if e else None,
+            "valu_per_wave": e.get("valu_per_wave") if e else None}
 
 
 # ---------------------------------------------------------------------------------- oracle
