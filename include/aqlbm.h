@@ -265,8 +265,8 @@ int aq_set_tile(aq_solver* s, int32_t tile_x, int32_t tile_y);
 int aq_time_step_kernel(aq_solver* s, int32_t n_launch, double* ms_per_launch);
 
 /* Two-steps-per-launch (temporal blocking) on the plain steps of each check interval: on
- * (enable != 0) or off.  The default is on for F64, F32X and F16S, and for F32 when a
- * step's working set exceeds the last-level cache.  F64, F32 and F32X give bitwise the same
+ * (enable != 0) or off.  The default is on for F64, F32X and F16S, and for F32 from 2^18
+ * active nodes or when a step's working set exceeds the last-level cache.  F64, F32 and F32X give bitwise the same
  * results either way.  F16S does not: a two-step launch keeps its intermediate step in
  * float, single steps round every step to binary16.  Batched instances always run two
  * steps per launch, so an instance reduces bitwise the same alone (with the default) and

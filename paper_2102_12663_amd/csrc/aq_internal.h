@@ -72,6 +72,9 @@ constexpr size_t kUseepOffset = 128;
 // MI355X last-level cache (MALL) holds 256 MB.
 constexpr double kMallBytes = 192.0 * 1024 * 1024;
 
+// FP32 lattices with at least this many active nodes run two steps per launch by default.
+constexpr long long kFuseMinActive = 1LL << 18;
+
 }  // namespace aq
 
 struct PlainPlan {

@@ -524,11 +524,14 @@ int setup(aq_solver* s, const uint8_t* mask, const aq_wall_node* walls, int32_t 
         }
     // the read and written populations of a step exceed the last-level cache: stream the writes
     s->nt_store = (double)s->n_active * bytes_per_update(s->mode) > kMallBytes ? 1 : 0;
-    // two steps per launch where it measured faster: the FP64-arithmetic storages always,
-    // FP32 and F16S past the cache
-    // F16S always: its two-step launch rounds to binary16 only where it stores, so the
-    // schedule is part of its arithmetic and a batched instance (always two-step) must match
-    s->fuse = (s->mode == AQ_F64 || s->mode == AQ_F32X || s->mode == AQ_F16S || s->nt_store) ? 1 : 0;
+    // two steps per launch where it measured faster: the FP64-arithmetic storages always;
+    // FP32 from kFuseMinActive active nodes or past the cache (below, the 64 x 8 tiles are
+    // too few blocks to fill the chip: 1024x512 eye 22.2k MLUPS in single steps against
+    // 17.6k, 2048x1024 45.9k against 48.0k); F16S always, since its two-step launch rounds
+    // to binary16 only where it stores, so the schedule is part of its arithmetic and a
+    // batched instance (always two-step) must match
+    s->fuse = (s->mode == AQ_F64 || s->mode == AQ_F32X || s->mode == AQ_F16S || s->nt_store ||
+               (s->mode == AQ_F32 && s->n_active >= kFuseMinActive)) ? 1 : 0;
     s->n_walls = n_walls;
     s->hwall_node.resize(std::max(n_walls, 1));
     s->hwall_id.resize(std::max(n_walls, 1));
