@@ -192,7 +192,7 @@ typedef struct aq_info {
     int32_t fusion;                 /* 1: the plain steps run two per launch */
     int32_t graph_launches;         /* launches replayed from a graph per check interval */
     int32_t nt_store;               /* 1: population stores bypass the caches (non-temporal) */
-    int32_t reserved0;
+    int32_t fused_tile_rows;        /* rows of a two-step tile (64 wide): 8, or 4 (F32, F16S) */
     int64_t step;
     size_t device_bytes;
     double bytes_per_node_update;   /* algorithmic HBM bytes per active-node update */
@@ -272,6 +272,13 @@ int aq_time_step_kernel(aq_solver* s, int32_t n_launch, double* ms_per_launch);
  * steps per launch, so an instance reduces bitwise the same alone (with the default) and
  * in a batch. */
 int aq_set_fusion(aq_solver* s, int32_t enable);
+
+/* Rows of the two-step tiles (64 wide): 8, or 4 in F32 and F16S (twice the blocks, for
+ * lattices too small to fill the chip with 64 x 8 tiles).  The default is 4 for F32 and
+ * F16S lattices below 2^20 active nodes, else 8 (aq_info.fused_tile_rows).  Results are
+ * bitwise the same either way.  Synchronises the solver's stream; AQ_EINVAL for other
+ * values. */
+int aq_set_fused_tile_rows(aq_solver* s, int32_t rows);
 
 /*
  * Vortex diagnostics of the current state (section 3.5, Table 3, Figs. 6-7), computed on
@@ -446,8 +453,10 @@ int aq_batch_get_info(aq_batch* b, aq_batch_info* out);
 
 /* Autotune the tile shape of a solver: time n_launch plain launches for each candidate
  * shape (64x4, 128x2, 256x1, and 64x1, 64x2, 128x1 unless only_256 is set) and keep the
- * fastest; *tile_x, *tile_y and *ms_per_launch receive it.  The state advances by the
- * launched steps (n_launch even; reductions are skipped, as in aq_time_step_kernel). */
+ * fastest; *tile_x, *tile_y and *ms_per_launch receive it.  When two steps run per launch
+ * in an F32 or F16S solver, the two-step tiles 64x8 and 64x4 are timed too (n_launch / 2
+ * launches each) and the faster kept (aq_info.fused_tile_rows).  The state advances by
+ * the launched steps (n_launch even; reductions are skipped, as in aq_time_step_kernel). */
 int aq_autotune_tile(aq_solver* s, int32_t n_launch, int32_t only_256, int32_t* tile_x, int32_t* tile_y,
                      double* ms_per_launch);
 

@@ -31,7 +31,8 @@ EXPORTS = ("aq_version", "aq_last_error", "aq_required_bytes", "aq_create", "aq_
            "aq_batch_create", "aq_batch_admit", "aq_batch_run", "aq_batch_poll", "aq_batch_read_field",
            "aq_batch_observe", "aq_batch_release", "aq_batch_get_info", "aq_batch_destroy",
            "aq_batch_set_outlet", "aq_batch_resume", "aq_diagnostics_bytes", "aq_diagnose",
-           "aq_batch_diagnose", "aq_diagnose_noalloc", "aq_batch_run_timed", "aq_copy_bandwidth")
+           "aq_batch_diagnose", "aq_diagnose_noalloc", "aq_batch_run_timed", "aq_copy_bandwidth",
+           "aq_set_fused_tile_rows")
 
 
 class AqParams(C.Structure):
@@ -75,7 +76,7 @@ class AqInfo(C.Structure):
                 ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("n_tiles", C.c_int32),
                 ("check_interval", C.c_int32), ("fp16_exp_flow", C.c_int32),
                 ("fp16_exp_thermal", C.c_int32), ("fusion", C.c_int32), ("graph_launches", C.c_int32),
-                ("nt_store", C.c_int32), ("reserved0", C.c_int32),
+                ("nt_store", C.c_int32), ("fused_tile_rows", C.c_int32),
                 ("step", C.c_int64), ("device_bytes", C.c_size_t),
                 ("bytes_per_node_update", C.c_double)]
 
@@ -170,6 +171,7 @@ def load_library(path: str = LIB_PATH):
     L.aq_batch_get_info.argtypes = [vp, C.POINTER(AqBatchInfo)]
     L.aq_batch_destroy.argtypes = [vp]
     L.aq_copy_bandwidth.argtypes = [sz, i32, C.POINTER(C.c_double)]
+    L.aq_set_fused_tile_rows.argtypes = [vp, i32]
     for name in EXPORTS:
         if name not in ("aq_version", "aq_last_error"):
             getattr(L, name).restype = C.c_int
@@ -341,6 +343,9 @@ class Solver:
         """Lumped meshwork: new permeability, thickness and canal pressure; the seepage
         speed in effect is re-evaluated at once from the last check step's IOP."""
         _check(_lib.aq_set_outlet(self._h, float(K_tm), float(h_tm), float(p_sc)))
+
+    def set_fused_tile_rows(self, rows: int):
+        _check(_lib.aq_set_fused_tile_rows(self._h, rows))
 
     def set_fusion(self, enable: bool):
         _check(_lib.aq_set_fusion(self._h, int(bool(enable))))

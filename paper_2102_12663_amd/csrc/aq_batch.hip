@@ -431,7 +431,8 @@ int convert_to_f32(aq_batch* b, int i)
     aq_solver* s32 = nullptr;
     int rc = AQ_OK;
     if (e == hipSuccess) {
-        rc = create_common(&P, mask.data(), walls.data(), s16->n_walls, b->arena + off32, sl.bytes32, b->stream, false, &s32);
+        rc = create_common(&P, mask.data(), walls.data(), s16->n_walls, b->arena + off32, sl.bytes32, b->stream, false, &s32,
+                           fused_tile_rows(AQ_F32));
         if (rc == AQ_OK) rc = aq_set_tile(s32, s16->tile_x, s16->tile_y);
         if (rc == AQ_OK) {
             // lumped outlet: the seepage speeds carry over with the state
@@ -637,7 +638,8 @@ int aq_batch_admit(aq_batch* b, const aq_params* P, const uint8_t* mask, const a
     size_t off = 0;
     if (!b->pool.alloc(total, &off)) return fail(AQ_EBUSY, "not enough free HBM in the batch arena");
     aq_solver* s = nullptr;
-    rc = create_common(P, mask, walls, n_walls, b->arena + off, L.total, b->stream, false, &s);
+    rc = create_common(P, mask, walls, n_walls, b->arena + off, L.total, b->stream, false, &s,
+                       fused_tile_rows(P->storage));
     if (rc == AQ_OK) rc = aq_set_tile(s, tile_x, tile_y);
     if (rc == AQ_OK && b->max_active && running_active(b) + s->n_active > b->max_active)
         rc = fail(AQ_EBUSY, "active-node cap reached");

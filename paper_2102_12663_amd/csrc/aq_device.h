@@ -108,7 +108,8 @@ hipError_t launch_batch_step(int mode, bool reduce, const BatchArgs& b, int grid
 // Two plain time steps in one launch (tiles 64 x fused_tile_rows(mode) from a.tiles).
 hipError_t launch_step2(int mode, const StepArgs& a, hipStream_t s);
 hipError_t launch_batch_step2(int mode, const BatchArgs& b, int grid, hipStream_t s);
-int fused_tile_rows(int mode);
+int fused_tile_rows(int mode);   // the batch's tile rows (64 x 8)
+bool fused_rows_supported(int mode, int rows);
 hipError_t launch_batch_finish(const BatchArgs& b, hipStream_t s);
 // Write into a.dst the buffer whose pull gives the pre-collision populations `pops`
 // (dense [13][ny][nx] doubles), or, if pops is null, the rest equilibrium with

@@ -73,7 +73,10 @@ constexpr size_t kUseepOffset = 128;
 constexpr double kMallBytes = 192.0 * 1024 * 1024;
 
 // FP32 lattices with at least this many active nodes run two steps per launch by default.
-constexpr long long kFuseMinActive = 1LL << 18;
+constexpr long long kFuseMinActive = 1LL << 17;
+// F32 and F16S lattices below this many active nodes take 64 x 4 two-step tiles by default
+// (twice the blocks of 64 x 8).
+constexpr long long kFuse4MaxActive = 1LL << 20;
 
 }  // namespace aq
 
@@ -100,7 +103,8 @@ struct aq_solver {
     int tile_x = 64, tile_y = 4, tiles_x = 0, n_tiles = 0, xcd_remap = 1;
     int nt_store = 0;
     int fuse = 1;                 // two steps per launch on the plain steps of an interval
-    std::vector<int> htiles2;     // active 64 x fused_tile_rows tiles
+    std::vector<int> htiles2;     // active 64 x fuse_rows tiles
+    int fuse_rows = 0;            // rows of a two-step tile: 8, or 4 (F32 and F16S)
     int tiles_x2 = 0, n_tiles2 = 0;
     std::vector<int> htiles;      // active tile indices (host copy of the device list)
     int cur = 0;                  // 0: buffer A holds the state
@@ -134,7 +138,8 @@ double seepage_speed(const aq_params& P, double p_iop);
 int lumped_guard(const aq_params& P, const uint8_t* mask, int stride);
 void raw_to_obs(const aq_solver* s, const double* raw, int64_t step, aq_observables* o);
 int create_common(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls,
-                  void* arena, size_t arena_bytes, void* stream, bool own, aq_solver** out);
+                  void* arena, size_t arena_bytes, void* stream, bool own, aq_solver** out,
+                  int fuse_rows = 0);
 int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls);
 // The reduced storages' 32-bit population offsets cover the lattice (always true in FP64).
 bool offsets_fit(const aq_params& P);

@@ -1081,8 +1081,10 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(BatchArgs b)
 // for every step-A node, a quarter of the kernel's VALU instructions, and the steady-state
 // IOP error against FP64 stays within 0.1% (smaller than with rounding every step on three
 // of four cases).
-template <int MODE> struct Fuse {
-    static constexpr int TY = 8;                              // output rows per tile
+// TYv: output rows per tile.  64 x 8 everywhere; F32 and F16S also come in 64 x 4 (more
+// blocks for mid-size lattices, which 64 x 8 tiles leave partly idle).
+template <int MODE, int TYv = 8> struct Fuse {
+    static constexpr int TY = TYv;
     // threads per block: the FP64-compute forms take two step-A nodes per thread
     static constexpr int THREADS = (MODE == 0 || MODE == 3) ? 512 : 256;
     static constexpr int EW = 66, EH = TY + 2;        // tile plus a one-node halo
@@ -1098,17 +1100,17 @@ template <int MODE> struct Fuse {
     static constexpr int PLANES = 12;
     static constexpr int WORDS = PLANES * EN;
     // resident blocks per CU the register budget is sized for (the LDS image allows it)
-    static constexpr int BLOCKS = (MODE == 0 || MODE == 3) ? 2 : 5;
+    static constexpr int BLOCKS = (MODE == 0 || MODE == 3) ? 2 : TY == 4 ? 6 : 5;
     static_assert((TY * 64) % THREADS == 0, "step B covers the tile in whole passes");
     static_assert(NT * THREADS + NH == EN, "the tile and its ring are the step-A nodes");
 };
 
 // Step-A node j of the calling thread in E coordinates (the tile is 1..64 x 1..TY);
 // false past the halo ring.
-template <int MODE>
+template <int MODE, int TY>
 __device__ __forceinline__ bool step_a_node(int j, int& ex, int& ey)
 {
-    using F = Fuse<MODE>;
+    using F = Fuse<MODE, TY>;
     const int t = threadIdx.x;
     if (j < F::NT) {
         ex = (t & 63) + 1;
@@ -1133,15 +1135,15 @@ __device__ __forceinline__ bool step_a_node(int j, int& ex, int& ey)
     return true;
 }
 
-template <int MODE>
+template <int MODE, int TY>
 __device__ __forceinline__ int lds_at(int q, int ly, int lx)
 {
-    return (q * Fuse<MODE>::EH + ly) * Fuse<MODE>::EW + lx;
+    return (q * Fuse<MODE, TY>::EH + ly) * Fuse<MODE, TY>::EW + lx;
 }
 
 // Pull from the LDS image of step n+1 (E coordinates: the tile node is (ex, ey)); g0 is
 // the node's own g_0 of step n+1, kept by the thread.
-template <int MODE, bool BC>
+template <int MODE, bool BC, int TY>
 __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Traits<MODE>::L* lds, int k, int ex,
                                          int ey, uint8_t t, typename Traits<MODE>::L g0,
                                          Node<typename Traits<MODE>::R>& n)
@@ -1153,9 +1155,9 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
     if (!(t & F_BOUNDARY)) {
         // every neighbour active: each link pulls from upstream at a fixed offset
 #pragma unroll
-        for (int i = 1; i <= 8; i++) n.h[i] = lds[lds_at<MODE>(i - 1, ey - EY[i], ex - EX[i])];
+        for (int i = 1; i <= 8; i++) n.h[i] = lds[lds_at<MODE, TY>(i - 1, ey - EY[i], ex - EX[i])];
 #pragma unroll
-        for (int i = 1; i <= 4; i++) n.g[i] = lds[lds_at<MODE>(7 + i, ey - EY[i], ex - EX[i])];
+        for (int i = 1; i <= 4; i++) n.g[i] = lds[lds_at<MODE, TY>(7 + i, ey - EY[i], ex - EX[i])];
         return;
     }
     uint8_t nt[9];
@@ -1165,10 +1167,10 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
     for (int i = 1; i <= 8; i++) up[i] = is_active(nt[i]);
 #pragma unroll
     for (int i = 1; i <= 8; i++)
-        n.h[i] = up[i] ? lds[lds_at<MODE>(i - 1, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE>(OPP[i] - 1, ey, ex)];
+        n.h[i] = up[i] ? lds[lds_at<MODE, TY>(i - 1, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE, TY>(OPP[i] - 1, ey, ex)];
 #pragma unroll
     for (int i = 1; i <= 4; i++)
-        n.g[i] = up[i] ? lds[lds_at<MODE>(7 + i, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE>(7 + OPP[i], ey, ex)];
+        n.g[i] = up[i] ? lds[lds_at<MODE, TY>(7 + i, ey - EY[i], ex - EX[i])] : lds[lds_at<MODE, TY>(7 + OPP[i], ey, ex)];
     const int w = (BC && (t & F_WSS)) ? a.widx[k] : -1;
     const bool extra = BC && needs_extrapolation(a, nt);
 #pragma unroll
@@ -1192,9 +1194,9 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
         } else if (BC && w >= 0) {                        // interpolated bounce-back
             const double q = wall_fraction(a, w, i);
             if (q >= 0.5)
-                n.h[i] = bouzidi(R(q), v, R(lds[lds_at<MODE>(i - 1, ey, ex)]), R(0));
+                n.h[i] = bouzidi(R(q), v, R(lds[lds_at<MODE, TY>(i - 1, ey, ex)]), R(0));
             else if (q > 0.0 && up[OPP[i]])
-                n.h[i] = bouzidi(R(q), v, R(0), R(lds[lds_at<MODE>(OPP[i] - 1, ey + EY[i], ex + EX[i])]));
+                n.h[i] = bouzidi(R(q), v, R(0), R(lds[lds_at<MODE, TY>(OPP[i] - 1, ey + EY[i], ex + EX[i])]));
         }
     }
 #pragma unroll
@@ -1213,10 +1215,10 @@ __device__ __forceinline__ void pull_lds(const StepArgs& a, const typename Trait
         if (!extra) return;
         Node<R> own;
 #pragma unroll
-        for (int i = 1; i <= 8; i++) own.h[i] = R(lds[lds_at<MODE>(i - 1, ey, ex)]);
+        for (int i = 1; i <= 8; i++) own.h[i] = R(lds[lds_at<MODE, TY>(i - 1, ey, ex)]);
         own.g[0] = R(g0);
 #pragma unroll
-        for (int i = 1; i <= 4; i++) own.g[i] = R(lds[lds_at<MODE>(7 + i, ey, ex)]);
+        for (int i = 1; i <= 4; i++) own.g[i] = R(lds[lds_at<MODE, TY>(7 + i, ey, ex)]);
         extrapolate_physical<MODE>(a, nt, own, n);
     }
 }
@@ -1244,7 +1246,7 @@ __device__ __forceinline__ void encode_decoded(const StepArgs& a, const Node<typ
 // Step A of one node (E coordinates ex, ey): collide, round as a store would (F16S: keep the
 // single-precision values), and keep the values in LDS; returns g_0, which only the node
 // itself reads.
-template <int MODE>
+template <int MODE, int TY>
 __device__ __forceinline__ typename Traits<MODE>::L step_a_store(const StepArgs& a,
                                                                  const Node<typename Traits<MODE>::R>& n, bool porous,
                                                                  int ex, int ey, typename Traits<MODE>::L* lds)
@@ -1257,29 +1259,29 @@ __device__ __forceinline__ typename Traits<MODE>::L step_a_store(const StepArgs&
     if constexpr (MODE == 2) {
         // F16S: the intermediate step stays in single precision
 #pragma unroll
-        for (int q = 0; q < 8; q++) lds[lds_at<MODE>(q, ey, ex)] = hs[q + 1];
+        for (int q = 0; q < 8; q++) lds[lds_at<MODE, TY>(q, ey, ex)] = hs[q + 1];
 #pragma unroll
-        for (int i = 1; i <= 4; i++) lds[lds_at<MODE>(7 + i, ey, ex)] = gs[i];
+        for (int i = 1; i <= 4; i++) lds[lds_at<MODE, TY>(7 + i, ey, ex)] = gs[i];
         return gs[0];
     }
     typename T::S enc[NPOP];
     encode_decoded<MODE>(a, n, hs, gs, enc);
     using L = typename T::L;   // exact: the decoded values of the storage
 #pragma unroll
-    for (int q = 0; q < 8; q++) lds[lds_at<MODE>(q, ey, ex)] = (L)T::ldv(enc[q], cst<R>(a.inv_sf, a.inv_sf32));
+    for (int q = 0; q < 8; q++) lds[lds_at<MODE, TY>(q, ey, ex)] = (L)T::ldv(enc[q], cst<R>(a.inv_sf, a.inv_sf32));
 #pragma unroll
-    for (int i = 1; i <= 4; i++) lds[lds_at<MODE>(7 + i, ey, ex)] = (L)T::ldv(enc[8 + i], cst<R>(a.inv_st, a.inv_st32));
+    for (int i = 1; i <= 4; i++) lds[lds_at<MODE, TY>(7 + i, ey, ex)] = (L)T::ldv(enc[8 + i], cst<R>(a.inv_st, a.inv_st32));
     return (L)T::ldv(enc[8], cst<R>(a.inv_st, a.inv_st32));
 }
 
 // PF: step A issues the loads of all of a thread's nodes before computing any (more bytes
 // in flight, more registers).
-template <int MODE, bool NT, bool PF, bool BC>
+template <int MODE, bool NT, bool PF, bool BC, int TY>
 __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typename Traits<MODE>::L* lds)
 {
     using T = Traits<MODE>;
     using R = typename T::R;
-    using F = Fuse<MODE>;
+    using F = Fuse<MODE, TY>;
     const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
     const int x0 = tx * 64, y0 = ty * F::TY;
     const typename T::S* src = (const typename T::S*)a.src;
@@ -1296,7 +1298,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
 #pragma unroll
         for (int j = 0; j < F::NA; j++) {
             int ex = 0, ey = 0;
-            const bool node = step_a_node<MODE>(j, ex, ey);
+            const bool node = step_a_node<MODE, TY>(j, ex, ey);
             exA[j] = ex;
             eyA[j] = ey;
             const int x = x0 - 1 + ex, y = y0 - 1 + ey;
@@ -1319,7 +1321,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
 #pragma unroll
         for (int j = 0; j < F::NA; j++) {
             if (!is_active(tA[j])) continue;
-            const L g0 = step_a_store<MODE>(a, nA[j], (tA[j] & CLS_MASK) == POROUS, exA[j], eyA[j], lds);
+            const L g0 = step_a_store<MODE, TY>(a, nA[j], (tA[j] & CLS_MASK) == POROUS, exA[j], eyA[j], lds);
             if (j < F::NT) g0A[j] = g0;
         }
     } else {
@@ -1327,7 +1329,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
 #pragma unroll
         for (int j = 0; j < F::NA; j++) {
             int ex = 0, ey = 0;
-            if (!step_a_node<MODE>(j, ex, ey)) continue;
+            if (!step_a_node<MODE, TY>(j, ex, ey)) continue;
             const int x = x0 - 1 + ex, y = y0 - 1 + ey;
             if (x < 0 || y < 0 || x >= a.nx || y >= a.ny) continue;
             const int k = y * a.pitch + x;
@@ -1335,7 +1337,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
             if (!is_active(t)) continue;
             Node<R> n;
             pull_all<MODE, BC>(a, src, k, t, n);
-            const L g0 = step_a_store<MODE>(a, n, (t & CLS_MASK) == POROUS, ex, ey, lds);
+            const L g0 = step_a_store<MODE, TY>(a, n, (t & CLS_MASK) == POROUS, ex, ey, lds);
             if (j < F::NT) g0A[j] = g0;
         }
     }
@@ -1350,7 +1352,7 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
         const uint8_t t = *at(a.type, 0, (unsigned)k);
         if (!is_active(t)) continue;
         Node<R> n;
-        pull_lds<MODE, BC>(a, lds, k, lx + 1, ly + 1, t, g0A[r], n);
+        pull_lds<MODE, BC, TY>(a, lds, k, lx + 1, ly + 1, t, g0A[r], n);
         const Moments<R> m = moments(n);
         R hs[9], gs[5];
         collide<MODE>(a, (t & CLS_MASK) == POROUS, n, m, hs, gs);
@@ -1360,18 +1362,26 @@ __device__ __forceinline__ void process_tile2(const StepArgs& a, int tile, typen
 
 // Two time steps of one lattice; one block per active 64 x TY tile (tile list in
 // a.tiles, laid out with a.tiles_x = ceil(nx / 64) tiles per row).
-template <int MODE, bool NT, bool BC>
-__global__ __launch_bounds__(Fuse<MODE>::THREADS, Fuse<MODE>::BLOCKS) void step2_kernel(StepArgs a)
+template <int MODE, bool NT, bool BC, int TY>
+__global__ __launch_bounds__((Fuse<MODE, TY>::THREADS), (Fuse<MODE, TY>::BLOCKS)) void step2_kernel(StepArgs a)
 {
-    __shared__ typename Traits<MODE>::L lds[Fuse<MODE>::WORDS];
-    process_tile2<MODE, NT, true, BC>(a, a.tiles[tile_of_block(a)], lds);
+    __shared__ typename Traits<MODE>::L lds[Fuse<MODE, TY>::WORDS];
+    process_tile2<MODE, NT, true, BC, TY>(a, a.tiles[tile_of_block(a)], lds);
 }
 
+// a.tile_y selects the tile rows: 4 (F32 and F16S) or 8
 template <int MODE, bool NT, bool BC>
 static hipError_t launch_step2_t(const StepArgs& a, hipStream_t s)
 {
     if (a.n_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((step2_kernel<MODE, NT, BC>), dim3(a.n_tiles), dim3(Fuse<MODE>::THREADS), 0, s, a);
+    if constexpr (MODE == 1 || MODE == 2) {
+        if (a.tile_y == 4) {
+            hipLaunchKernelGGL((step2_kernel<MODE, NT, BC, 4>), dim3(a.n_tiles), dim3(Fuse<MODE, 4>::THREADS), 0, s, a);
+            return hipGetLastError();
+        }
+    }
+    if (a.tile_y != 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((step2_kernel<MODE, NT, BC, 8>), dim3(a.n_tiles), dim3(Fuse<MODE, 8>::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1401,6 +1411,11 @@ int fused_tile_rows(int mode)
     return mode == 0 ? Fuse<0>::TY : mode == 1 ? Fuse<1>::TY : mode == 2 ? Fuse<2>::TY : Fuse<3>::TY;
 }
 
+bool fused_rows_supported(int mode, int rows)
+{
+    return rows == 8 || (rows == 4 && (mode == 1 || mode == 2));
+}
+
 // Two time steps of every running instance of a batch in kernel class b.kind (fused tile
 // work list; the same item assignment and argument loads as batch_step_kernel).
 template <int MODE, bool NT, bool BC>
@@ -1413,7 +1428,7 @@ __global__ __launch_bounds__(Fuse<MODE>::THREADS, Fuse<MODE>::BLOCKS) void batch
     // step A issues all of a thread's loads first (512-instance sweep, FP32: 60.4 against 55.9
     // GLUPS one node at a time; F16S: 69.3 against 61.2), except in the paper-scheme variants
     // of the single-precision storages (F32, F16S, F32X), which would spill
-    process_tile2<MODE, NT, !(MODE != 0 && BC), BC>(batch_desc<true>(b, it.x), it.y, lds);
+    process_tile2<MODE, NT, !(MODE != 0 && BC), BC, 8>(batch_desc<true>(b, it.x), it.y, lds);
 }
 
 template <int MODE, bool NT, bool BC>

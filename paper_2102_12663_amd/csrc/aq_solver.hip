@@ -140,7 +140,7 @@ StepArgs make_args2(const aq_solver* s, bool a_is_src)
     a.n_tiles = s->n_tiles2;
     a.tiles_x = s->tiles_x2;
     a.tile_x = 64;
-    a.tile_y = fused_tile_rows(s->mode);
+    a.tile_y = s->fuse_rows;
     return a;
 }
 
@@ -301,7 +301,7 @@ int upload_tiles(aq_solver* s)
     if (s->n_tiles > s->L.max_tiles) return fail(AQ_EINVAL, "tile list overflow");
     if (s->n_tiles)
         HIPCHK(hipMemcpyAsync(s->base + s->L.off_tiles, tiles.data(), tiles.size() * 4, hipMemcpyHostToDevice, s->stream));
-    s->tiles_x2 = list_tiles(s, 64, fused_tile_rows(s->mode), s->htiles2);
+    s->tiles_x2 = list_tiles(s, 64, s->fuse_rows, s->htiles2);
     s->n_tiles2 = (int)s->htiles2.size();
     if (s->n_tiles2 > s->L.max_tiles2) return fail(AQ_EINVAL, "fused tile list overflow");
     if (s->n_tiles2)
@@ -525,13 +525,20 @@ int setup(aq_solver* s, const uint8_t* mask, const aq_wall_node* walls, int32_t 
     // the read and written populations of a step exceed the last-level cache: stream the writes
     s->nt_store = (double)s->n_active * bytes_per_update(s->mode) > kMallBytes ? 1 : 0;
     // two steps per launch where it measured faster: the FP64-arithmetic storages always;
-    // FP32 from kFuseMinActive active nodes or past the cache (below, the 64 x 8 tiles are
-    // too few blocks to fill the chip: 1024x512 eye 22.2k MLUPS in single steps against
-    // 17.6k, 2048x1024 45.9k against 48.0k); F16S always, since its two-step launch rounds
-    // to binary16 only where it stores, so the schedule is part of its arithmetic and a
-    // batched instance (always two-step) must match
+    // FP32 from kFuseMinActive active nodes or past the cache (below, even 64 x 4 tiles are
+    // too few blocks to fill the chip); F16S always, since its two-step launch rounds to
+    // binary16 only where it stores, so the schedule is part of its arithmetic and a batched
+    // instance (always two-step) must match
     s->fuse = (s->mode == AQ_F64 || s->mode == AQ_F32X || s->mode == AQ_F16S || s->nt_store ||
                (s->mode == AQ_F32 && s->n_active >= kFuseMinActive)) ? 1 : 0;
+    // two-step tile rows: given (the batch: 8), else 4 for mid-size F32 / F16S lattices,
+    // whose 64 x 8 tiles leave part of the chip idle (eye check intervals, 64 x 8 against
+    // 64 x 4: 1024x512 F32 17.7k / 22.6k MLUPS, F16S 18.6k / 24.6k; 2048x1024 F32 48.1k /
+    // 50.3k, F16S 55.1k / 58.6k; 4096x2048 F32 66.7k / 63.1k, F16S 101.0k / 96.7k)
+    if (s->fuse_rows == 0)
+        s->fuse_rows = ((s->mode == AQ_F32 || s->mode == AQ_F16S) && s->n_active < kFuse4MaxActive) ? 4 : 8;
+    if (!fused_rows_supported(s->mode, s->fuse_rows))
+        return fail(AQ_EINVAL, "two-step tile rows not supported for the storage");
     s->n_walls = n_walls;
     s->hwall_node.resize(std::max(n_walls, 1));
     s->hwall_id.resize(std::max(n_walls, 1));
@@ -571,13 +578,14 @@ int setup(aq_solver* s, const uint8_t* mask, const aq_wall_node* walls, int32_t 
 }
 
 int create_common(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls, int32_t n_walls,
-                  void* arena, size_t arena_bytes, void* stream, bool own, aq_solver** out)
+                  void* arena, size_t arena_bytes, void* stream, bool own, aq_solver** out, int fuse_rows)
 {
     if (!out) return fail(AQ_EINVAL, "null out");
     int rc = validate(P, mask, walls, n_walls);
     if (rc) return rc;
     aq_solver* s = new aq_solver();
     s->P = *P;
+    s->fuse_rows = fuse_rows;   // 0: chosen in setup from the lattice
     s->mode = P->storage;
     s->L = make_layout(*P, n_walls);
     if (hipGetDevice(&s->device) != hipSuccess) s->device = -1;   // resolved where it is needed
@@ -855,6 +863,7 @@ int aq_get_info(aq_solver* s, aq_info* o)
     o->fp16_exp_flow = s->exp_f;
     o->fp16_exp_thermal = s->exp_t;
     o->fusion = s->fuse ? 1 : 0;
+    o->fused_tile_rows = s->fuse_rows;
     o->graph_launches = plain_plan(s).graph_launches;
     o->nt_store = s->nt_store ? 1 : 0;
     o->step = s->step;
@@ -995,6 +1004,23 @@ int aq_time_fused_kernel(aq_solver* s, int32_t n_launch, double* ms)
     return AQ_OK;
 }
 
+// Switch the two-step tile rows (the tile lists are rebuilt and the graphs captured anew).
+static int set_fuse_rows(aq_solver* s, int rows)
+{
+    if (!fused_rows_supported(s->mode, rows)) return fail(AQ_EINVAL, "two-step tile rows not supported");
+    if (rows == s->fuse_rows) return AQ_OK;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);
+    s->fuse_rows = rows;
+    return upload_tiles(s);
+}
+
+int aq_set_fused_tile_rows(aq_solver* s, int32_t rows)
+{
+    if (!s) return fail(AQ_EINVAL, "null solver");
+    return set_fuse_rows(s, rows);
+}
+
 int aq_autotune_tile(aq_solver* s, int32_t n_launch, int32_t only_256, int32_t* tile_x, int32_t* tile_y,
                      double* ms_per_launch)
 {
@@ -1018,6 +1044,28 @@ int aq_autotune_tile(aq_solver* s, int32_t n_launch, int32_t only_256, int32_t* 
     }
     int rc = aq_set_tile(s, cand[best][0], cand[best][1]);
     if (rc) return rc;
+    // the two-step tile, where a storage has two: timed per pair of steps
+    if (s->fuse && fused_rows_supported(s->mode, 4)) {
+        const int keep = s->fuse_rows;
+        int best_rows = keep;
+        double best2 = -1;
+        for (int rows : {8, 4}) {
+            rc = set_fuse_rows(s, rows);
+            double ms = 0;
+            if (rc == AQ_OK) rc = aq_time_fused_kernel(s, 1, &ms);          // warm up
+            if (rc == AQ_OK) rc = aq_time_fused_kernel(s, std::max(1, n_launch / 2), &ms);
+            if (rc) {
+                (void)set_fuse_rows(s, keep);
+                return rc;
+            }
+            if (best2 < 0 || ms < best2) {
+                best2 = ms;
+                best_rows = rows;
+            }
+        }
+        rc = set_fuse_rows(s, best_rows);
+        if (rc) return rc;
+    }
     *tile_x = cand[best][0];
     *tile_y = cand[best][1];
     *ms_per_launch = best_ms;

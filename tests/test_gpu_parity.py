@@ -240,6 +240,28 @@ def test_two_step_fusion_bitwise(aq, storage, size):
     assert out[0][1] == out[1][1]
 
 
+@pytest.mark.parametrize("storage", [A.F32, A.F16S])
+@pytest.mark.parametrize("size", [(300, 150), (2048, 1024)])
+def test_fused_tile_rows_bitwise(aq, storage, size):
+    """The two-step tiles of F32 and F16S come in 64 x 8 and 64 x 4: the state and the
+    observables are bitwise the same with either (a node's step-A value does not depend on
+    which tile's halo computes it)."""
+    nx, ny = size
+    p, mask, walls, geo = A.sweep_instance(4, nx, ny, tau_f="draw", phi_deg="draw", storage=storage)
+    out = []
+    for rows in (8, 4):
+        s = aq.Solver(p, mask, walls)
+        s.set_fusion(True)
+        s.set_fused_tile_rows(rows)
+        assert s.info()["fused_tile_rows"] == rows
+        s.step(537)
+        out.append(([s.read_field(f) for f in ("p", "ux", "uy", "T")], s.observe()))
+        s.close()
+    for x, y in zip(out[0][0], out[1][0]):
+        assert np.array_equal(np.nan_to_num(x, nan=7.0), np.nan_to_num(y, nan=7.0))
+    assert out[0][1] == out[1][1]
+
+
 @pytest.mark.parametrize("fused", [True, False])
 def test_f16s_launch_against_the_oracle(aq, fused):
     """F16S stores binary16 and computes in single precision; a two-step launch keeps its

@@ -138,3 +138,8 @@ def test_copy_bandwidth_rejects_invalid_sizes(aq, nbytes, reps):
     g = C.c_double(-1.0)
     assert aq._lib.aq_copy_bandwidth(nbytes, reps, C.byref(g)) == aq.AQ_EINVAL
     assert g.value == -1.0
+
+
+def test_fused_tile_rows_rejected_without_a_solver(aq):
+    """aq_set_fused_tile_rows checks its handle before anything else."""
+    assert aq._lib.aq_set_fused_tile_rows(None, 4) == aq.AQ_EINVAL
