@@ -220,7 +220,7 @@ def eye_run(storage, nx, ny, seed, steps, warmup, tm="resolved", bc=0, tile=(64,
     launch_ms = plain_ms / (steps * info["graph_launches"])
     nt = "true" if info["nt_store"] else "false"
     bcs = "true" if bc else "false"
-    kernel = (f"step2_kernel<{STORAGES[storage]}, {nt}, {bcs}>" if info["fusion"]
+    kernel = (f"step2_kernel<{STORAGES[storage]}, {nt}, {bcs}, {info['fused_tile_rows']}>" if info["fusion"]
               else f"step_kernel<{STORAGES[storage]}, false, {nt}, {bcs}>")
     return {"mlups": act * steps * D / wall / 1e6, "wall": wall, "active_nodes": act, "launch_ms": launch_ms,
             "kernel": kernel, "steps_per_launch": 2 if info["fusion"] else 1, "obs": ob, "geo": geo, "p": p}

@@ -28,11 +28,12 @@ def test_traffic_reported_only_for_the_measured_source_and_kernel(tmp_path, monk
     h = bench.kernel_source_hash()
     (tmp_path / "profiles").mkdir()
     (tmp_path / "profiles" / "kernel_traffic.json").write_text(json.dumps(
-        {"eye64x32s0/f64": {"kernel": "step2_kernel<0, false, false>", "bytes_per_launch": 1234, "kernel_hash": h}}))
-    assert bench.measured_traffic("eye64x32s0/f64", "step2_kernel<0, false, false> (two time steps per launch)") == 1234
+        {"eye64x32s0/f64": {"kernel": "step2_kernel<0, false, false, 8>", "bytes_per_launch": 1234, "kernel_hash": h}}))
+    assert bench.measured_traffic("eye64x32s0/f64", "step2_kernel<0, false, false, 8> (two time steps per launch)") == 1234
     assert bench.measured_traffic("eye64x32s0/f64", "step_kernel<0, false, false, false>") is None
-    assert bench.measured_traffic("eye64x32s1/f64", "step2_kernel<0, false, false>") is None
+    assert bench.measured_traffic("eye64x32s0/f64", "step2_kernel<0, false, false, 4>") is None
+    assert bench.measured_traffic("eye64x32s1/f64", "step2_kernel<0, false, false, 8>") is None
     with open(csrc / "aq_device.h", "a") as f:
         f.write("\n// changed\n")
     assert bench.kernel_source_hash() != h
-    assert bench.measured_traffic("eye64x32s0/f64", "step2_kernel<0, false, false>") is None
+    assert bench.measured_traffic("eye64x32s0/f64", "step2_kernel<0, false, false, 8>") is None
