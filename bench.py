@@ -138,7 +138,33 @@ def cpu_baseline(n_inst=8, budget_s=2.5):
             "sample": f"the first {n_inst} requests of the 512-instance sweep ({', '.join(sizes)}; {act} active "
                       f"nodes), {n_all} time steps each at {all_threads} threads and {n_one} at 1 thread; "
                       f"median of 3 runs",
-            "single_thread": round(v_one, 2), "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+            "single_thread": round(v_one, 2), "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "other_samples": other_oracle_samples()}
+
+
+def other_oracle_samples():
+    """The oracle at all threads on the two single-lattice FP64 workloads: the 192x96 eye
+    (all 5,000 time steps of its run) and the 8192x4096 eye (sweep draw seed 0; 5 time
+    steps of it).  Active-node MLUPS, median of 3 runs after one warm-up step."""
+    import numpy as np
+    import aqinputs as A
+    import oracle as O
+    out = {}
+    for name, make, steps in (("eye192x96_f64", A.config0, 5000),
+                              ("eye8192x4096_f64", lambda: A.sweep_instance(0, 8192, 4096), 5)):
+        p, mask, walls, _ = make()
+        act = int(A.active(mask).sum())
+        o = O.Oracle(p, mask, walls)
+        o.step(1)
+        runs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            o.step(steps)
+            runs.append(act * steps / (time.perf_counter() - t0) / 1e6)
+        del o
+        out[name] = {"mlups": round(float(np.median(runs)), 2), "active_nodes": act, "time_steps": steps,
+                     "threads": O.max_threads()}
+    return out
 
 
 # ------------------------------------------------------------------------- headline: sweep
