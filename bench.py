@@ -212,7 +212,8 @@ def sweep512(steps, warmup, n=512, tol=1e-6, max_steps=200000, time_limit=240.0,
     act = info["active_nodes"]
     mlups = act * steps * 100 / timed["wall"] / 1e6
     launch_ms = timed["fused_ms"] / timed["n_fused"]
-    kernel = f"batch_step2_kernel<{STORAGES[storage]}, {'true' if info['active_nodes'] * 105 > 192 * 2 ** 20 else 'false'}, false>"
+    kernel = (f"batch_step2_kernel<{STORAGES[storage]}, {'true' if info['active_nodes'] * 105 > 192 * 2 ** 20 else 'false'}, "
+              f"false, {info['fused_tile_rows'][STORAGES[storage]]}>")
     tiles = {k[len("gfx950/1/"):]: "x".join(map(str, v)) for k, v in cache.d.items()}
     return {"mlups": mlups, "wall": timed["wall"], "active_nodes": act, "running": info["running"],
             "roofline": roofline(f"sweep512/{storage}", kernel, storage, act, launch_ms),

@@ -387,6 +387,7 @@ typedef struct aq_batch_info {
     int64_t active_nodes;           /* over running instances */
     size_t budget_bytes, used_bytes, largest_free_bytes;
     int64_t step;                   /* time steps run by the batch */
+    int32_t fused_tile_rows[4];     /* rows of the two-step tiles (64 x rows) per storage mode */
 } aq_batch_info;
 
 /* Create a batch: budget_bytes of device memory for instances (allocated once), at most
@@ -450,6 +451,15 @@ int aq_batch_resume(aq_batch* b, int32_t slot, double tol, int64_t max_steps);
 int aq_batch_diagnose(aq_batch* b, int32_t slot, void* workspace, size_t workspace_bytes, aq_diagnostics* out);
 
 int aq_batch_get_info(aq_batch* b, aq_batch_info* out);
+
+/* Rows of the two-step tiles (64 x rows) of the batch's F32 and F16S instances: 0 chooses
+ * by size (64 x 4, six blocks per CU, while a kernel class's running instances hold fewer
+ * than 2^20 active nodes, so a small batch still spreads over the chip; 64 x 8 otherwise),
+ * 4 or 8 fixes it.  FP64 and F32X always use 64 x 8, and a class whose 64 x 4 list would
+ * exceed the work-list capacity takes 64 x 8.  Results are bitwise the same with either
+ * height.  Applies from the next interval; synchronises the batch's stream.  AQ_EINVAL for
+ * any other value. */
+int aq_batch_set_fused_tile_rows(aq_batch* b, int32_t rows);
 
 /* Autotune the tile shape of a solver: time n_launch plain launches for each candidate
  * shape (64x4, 128x2, 256x1, and 64x1, 64x2, 128x1 unless only_256 is set) and keep the

@@ -32,7 +32,7 @@ EXPORTS = ("aq_version", "aq_last_error", "aq_required_bytes", "aq_create", "aq_
            "aq_batch_observe", "aq_batch_release", "aq_batch_get_info", "aq_batch_destroy",
            "aq_batch_set_outlet", "aq_batch_resume", "aq_diagnostics_bytes", "aq_diagnose",
            "aq_batch_diagnose", "aq_diagnose_noalloc", "aq_batch_run_timed", "aq_copy_bandwidth",
-           "aq_set_fused_tile_rows")
+           "aq_set_fused_tile_rows", "aq_batch_set_fused_tile_rows")
 
 
 class AqParams(C.Structure):
@@ -98,11 +98,13 @@ class AqResult(C.Structure):
 class AqBatchInfo(C.Structure):
     _fields_ = [("max_slots", C.c_int32), ("running", C.c_int32), ("finished", C.c_int32),
                 ("n_work", C.c_int32 * 4), ("active_nodes", C.c_int64), ("budget_bytes", C.c_size_t),
-                ("used_bytes", C.c_size_t), ("largest_free_bytes", C.c_size_t), ("step", C.c_int64)]
+                ("used_bytes", C.c_size_t), ("largest_free_bytes", C.c_size_t), ("step", C.c_int64),
+                ("fused_tile_rows", C.c_int32 * 4)]
 
     def asdict(self):
-        d = {n: getattr(self, n) for n, _ in self._fields_ if n != "n_work"}
+        d = {n: getattr(self, n) for n, _ in self._fields_ if n not in ("n_work", "fused_tile_rows")}
         d["n_work"] = list(self.n_work)
+        d["fused_tile_rows"] = list(self.fused_tile_rows)
         return d
 
 
@@ -172,6 +174,7 @@ def load_library(path: str = LIB_PATH):
     L.aq_batch_destroy.argtypes = [vp]
     L.aq_copy_bandwidth.argtypes = [sz, i32, C.POINTER(C.c_double)]
     L.aq_set_fused_tile_rows.argtypes = [vp, i32]
+    L.aq_batch_set_fused_tile_rows.argtypes = [vp, i32]
     for name in EXPORTS:
         if name not in ("aq_version", "aq_last_error"):
             getattr(L, name).restype = C.c_int
@@ -475,6 +478,11 @@ class Batch:
 
     def release(self, slot: int):
         _check(_lib.aq_batch_release(self._h, int(slot)))
+
+    def set_fused_tile_rows(self, rows: int):
+        """Two-step tile rows of the F32 and F16S instances: 0 by size, 4 or 8
+        (aq_batch_set_fused_tile_rows)."""
+        _check(_lib.aq_batch_set_fused_tile_rows(self._h, int(rows)))
 
     def info(self) -> dict:
         i = AqBatchInfo()

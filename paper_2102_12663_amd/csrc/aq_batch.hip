@@ -194,6 +194,9 @@ struct aq_batch {
     hipGraph_t graph_src[2] = {nullptr, nullptr};
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int fused_launches = 0;         // two-step launches per kernel class and interval
+    // two-step tile rows per kernel class, and the caller's choice (0: by the class's size)
+    int rows2[NKIND] = {8, 8, 8, 8, 8, 8, 8, 8};
+    int rows_choice = 0;
 };
 
 namespace {
@@ -214,6 +217,7 @@ BatchArgs batch_args(const aq_batch* b, int kind, int parity)
     a.kind = kind;
     a.nt_store = b->nt_store;
     a.bc = kind / NMODE;
+    a.tile_y = b->rows2[kind];
     return a;
 }
 
@@ -327,10 +331,51 @@ int ensure_graph(aq_batch* b)
     return AQ_OK;
 }
 
+// Two-step tile rows of a kernel class: 64 x 4 tiles (six blocks per CU) in F32 and F16S
+// while the class's running instances hold fewer than kFuse4MaxActive active nodes, so a
+// small batch still spreads over the chip; 64 x 8 otherwise, or as the caller chose.
+// Instances whose fused tile list has another height are listed again.
+int choose_rows(aq_batch* b, const bool* force8)
+{
+    int64_t act[NKIND] = {};
+    for (const Slot& sl : b->slots)
+        if (sl.used && sl.running) act[kind_of(sl.s)] += sl.s->n_active;
+    for (int m = 0; m < NKIND; m++) {
+        int rows = 8;
+        if (fused_rows_supported(m % NMODE, 4) && !force8[m])
+            rows = b->rows_choice ? b->rows_choice : (act[m] < kFuse4MaxActive ? 4 : 8);
+        if (rows != b->rows2[m]) {
+            b->rows2[m] = rows;
+            drop_graph(b);                 // the captured launches bake the tile height in
+        }
+    }
+    for (const Slot& sl : b->slots) {
+        if (!sl.used || !sl.running || sl.s->fuse_rows == b->rows2[kind_of(sl.s)]) continue;
+        const int rc = set_fuse_rows(sl.s, b->rows2[kind_of(sl.s)]);
+        if (rc) return rc;
+    }
+    return AQ_OK;
+}
+
 // Rebuild the instance table and the per-mode work lists from the running slots and
-// copy them to the device (ordered on the batch stream, then synchronised).
+// copy them to the device (ordered on the batch stream, then synchronised).  A class whose
+// 64 x 4 list would not fit the work-list capacity takes 64 x 8 tiles.
 int upload_tables(aq_batch* b)
 {
+    bool force8[NKIND] = {};
+    int rc = choose_rows(b, force8);
+    if (rc) return rc;
+    for (;;) {
+        int64_t n2[NKIND] = {};
+        for (const Slot& sl : b->slots)
+            if (sl.used && sl.running) n2[kind_of(sl.s)] += (int64_t)sl.s->htiles2.size();
+        bool again = false;
+        for (int m = 0; m < NKIND; m++)
+            if (b->rows2[m] == 4 && n2[m] > b->max_tiles) force8[m] = again = true;
+        if (!again) break;
+        rc = choose_rows(b, force8);
+        if (rc) return rc;
+    }
     std::vector<int2> work[NKIND], work2[NKIND];
     double bytes = 0;
     for (const Slot& sl : b->slots)
@@ -361,7 +406,7 @@ int upload_tables(aq_batch* b)
         if ((int)work[m].size() > b->max_tiles || (int)work2[m].size() > b->max_tiles)
             return fail(AQ_EBUSY, "work list capacity exceeded");
         if (!work[m].empty()) {
-            int rc = ensure_kind(b, m);
+            rc = ensure_kind(b, m);
             if (rc) return rc;
         }
         b->n_work[m] = (int)work[m].size();
@@ -814,7 +859,16 @@ int aq_batch_get_info(aq_batch* b, aq_batch_info* o)
     o->used_bytes = b->pool.used();
     o->largest_free_bytes = b->pool.largest();
     o->step = b->step;
+    for (int m = 0; m < NMODE; m++) o->fused_tile_rows[m] = b->rows2[m];
     return AQ_OK;
+}
+
+int aq_batch_set_fused_tile_rows(aq_batch* b, int32_t rows)
+{
+    if (!b) return fail(AQ_EINVAL, "null batch");
+    if (rows != 0 && rows != 4 && rows != 8) return fail(AQ_EINVAL, "two-step tile rows must be 0 (by size), 4 or 8");
+    b->rows_choice = rows;
+    return upload_tables(b);
 }
 
 }  // extern "C"

@@ -100,6 +100,7 @@ struct BatchArgs {
     int kind;                  // kernel class of this launch (instances with InstDesc.mode == kind)
     int nt_store;              // non-temporal population stores
     int bc;                    // 1: the instances of this launch use the paper's boundary schemes
+    int tile_y;                // rows of the two-step tiles of this launch (8, or 4 in F32 and F16S)
 };
 
 // Host-side launchers (defined in aq_kernels.hip).
@@ -108,7 +109,7 @@ hipError_t launch_batch_step(int mode, bool reduce, const BatchArgs& b, int grid
 // Two plain time steps in one launch (tiles 64 x fused_tile_rows(mode) from a.tiles).
 hipError_t launch_step2(int mode, const StepArgs& a, hipStream_t s);
 hipError_t launch_batch_step2(int mode, const BatchArgs& b, int grid, hipStream_t s);
-int fused_tile_rows(int mode);   // the batch's tile rows (64 x 8)
+int fused_tile_rows(int mode);   // the default two-step tile rows (64 x 8)
 bool fused_rows_supported(int mode, int rows);
 hipError_t launch_batch_finish(const BatchArgs& b, hipStream_t s);
 // Write into a.dst the buffer whose pull gives the pre-collision populations `pops`

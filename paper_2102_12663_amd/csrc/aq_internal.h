@@ -144,5 +144,7 @@ int validate(const aq_params* P, const uint8_t* mask, const aq_wall_node* walls,
 // The reduced storages' 32-bit population offsets cover the lattice (always true in FP64).
 bool offsets_fit(const aq_params& P);
 int upload_tiles(aq_solver* s);
+// Set the two-step tile rows of a solver and rebuild its tile lists (synchronises its stream).
+int set_fuse_rows(aq_solver* s, int rows);
 
 }  // namespace aq

@@ -1417,25 +1417,35 @@ bool fused_rows_supported(int mode, int rows)
 }
 
 // Two time steps of every running instance of a batch in kernel class b.kind (fused tile
-// work list; the same item assignment and argument loads as batch_step_kernel).
-template <int MODE, bool NT, bool BC>
-__global__ __launch_bounds__(Fuse<MODE>::THREADS, Fuse<MODE>::BLOCKS) void batch_step2_kernel(BatchArgs b)
+// work list of 64 x TY tiles; the same item assignment and argument loads as
+// batch_step_kernel).
+template <int MODE, bool NT, bool BC, int TY>
+__global__ __launch_bounds__((Fuse<MODE, TY>::THREADS), (Fuse<MODE, TY>::BLOCKS)) void batch_step2_kernel(BatchArgs b)
 {
-    __shared__ typename Traits<MODE>::L lds[Fuse<MODE>::WORDS];
+    __shared__ typename Traits<MODE>::L lds[Fuse<MODE, TY>::WORDS];
     const int w = batch_item();
     if (w >= *b.n_work2) return;
     const int2 it = load_item(b.work2, w);
     // step A issues all of a thread's loads first (512-instance sweep, FP32: 60.4 against 55.9
     // GLUPS one node at a time; F16S: 69.3 against 61.2), except in the paper-scheme variants
     // of the single-precision storages (F32, F16S, F32X), which would spill
-    process_tile2<MODE, NT, !(MODE != 0 && BC), BC, 8>(batch_desc<true>(b, it.x), it.y, lds);
+    process_tile2<MODE, NT, !(MODE != 0 && BC), BC, TY>(batch_desc<true>(b, it.x), it.y, lds);
 }
 
+// b.tile_y selects the tile rows: 4 (F32 and F16S) or 8; every instance of the launch
+// has its fused tile list in rows of that height
 template <int MODE, bool NT, bool BC>
 static hipError_t launch_batch2_k(const BatchArgs& b, int grid, hipStream_t s)
 {
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((batch_step2_kernel<MODE, NT, BC>), dim3(grid), dim3(Fuse<MODE>::THREADS), 0, s, b);
+    if constexpr (MODE == 1 || MODE == 2) {
+        if (b.tile_y == 4) {
+            hipLaunchKernelGGL((batch_step2_kernel<MODE, NT, BC, 4>), dim3(grid), dim3(Fuse<MODE, 4>::THREADS), 0, s, b);
+            return hipGetLastError();
+        }
+    }
+    if (b.tile_y != 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((batch_step2_kernel<MODE, NT, BC, 8>), dim3(grid), dim3(Fuse<MODE, 8>::THREADS), 0, s, b);
     return hipGetLastError();
 }
 

@@ -320,10 +320,17 @@ void drop_graph(aq_solver* s)
     }
 }
 
-// The plain (non-reducing) part of a check interval: check_interval - 1 steps, as
-// (check_interval - 2)/2 two-step launches and one single step when fusion is on (the
-// interval must end with a single step so the previous buffer pulls back to the current
-// state), else as single steps.  Returns the number of buffer swaps.
+// Switch the two-step tile rows (the tile lists are rebuilt and the graphs captured anew).
+int set_fuse_rows(aq_solver* s, int rows)
+{
+    if (!fused_rows_supported(s->mode, rows)) return fail(AQ_EINVAL, "two-step tile rows not supported");
+    if (rows == s->fuse_rows) return AQ_OK;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);
+    s->fuse_rows = rows;
+    return upload_tiles(s);
+}
+
 // The check_interval - 1 plain steps of an interval: `graph_launches` launches replayed
 // from a graph (two-step launches when fusion is on, else single steps) covering
 // `graph_steps` steps, then `tail` single steps launched directly.  The reducing step that
@@ -1002,17 +1009,6 @@ int aq_time_fused_kernel(aq_solver* s, int32_t n_launch, double* ms)
     HIPCHK(hipEventElapsedTime(&t, s->ev[0], s->ev[1]));
     *ms = t / n_launch;
     return AQ_OK;
-}
-
-// Switch the two-step tile rows (the tile lists are rebuilt and the graphs captured anew).
-static int set_fuse_rows(aq_solver* s, int rows)
-{
-    if (!fused_rows_supported(s->mode, rows)) return fail(AQ_EINVAL, "two-step tile rows not supported");
-    if (rows == s->fuse_rows) return AQ_OK;
-    HIPCHK(hipStreamSynchronize(s->stream));
-    drop_graph(s);
-    s->fuse_rows = rows;
-    return upload_tiles(s);
 }
 
 int aq_set_fused_tile_rows(aq_solver* s, int32_t rows)

@@ -58,6 +58,32 @@ def test_alone_vs_in_the_mix_bitwise(aq):
     b.close()
 
 
+def test_fused_tile_rows_bitwise(aq):
+    """The batch's two-step tiles: a small batch takes 64 x 4 in its F32 and F16S classes
+    (FP64 and F32X keep 64 x 8), and the fields are bitwise the same as with 64 x 8
+    throughout, or with the height switched between intervals."""
+    insts = _instances()
+    runs = {}
+    for name, plan in (("auto", (0, 0)), ("eight", (8, 8)), ("switch", (4, 8))):
+        b = aq.Batch(budget_bytes=1 << 30, max_slots=16)
+        slots = [b.admit(p, m, w, tile=(64, 4), tol=1e-12, max_steps=10 ** 6, request_id=i, keep=True)
+                 for i, (p, m, w) in enumerate(insts)]
+        b.set_fused_tile_rows(plan[0])
+        rows_first = b.info()["fused_tile_rows"]
+        b.run(3)
+        b.set_fused_tile_rows(plan[1])
+        b.run(4)
+        announce(f"[batch] fused rows {name}: {rows_first} then {b.info()['fused_tile_rows']}")
+        runs[name] = (rows_first, [[b.read_field(sl, f) for f in ("p", "ux", "uy", "T")] for sl in slots])
+        b.close()
+    assert runs["auto"][0] == [8, 4, 4, 8]
+    assert runs["eight"][0] == [8, 8, 8, 8]
+    assert runs["switch"][0] == [8, 4, 4, 8]
+    for i in range(len(insts)):
+        assert _fields_equal(runs["auto"][1][i], runs["eight"][1][i]), f"instance {i}"
+        assert _fields_equal(runs["switch"][1][i], runs["eight"][1][i]), f"instance {i}"
+
+
 def test_staggered_admission_and_retirement_bitwise(aq):
     """Work lists that grow and shrink between runs (each change re-sizes the launches):
     an instance admitted late and one that keeps running after another retires both match

@@ -143,3 +143,8 @@ def test_copy_bandwidth_rejects_invalid_sizes(aq, nbytes, reps):
 def test_fused_tile_rows_rejected_without_a_solver(aq):
     """aq_set_fused_tile_rows checks its handle before anything else."""
     assert aq._lib.aq_set_fused_tile_rows(None, 4) == aq.AQ_EINVAL
+
+
+def test_batch_fused_tile_rows_rejected_without_a_batch(aq):
+    """aq_batch_set_fused_tile_rows checks its handle before anything else."""
+    assert aq._lib.aq_batch_set_fused_tile_rows(None, 4) == aq.AQ_EINVAL
