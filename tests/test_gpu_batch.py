@@ -239,3 +239,42 @@ def test_full_sweep_batch_sampled_oracle_parity(aq):
         err = field_errors(g, o.fields(), m, p.T_ref)
         assert all(v <= 1e-12 for v in err.values()), (seed, err)
     b.close()
+
+
+def test_full_sweep_fp32_batch_against_the_oracle(aq):
+    """The benchmark's workload in its launch configuration: the 512-instance sweep in one
+    FP32 batch (autotuned single-step tiles, 64x8 two-step tiles, non-temporal stores).
+    After two check intervals, one sampled instance of each size class hands its FP32
+    populations to the oracle; one more interval of the batch (48 two-step launches, three
+    single steps and the reducing step) is compared with 100 FP64 oracle steps from that
+    state.  Every field must agree to 1e-4 of its largest value.  That is the linear-growth
+    bound of FP32 arithmetic: about 16 roundings of 2^-24 per value and step, over 100 steps.
+    A wrong pull, halo or rule is off by a good part of the field."""
+    from paper_2102_12663_amd import serve as S
+    reqs = [S.sweep_request(i, aq.F32) for i in range(512)]
+    cache = S.ShapeCache()
+    b = aq.Batch(budget_bytes=64 << 30, max_slots=512, max_tiles=1 << 21)
+    slots = [b.admit(p, m, w, tile=S.autotune_shape(cache, p, m, w), tol=1e-30, max_steps=10 ** 9,
+                     request_id=i, keep=True) for i, (p, m, w) in enumerate(reqs)]
+    assert all(s is not None for s in slots)
+    assert b.info()["fused_tile_rows"][aq.F32] == 8
+    b.run(2)
+    oracles = {}
+    for seed in (3, 16, 13, 4):            # 256x128, 512x256, 768x384, 1024x512
+        p, m, w = reqs[seed]
+        h = np.stack([b.read_field(slots[seed], "pop_flow", q) for q in range(1, 9)])
+        g = np.stack([b.read_field(slots[seed], "pop_heat", q) for q in range(5)])
+        o = O.Oracle(p, m, w)
+        o.set_populations(h, g)
+        oracles[seed] = o
+    b.run(1)
+    for seed, o in oracles.items():
+        p, m, w = reqs[seed]
+        o.step(100)
+        gf = [b.read_field(slots[seed], f) for f in ("p", "ux", "uy", "T")]
+        gf[0] = gf[0] - p.p_ref
+        err = field_errors(gf, o.fields(), m, p.T_ref)
+        announce(f"[batch] FP32 sweep instance {seed} {p.nx}x{p.ny}, one interval vs the oracle: "
+                 + ", ".join(f"{k} {v:.2e}" for k, v in err.items()))
+        assert all(v <= 1e-4 for v in err.values()), (seed, err)
+    b.close()
