@@ -79,6 +79,7 @@ def lib():
         L.or_step_count.restype = C.c_int64
         L.or_set_outlet.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double]
         L.or_observables_get.argtypes = [C.c_void_p, C.POINTER(OrObservables)]
+        L.or_observe.argtypes = [C.c_void_p, C.POINTER(OrObservables)]
         L.or_fields.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.or_get_populations.argtypes = [C.c_void_p, dp, dp]
         L.or_set_populations.argtypes = [C.c_void_p, dp, dp]
@@ -166,6 +167,12 @@ class Oracle:
     def observables(self) -> dict:
         o = OrObservables()
         lib().or_observables_get(self._s, C.byref(o))
+        return o.asdict()
+
+    def observe_now(self) -> dict:
+        """The check-step observables of the current state, computed now."""
+        o = OrObservables()
+        lib().or_observe(self._s, C.byref(o))
         return o.asdict()
 
     def fields(self):

@@ -606,6 +606,12 @@ void or_set_outlet(or_state* s, double K_tm, double h_tm, double p_sc)
 
 void or_observables_get(const or_state* s, or_observables* out) { *out = s->obs; }
 
+void or_observe(or_state* s, or_observables* out)
+{
+    observe(s);
+    *out = s->obs;
+}
+
 /* Macroscopic fields of the current (pre-collision) state; NaN at non-active nodes. */
 void or_fields(const or_state* s, double* dp, double* ux, double* uy, double* T)
 {

@@ -44,6 +44,9 @@ void or_step(or_state* s, int64_t nsteps);
 int64_t or_step_count(const or_state* s);
 void or_set_outlet(or_state* s, double K_tm, double h_tm, double p_sc);
 void or_observables_get(const or_state* s, or_observables* out);
+/* The check-step observables of the current state, computed now (as a check step does,
+ * including its update of the residual reference and of the lumped seepage speed). */
+void or_observe(or_state* s, or_observables* out);
 void or_fields(const or_state* s, double* dp, double* ux, double* uy, double* T);
 void or_get_populations(const or_state* s, double* h, double* g);
 void or_set_populations(or_state* s, const double* h, const double* g);
