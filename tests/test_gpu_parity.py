@@ -107,6 +107,51 @@ def test_ragged_random_state_every_boundary(aq, nx, ny, alpha):
     assert not bad, bad
 
 
+def _apart(p):
+    """The eye's parameters with every reference level apart: the deviation form's T_ref and
+    p_ref, the Boussinesq T0 (eq. 16), the initial, wall and inlet temperatures, the initial
+    and outlet pressures."""
+    return A.Params(**{**p.asdict(), "T_ref": 0.2, "T0": 0.6, "T_init": 0.45, "T_cornea": 0.05,
+                       "T_iris": 0.95, "T_inlet": 0.8, "p_init": p.p_ref + 2e-5, "p_out": p.p_ref + 1e-4})
+
+
+@pytest.mark.parametrize("storage,tol", [(A.F64, FIELD_TOL), (A.F32, 1e-4)])
+def test_reference_levels_apart(aq, storage, tol):
+    """192x96 eye with every reference level apart (T_ref, T0, the wall, inlet and initial
+    temperatures, p_ref, p_init, p_out) and strong buoyancy (Ra 2e4), 500 steps: fields
+    against the oracle, FP64 to 1e-12 and FP32 to 1e-4 of each field's largest value.  A
+    level taken for another (say the buoyancy measured from T_ref, off by 0.4 g beta
+    against forces of at most 0.55 g beta) moves the fields by far more than either."""
+    p0, mask, walls, geo = A.config0()
+    p = _apart(A.Params(**{**p0.asdict(), "gbeta": 20 * p0.gbeta, "storage": storage}))
+    s, o, gf, of, gobs, oobs = _run_pair(aq, p, mask, walls, 500)
+    err = field_errors(gf, of, mask, p.T_ref)
+    announce(f"[parity] reference levels apart, storage={storage}: {err}")
+    assert all(v <= tol for v in err.values()), err
+    if storage == A.F64:
+        bad = obs_close(gobs, oobs, 1e-11, keys=["iop_gauge", "q_in", "q_out", "wss_cornea_mean", "wss_iris_mean",
+                                                  "resid_u", "resid_T", "u_max"])
+        assert not bad, bad
+
+
+def test_reference_levels_apart_in_a_batch(aq):
+    """The same case as an FP64 instance of a batch, beside an instance at the default
+    levels: the batch's per-instance constants carry every level."""
+    p0, mask, walls, geo = A.config0()
+    p = _apart(A.Params(**{**p0.asdict(), "gbeta": 20 * p0.gbeta}))
+    b = aq.Batch(budget_bytes=1 << 30, max_slots=4)
+    sa = b.admit(p, mask, walls, tile=(64, 4), tol=1e-30, max_steps=10 ** 6, keep=True)
+    sb = b.admit(p0, mask, walls, tile=(64, 4), tol=1e-30, max_steps=10 ** 6, keep=True)
+    b.run(5)
+    for sl, q in ((sa, p), (sb, p0)):
+        o = O.Oracle(q, mask, walls).step(500)
+        g = [b.read_field(sl, f) for f in ("p", "ux", "uy", "T")]
+        g[0] = g[0] - q.p_ref
+        err = field_errors(g, o.fields(), mask, q.T_ref)
+        assert all(v <= FIELD_TOL for v in err.values()), err
+    b.close()
+
+
 @pytest.mark.parametrize("tile", [(64, 1), (64, 2), (128, 2), (256, 1)])
 def test_tile_shapes_bitwise(aq, tile):
     """The per-node arithmetic does not depend on the tile shape: fields bitwise equal."""
