@@ -38,6 +38,25 @@ def _lumped0(storage=A.F64):
     return p, mask, walls
 
 
+def test_lumped_parity_canal_pressure_apart(aq):
+    """The Schlemm's-canal pressure below p_ref and the outlet pressure above it: the
+    seepage speed follows IOP - p_sc (eq. 4 over the meshwork), not IOP - p_ref."""
+    p, mask, walls = _lumped0()
+    p.p_sc = p.p_ref - 3e-5
+    p.p_out = p.p_ref + 5e-5
+    p.p_init = p.p_sc + 1e-4
+    s = aq.Solver(p, mask, walls)
+    s.step(1000)
+    o = O.Oracle(p, mask, walls).step(1000)
+    err = field_errors(s.fields(), o.fields(), mask, p.T_ref)
+    announce(f"[lumped] canal pressure apart: {err}")
+    assert all(v <= FIELD_TOL for v in err.values()), err
+    gobs, oobs = s.observe(), o.observables()
+    assert not obs_close(gobs, oobs, 1e-11, keys=OBS_KEYS)
+    assert gobs["u_seep"] == pytest.approx(oobs["u_seep"], rel=1e-11)
+    s.close()
+
+
 def _small(storage=A.F64):
     mask, walls, geo = A.eye_mask(96, 48, 45.0, R=40.0, pupil_gap=2, tm="lumped")
     p = A.eye_params(96, 48, geo, Ra=0.0, Da=1e-3, tm="lumped", storage=storage)
