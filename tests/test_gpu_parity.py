@@ -115,13 +115,15 @@ def _apart(p):
                        "T_iris": 0.95, "T_inlet": 0.8, "p_init": p.p_ref + 2e-5, "p_out": p.p_ref + 1e-4})
 
 
-@pytest.mark.parametrize("storage,tol", [(A.F64, FIELD_TOL), (A.F32, 1e-4)])
+@pytest.mark.parametrize("storage,tol", [(A.F64, FIELD_TOL), (A.F32, 1e-4), (A.F32X, 1e-4), (A.F16S, 1e-2)])
 def test_reference_levels_apart(aq, storage, tol):
     """192x96 eye with every reference level apart (T_ref, T0, the wall, inlet and initial
     temperatures, p_ref, p_init, p_out) and strong buoyancy (Ra 2e4), 500 steps: fields
-    against the oracle, FP64 to 1e-12 and FP32 to 1e-4 of each field's largest value.  A
-    level taken for another (say the buoyancy measured from T_ref, off by 0.4 g beta
-    against forces of at most 0.55 g beta) moves the fields by far more than either."""
+    against the oracle: FP64 to 1e-12 of each field's largest value, FP32 and F32X to
+    1e-4 (measured 7e-7 and 2e-7), F16S (binary16 storage, 11 significant bits) to 1e-2
+    (measured 1.6e-3).  A level taken for another
+    (say the buoyancy measured from T_ref, off by 0.4 g beta against forces of at most
+    0.55 g beta) moves the fields by far more than any of these."""
     p0, mask, walls, geo = A.config0()
     p = _apart(A.Params(**{**p0.asdict(), "gbeta": 20 * p0.gbeta, "storage": storage}))
     s, o, gf, of, gobs, oobs = _run_pair(aq, p, mask, walls, 500)
