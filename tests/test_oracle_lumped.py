@@ -87,10 +87,12 @@ def test_lumped_mask_and_outflow_area():
     assert area > 0 and q_in == pytest.approx(2 * 1e-4, rel=1e-12)   # pupil gap of 2 cells
 
 
-def test_steady_iop_closed_form():
-    """IOP - p_sc = mu h Q_in / (K A) at the steady state, and the outflow equals the inflow."""
+@pytest.mark.parametrize("canal", [0.0, -3e-5])
+def test_steady_iop_closed_form(canal):
+    """IOP - p_sc = mu h Q_in / (K A) at the steady state, and the outflow equals the inflow;
+    also with the canal pressure p_sc below the reference pressure p_ref."""
     mask, walls, geo = _eye()
-    p = _params(geo)
+    p = _params(geo, p_sc=1.0 / 3.0 + canal)
     area, q_in, n = _counts(mask, p)
     ob = _to_steady(p, mask, walls)
     expect = _nu(p) * p.h_tm * q_in / (p.K_tm * area)
