@@ -88,6 +88,42 @@ M = [  # id, file, description, old, new
  ("intensity", D, "intensity without the factor 2", "float(2.0 * np.sum(np.abs(w[fluid])))", "float(1.0 * np.sum(np.abs(w[fluid])))"),
  ("psi_axis", D, "stream function summed along x", "np.cumsum(np.where(act, ux, 0.0), axis=0)", "np.cumsum(np.where(act, ux, 0.0), axis=1)"),
  ("psi_uy", D, "stream function sign", "def stream_function(ux, mask):\n    act = _active(mask)\n    return np.cumsum(np.where(act, ux, 0.0), axis=0)", "def stream_function(ux, mask):\n    act = _active(mask)\n    return np.cumsum(np.where(act, -ux, 0.0), axis=0)"),
+ ("ext_lumped_dir", C, "extrapolated lumped outlet direction off by one",
+  "} else if (P->outlet_mode == OR_OUTLET_LUMPED) {\n                        int d = s->wall[kk] + 1;\n                        uxb = ex[d] * s->u_seep;\n                        uyb = ey[d] * s->u_seep;\n                    } else {\n                        dpb = P->p_out - P->p_ref;\n                    }\n                    *back",
+  "} else if (P->outlet_mode == OR_OUTLET_LUMPED) {\n                        int d = s->wall[kk];\n                        uxb = ex[d] * s->u_seep;\n                        uyb = ey[d] * s->u_seep;\n                    } else {\n                        dpb = P->p_out - P->p_ref;\n                    }\n                    *back"),
+ ("ext_q_out", C, "outflow of the extrapolated outlet with the wrong sign",
+  "if (c == OR_INLET) q_in += *back - hout;\n                    else q_out += hout - *back;",
+  "if (c == OR_INLET) q_in += *back - hout;\n                    else q_out += *back - hout;"),
+ ("abb_q_out", C, "outflow of the pressure outlet with the wrong sign",
+  "*back = -hout + 2.0 * lambda_i(i) * (P->p_out - P->p_ref); /* pressure ABB */\n                    q_out += hout - *back;",
+  "*back = -hout + 2.0 * lambda_i(i) * (P->p_out - P->p_ref); /* pressure ABB */\n                    q_out += *back - hout;"),
+ ("ext_T_inlet_u", C, "thermal extrapolation at the inlet with the fluid at rest",
+  "double uxb = c == OR_INLET ? P->u_in_x : 0.0, uyb = c == OR_INLET ? P->u_in_y : 0.0;\n                    moments ms = post_moments(s, k);                        /* extrapolation */",
+  "double uxb = 0.0, uyb = 0.0;\n                    moments ms = post_moments(s, k);                        /* extrapolation */"),
+ ("bz_fallback", C, "interpolation for q < 1/2 without an active node behind",
+  "} else if (q > 0.0 && kb >= 0 && is_active(s, (size_t)kb)) {",
+  "} else if (q > 0.0 && kb >= 0) {"),
+ ("bz_threshold", C, "interpolation branches split at q = 1 instead of 1/2",
+  "if (q >= 0.5) {                                     /* interpolated bounce-back */",
+  "if (q >= 1.0) {                                     /* interpolated bounce-back */"),
+ ("wss_max", C, "maximum wall shear taken as the last value",
+  "if (tau_w > wm[id]) wm[id] = tau_w;", "wm[id] = tau_w;"),
+ ("wss_sign_f", C, "wall shear from Pi^neq without the factor's sign and size",
+  "double f = -(1.0 - 0.5 / P->tau_f);", "double f = 1.0;"),
+ ("mass_thermal", C, "thermal mass without the rest population",
+  "for (int i = 0; i < 5; i++) mt += g5[i];", "for (int i = 1; i < 5; i++) mt += g5[i];"),
+ ("resid_T_ref", C, "thermal residual relative to T instead of T - T_ref",
+  "T2 += (m.T - P->T_ref) * (m.T - P->T_ref);", "T2 += m.T * m.T;"),
+ ("umax_fluid", C, "maximum speed as the sum of the components",
+  "double um = sqrt(m.ux * m.ux + m.uy * m.uy);", "double um = fabs(m.ux) + fabs(m.uy);"),
+ ("init_ext", C, "paper scheme started without its boundary populations",
+  "if (P->bc_scheme == OR_BC_PAPER) initial_boundary_populations(s);", "(void)initial_boundary_populations;"),
+ ("lumped_first", C, "first lumped interval at zero seepage",
+  "s->u_seep = P->outlet_mode == OR_OUTLET_LUMPED ? seepage_speed(P, P->p_init) : 0.0;", "s->u_seep = 0.0;"),
+ ("set_outlet_iop", C, "recalibrated seepage from p_init instead of the last IOP",
+  "s->u_seep = seepage_speed(&s->P, s->obs.step > 0 ? s->obs.p_mean_fluid : s->P.p_init);",
+  "s->u_seep = seepage_speed(&s->P, s->P.p_init);"),
+ ("darcy_by_tau", C, "Darcy drag with nu replaced by tau", "double nuK = nu_of(P) / P->K;", "double nuK = P->tau_f / P->K;"),
 ]
 
 

@@ -216,3 +216,51 @@ def test_calibration_loop_reaches_closed_form_thickness():
         o.set_outlet(p.K_tm, h, p.p_sc)
     assert rounds <= 3
     assert h == pytest.approx(h_star, rel=2e-8)
+
+
+def _lumped_duct(bc, U=1e-3, nx=24, ny=4, K_tm=0.05, h_tm=3.0, D=10):
+    """Duct periodic in y: INLET column (velocity U along x), lumped OUTLET column draining
+    along +x, no walls."""
+    m = np.full((ny, nx), A.encode(A.FLUID), np.uint8)
+    m[:, 0] = A.encode(A.INLET)
+    m[:, nx - 1] = A.encode(A.OUTLET, 0)
+    P = A.Params(nx=nx, ny=ny, tau_f=0.8, periodic_y=1, u_in_x=U, check_interval=D, bc_scheme=bc,
+                 outlet_mode=A.OUTLET_LUMPED, K_tm=K_tm, h_tm=h_tm, p_sc=1.0 / 3.0 - 2e-5, p_init=1.0 / 3.0)
+    return m, P
+
+
+@pytest.mark.parametrize("bc", [A.BC_LINKWISE, A.BC_PAPER])
+def test_lumped_duct_closed_form(bc):
+    """Plug flow U into a duct drained by the lumped meshwork: the steady state is the
+    uniform flow with u_s = U, so IOP - p_sc = mu h U / K exactly (eq. 4 over the meshwork),
+    with the link-wise moving wall and with the paper's extrapolation at the outlet."""
+    m, P = _lumped_duct(bc)
+    o = O.Oracle(P, m).step(30000)
+    ob = o.observables()
+    assert ob["p_mean_fluid"] - P.p_sc == pytest.approx(_nu(P) * P.h_tm * P.u_in_x / P.K_tm, rel=1e-12)
+    assert ob["u_seep"] == pytest.approx(P.u_in_x, rel=1e-12)
+    assert ob["q_out"] == pytest.approx(ob["q_in"], rel=1e-12)
+
+
+def test_first_interval_drains_at_the_initial_pressure():
+    """Before the first check step the seepage speed is that of p_init, and the moving-wall
+    outlet drains u_s per outlet node (6 w_i e_i.n summed over the three outgoing links is
+    1): the outflow of the last step of the first interval is (K/mu)(p_init - p_sc)/h per node."""
+    m, P = _lumped_duct(A.BC_LINKWISE)
+    ny = m.shape[0]
+    ob = O.Oracle(P, m).step(P.check_interval).observables()
+    assert ob["q_out"] == pytest.approx(P.K_tm / _nu(P) * (P.p_init - P.p_sc) / P.h_tm * ny, rel=1e-12)
+
+
+def test_recalibration_drains_at_the_last_iop():
+    """A new thickness takes effect at once, with the seepage speed of the IOP of the last
+    check step (the warm restart of the calibration loop, section 3.1)."""
+    m, P = _lumped_duct(A.BC_LINKWISE)
+    ny = m.shape[0]
+    o = O.Oracle(P, m).step(3 * P.check_interval)
+    iop = o.observables()["p_mean_fluid"]
+    h2 = 1.7 * P.h_tm
+    o.set_outlet(P.K_tm, h2, P.p_sc)
+    o.step(1)
+    ob = o.observe_now()
+    assert ob["q_out"] == pytest.approx(P.K_tm / _nu(P) * (iop - P.p_sc) / h2 * ny, rel=1e-12)

@@ -84,11 +84,16 @@ def test_extrapolation_carries_the_non_equilibrium_part():
     cols = slice(1, nx - 1 - n)   # columns the outlet's bounce-back has not reached yet
     want_g = g0 + (1 - 1 / P.tau_t) ** n * dg[:, None, None]
     assert np.max(np.abs(g[:, :, cols] - want_g[:, :, cols])) < 1e-12 * np.max(np.abs(dg))
+    # the stress patterns carry no momentum: in and out flow U per boundary node
+    ob = o.observe_now()
+    assert ob["q_in"] == pytest.approx(P.u_in_x * ny, rel=1e-12)
+    assert ob["q_out"] == pytest.approx(P.u_in_x * ny, rel=1e-12)
 
 
 def _channel_state(tau, s, a, b):
     """A channel between an IRIS wall below (normal +y) and a CORNEA wall above (normal
-    -y), at rest, with the non-equilibrium part s SHEAR + a ISO + b NORMAL at every node."""
+    -y), at rest, with the non-equilibrium part s SHEAR + a ISO + b NORMAL at every node
+    (s a scalar, or one value per column)."""
     nx, ny = 4, 8
     P = A.Params(nx=nx, ny=ny, tau_f=tau, periodic_x=1, check_interval=1000)
     mask = A.channel_mask(nx, ny)
@@ -100,8 +105,9 @@ def _channel_state(tau, s, a, b):
     init_from_fields(o, P, P.p_ref, 0.0, 0.0, P.T_ref)
     h, g = o.populations()
     act = A.active(mask)
-    d = s * SHEAR + a * ISO + b * NORMAL
-    o.set_populations(h + d[:, None, None] * act, g)
+    sx = np.broadcast_to(np.asarray(s, float), (nx,))
+    d = SHEAR[:, None, None] * sx[None, None, :] + (a * ISO + b * NORMAL)[:, None, None]
+    o.set_populations(h + d * act, g)
     return o
 
 
@@ -118,6 +124,62 @@ def test_wall_shear_is_the_tangential_traction(tau):
         ob = _channel_state(tau, s, a, b).observe_now()
         for k in ("wss_iris_mean", "wss_iris_max", "wss_cornea_mean", "wss_cornea_max"):
             assert ob[k] == pytest.approx(want, rel=1e-12), (a, b, k)
+
+
+def test_wall_shear_mean_and_maximum():
+    """With a different shear in every column, the mean and the maximum over a wall are
+    those of the per-node values (1 - 1/(2 tau)) 4 |s(x)|."""
+    tau = 0.9
+    s = np.array([1.0, 3.0, 2.0, 0.5]) * 1e-6
+    ob = _channel_state(tau, s, 2e-6, -1e-6).observe_now()
+    f = (1 - 1 / (2 * tau)) * 4
+    for w in ("iris", "cornea"):
+        assert ob[f"wss_{w}_mean"] == pytest.approx(f * np.mean(s), rel=1e-12)
+        assert ob[f"wss_{w}_max"] == pytest.approx(f * np.max(s), rel=1e-12)
+
+
+def test_max_speed_is_the_magnitude():
+    """A uniform flow of speed U at 30 degrees: the reported maximum speed is U."""
+    n, U = 8, 0.01
+    P = A.Params(nx=n, ny=n, periodic_x=1, periodic_y=1, check_interval=1000)
+    o = O.Oracle(P, np.full((n, n), A.encode(A.FLUID), np.uint8))
+    init_from_fields(o, P, P.p_ref, U * math.cos(math.pi / 6), U * math.sin(math.pi / 6), P.T_ref)
+    assert o.observe_now()["u_max"] == pytest.approx(U, rel=1e-12)
+
+
+def test_paper_scheme_initial_wall_populations():
+    """At t = 0 the paper's scheme gives the populations entering from Dirichlet walls the
+    extrapolation of the initial equilibrium: a node at rest beside a wall at T_w receives
+    w^T (T_w - T_ref) from it, whatever T_init (section 2.3)."""
+    nx, ny = 4, 8
+    mask = A.channel_mask(nx, ny, bottom_wall=A.WALL_IRIS, top_wall=A.WALL_CORNEA)
+    P = A.Params(nx=nx, ny=ny, periodic_x=1, check_interval=1000, T_ref=0.2, T_init=0.45, T_iris=0.9,
+                 T_cornea=0.1, bc_scheme=A.BC_PAPER)
+    g = O.Oracle(P, mask).populations()[1]
+    w = (1 - P.w0) / 4
+    assert np.allclose(g[2, 1, :], w * (P.T_iris - P.T_ref), rtol=0, atol=1e-15)
+    assert np.allclose(g[4, ny - 2, :], w * (P.T_cornea - P.T_ref), rtol=0, atol=1e-15)
+    assert np.allclose(g[2, 2:ny - 1, :], w * (P.T_init - P.T_ref), rtol=0, atol=1e-15)
+
+
+def test_interpolation_falls_back_without_a_node_behind():
+    """In a one-row channel every wall link with q < 1/2 has no fluid node behind it, so the
+    paper's scheme keeps the half-way bounce-back (section 2.3): with q = 0.3 on every wall
+    link it steps exactly as the link-wise scheme."""
+    nx, ny = 4, 3
+    mask = A.channel_mask(nx, ny)
+    walls = np.zeros(2 * nx, dtype=A.WALL_DTYPE)
+    for x in range(nx):
+        walls[x] = (nx + x, A.WALL_IRIS, 0.0, 1.0, [0.3] * 8)
+        walls[nx + x] = (nx + x, A.WALL_CORNEA, 0.0, -1.0, [0.3] * 8)
+    out = []
+    for bc in (A.BC_LINKWISE, A.BC_PAPER):
+        P = A.Params(nx=nx, ny=ny, periodic_x=1, check_interval=1000, gbeta=1e-4, gravity_angle=math.pi / 2,
+                     T_init=1.0, T0=0.5, bc_scheme=bc)
+        o = O.Oracle(P, mask, walls[:nx])
+        o.step(50)
+        out.append(o.populations()[0][:, 1, :])
+    assert np.array_equal(out[0], out[1])
 
 
 def test_iop_is_the_mean_over_the_chamber_fluid():
