@@ -124,6 +124,16 @@ M = [  # id, file, description, old, new
   "s->u_seep = seepage_speed(&s->P, s->obs.step > 0 ? s->obs.p_mean_fluid : s->P.p_init);",
   "s->u_seep = seepage_speed(&s->P, s->P.p_init);"),
  ("darcy_by_tau", C, "Darcy drag with nu replaced by tau", "double nuK = nu_of(P) / P->K;", "double nuK = P->tau_f / P->K;"),
+ ("periodic_wrap", C, "periodic wrap without the shift", "if (s->P.periodic_x) xx = (xx + s->nx) % s->nx;", "if (s->P.periodic_x) xx = xx % s->nx;"),
+ ("inlet_uy_index", C, "inlet wall velocity's y part along e_x", "double eu = ex[i] * P->u_in_x + ey[i] * P->u_in_y;", "double eu = ex[i] * P->u_in_x + ex[i] * P->u_in_y;"),
+ ("lumped_y", C, "lumped outlet flux along x only", "double eu = (ex[i] * ex[d] + ey[i] * ey[d]) * s->u_seep;", "double eu = (ex[i] * ex[d]) * s->u_seep;"),
+ ("outlet_T_dirichlet", C, "outlet treated as a Dirichlet thermal wall", "} else if ((c == OR_SOLID && wall != OR_WALL_BOX) || c == OR_INLET) {\n                    double Tw = (c == OR_INLET) ? P->T_inlet : wall_temperature(s, wall);\n                    *back = -gout", "} else if ((c == OR_SOLID && wall != OR_WALL_BOX) || c == OR_INLET || c == OR_OUTLET) {\n                    double Tw = (c == OR_INLET) ? P->T_inlet : wall_temperature(s, wall);\n                    *back = -gout"),
+ ("iop_pref", C, "mean pressure without p_ref", "o->p_mean_fluid = P->p_ref + (cnt > 0 ? sum_dp / cnt : 0.0);", "o->p_mean_fluid = (cnt > 0 ? sum_dp / cnt : 0.0);"),
+ ("darcy_in_fluid", C, "Darcy drag in fluid nodes instead of porous ones", "collide_node(s, s->cls[k] == OR_POROUS, h8, g5, h8s, g5s);", "collide_node(s, s->cls[k] == OR_FLUID, h8, g5, h8s, g5s);"),
+ ("back_one_sided", D, "backward one-sided difference sign", "    if dn:\n        return f[y, x] - f[y - dy, x - dx]", "    if dn:\n        return f[y - dy, x - dx] - f[y, x]"),
+ ("umax_active", D, "maximum speed over all active nodes", "float(np.max(np.hypot(ux, uy)[fluid]))", "float(np.nanmax(np.where(_active(mask), np.hypot(ux, uy), np.nan)))"),
+ ("argmax_last", D, "vortex centre at the last maximum", "imax = int(np.nanargmax(flat))      # first occurrence in y * nx + x order", "imax = int(len(flat) - 1 - np.nanargmax(flat[::-1]))"),
+ ("psi_active", D, "stream function summed over inactive nodes too", "np.cumsum(np.where(act, ux, 0.0), axis=0)", "np.cumsum(np.nan_to_num(ux), axis=0)"),
 ]
 
 

@@ -62,6 +62,26 @@ def test_uniform_flow():
     assert np.allclose(psi, U * np.cumsum(fluid, axis=0), rtol=1e-12)
 
 
+def test_fluid_only_definitions():
+    """u_max and the vortex measures count FLUID nodes only, and the stream function sums
+    active nodes only: a faster POROUS node does not set u_max, and values at inactive
+    nodes (here finite, as a caller might pass them) change nothing."""
+    U = 3e-5
+    mask, ii, jj = _disc()
+    fluid = (mask & 7) == A.FLUID
+    porous = mask.copy()
+    porous[20, 20] = A.encode(A.POROUS)
+    act = A.active(porous)
+    ux = np.where(act, U, 7.0)
+    uy = np.where(act, 0.0, -3.0)
+    ux[20, 20] = 5 * U
+    d = D.diagnose(ux, uy, porous)
+    assert d["u_max_fluid"] == pytest.approx(U, rel=1e-15)
+    psi = D.stream_function(ux, porous)
+    assert np.allclose(psi, np.cumsum(np.where(act, ux, 0.0), axis=0), rtol=1e-15, atol=0)
+    assert np.allclose(psi[:, 0], 0.0) and psi[-1, 20] == pytest.approx(U * (fluid[:, 20].sum() + 4), rel=1e-12)
+
+
 def _standing(dT):
     mask, walls, geo = A.eye_mask(96, 48, 45.0, R=40.0, pupil_gap=2)
     p = A.eye_params(96, 48, geo, u_in=0.0, Ra=0.0, Da=1e-3, phi_deg=90.0, check_interval=500)

@@ -218,27 +218,36 @@ def test_calibration_loop_reaches_closed_form_thickness():
     assert h == pytest.approx(h_star, rel=2e-8)
 
 
-def _lumped_duct(bc, U=1e-3, nx=24, ny=4, K_tm=0.05, h_tm=3.0, D=10):
-    """Duct periodic in y: INLET column (velocity U along x), lumped OUTLET column draining
-    along +x, no walls."""
+def _lumped_duct(bc, U=1e-3, nx=24, ny=4, K_tm=0.05, h_tm=3.0, D=10, along_y=False):
+    """Duct periodic across: INLET column (velocity U along x), lumped OUTLET column
+    draining along +x, no walls; or the same duct turned to run along +y."""
     m = np.full((ny, nx), A.encode(A.FLUID), np.uint8)
     m[:, 0] = A.encode(A.INLET)
     m[:, nx - 1] = A.encode(A.OUTLET, 0)
-    P = A.Params(nx=nx, ny=ny, tau_f=0.8, periodic_y=1, u_in_x=U, check_interval=D, bc_scheme=bc,
-                 outlet_mode=A.OUTLET_LUMPED, K_tm=K_tm, h_tm=h_tm, p_sc=1.0 / 3.0 - 2e-5, p_init=1.0 / 3.0)
+    kw = dict(periodic_y=1, u_in_x=U)
+    if along_y:
+        m = np.ascontiguousarray(m.T)
+        m[nx - 1, :] = A.encode(A.OUTLET, 1)
+        nx, ny = ny, nx
+        kw = dict(periodic_x=1, u_in_y=U)
+    P = A.Params(nx=nx, ny=ny, tau_f=0.8, check_interval=D, bc_scheme=bc, outlet_mode=A.OUTLET_LUMPED,
+                 K_tm=K_tm, h_tm=h_tm, p_sc=1.0 / 3.0 - 2e-5, p_init=1.0 / 3.0, **kw)
     return m, P
 
 
+@pytest.mark.parametrize("along_y", [False, True])
 @pytest.mark.parametrize("bc", [A.BC_LINKWISE, A.BC_PAPER])
-def test_lumped_duct_closed_form(bc):
+def test_lumped_duct_closed_form(bc, along_y):
     """Plug flow U into a duct drained by the lumped meshwork: the steady state is the
     uniform flow with u_s = U, so IOP - p_sc = mu h U / K exactly (eq. 4 over the meshwork),
-    with the link-wise moving wall and with the paper's extrapolation at the outlet."""
-    m, P = _lumped_duct(bc)
+    with the link-wise moving wall and with the paper's extrapolation at the outlet, for a
+    meshwork draining along x or along y."""
+    m, P = _lumped_duct(bc, along_y=along_y)
     o = O.Oracle(P, m).step(30000)
     ob = o.observables()
-    assert ob["p_mean_fluid"] - P.p_sc == pytest.approx(_nu(P) * P.h_tm * P.u_in_x / P.K_tm, rel=1e-12)
-    assert ob["u_seep"] == pytest.approx(P.u_in_x, rel=1e-12)
+    U = max(P.u_in_x, P.u_in_y)
+    assert ob["p_mean_fluid"] - P.p_sc == pytest.approx(_nu(P) * P.h_tm * U / P.K_tm, rel=1e-12)
+    assert ob["u_seep"] == pytest.approx(U, rel=1e-12)
     assert ob["q_out"] == pytest.approx(ob["q_in"], rel=1e-12)
 
 
