@@ -57,6 +57,60 @@ def test_lumped_parity_canal_pressure_apart(aq):
     s.close()
 
 
+def _duct(n=40, w=12):
+    """A walled duct along +x: INLET cells across its left end, OUTLET cells across its
+    right end, BOX walls along its sides."""
+    m = np.full((w, n), A.encode(A.SOLID), np.uint8)
+    m[1:w - 1, 1:n - 1] = A.encode(A.FLUID)
+    m[1:w - 1, 0] = A.encode(A.INLET)
+    m[1:w - 1, n - 1] = A.encode(A.OUTLET)
+    return m
+
+
+def _duct_mask(d):
+    """The duct turned by d quarter turns, with the OUTLET cells' wall bits set to the
+    outward direction (0 +x, 1 +y, 2 -x, 3 -y) of the side they landed on."""
+    m = np.ascontiguousarray(np.rot90(_duct(), k=d))
+    ny, nx = m.shape
+    out = (m & 7) == A.OUTLET
+    ys, xs = np.nonzero(out)
+    if np.all(xs == nx - 1):
+        bits = 0
+    elif np.all(ys == ny - 1):
+        bits = 1
+    elif np.all(xs == 0):
+        bits = 2
+    else:
+        bits = 3
+    m[out] = A.encode(A.OUTLET, bits)
+    return m, bits
+
+
+@pytest.mark.parametrize("bc", [A.BC_LINKWISE, A.BC_PAPER])
+@pytest.mark.parametrize("d", [0, 1, 2, 3])
+def test_lumped_outlet_every_direction(aq, d, bc):
+    """The lumped outlet drains along +x, -y, -x or +y (the OUTLET cells' wall bits): a
+    walled duct with the inlet flow along the same axis, 1000 steps, against the oracle to
+    1e-12, under the link-wise and the paper's schemes."""
+    m, bits = _duct_mask(d)
+    ny, nx = m.shape
+    ex, ey = [(1, 0), (0, 1), (-1, 0), (0, -1)][bits]
+    U = 2e-3
+    p = A.Params(nx=nx, ny=ny, tau_f=0.8, u_in_x=U * ex, u_in_y=U * ey, check_interval=50, bc_scheme=bc,
+                 outlet_mode=A.OUTLET_LUMPED, K_tm=0.05, h_tm=3.0, p_sc=1.0 / 3.0 - 2e-5, p_init=1.0 / 3.0 + 1e-4)
+    s = aq.Solver(p, m, A.no_walls())
+    s.step(1000)
+    o = O.Oracle(p, m).step(1000)
+    err = field_errors(s.fields(), o.fields(), m, p.T_ref)
+    announce(f"[lumped] duct draining along {bits} bc {bc}: {err}")
+    assert all(v <= FIELD_TOL for v in err.values()), err
+    gobs, oobs = s.observe(), o.observables()
+    assert oobs["q_out"] > 0
+    assert gobs["u_seep"] == pytest.approx(oobs["u_seep"], rel=1e-11)
+    assert gobs["q_out"] == pytest.approx(oobs["q_out"], rel=1e-11)
+    s.close()
+
+
 def _small(storage=A.F64):
     mask, walls, geo = A.eye_mask(96, 48, 45.0, R=40.0, pupil_gap=2, tm="lumped")
     p = A.eye_params(96, 48, geo, Ra=0.0, Da=1e-3, tm="lumped", storage=storage)
