@@ -86,23 +86,26 @@ def _duct_mask(d):
     return m, bits
 
 
+@pytest.mark.parametrize("mode", [A.OUTLET_LUMPED, A.OUTLET_PRESSURE])
 @pytest.mark.parametrize("bc", [A.BC_LINKWISE, A.BC_PAPER])
 @pytest.mark.parametrize("d", [0, 1, 2, 3])
-def test_lumped_outlet_every_direction(aq, d, bc):
-    """The lumped outlet drains along +x, -y, -x or +y (the OUTLET cells' wall bits): a
-    walled duct with the inlet flow along the same axis, 1000 steps, against the oracle to
-    1e-12, under the link-wise and the paper's schemes."""
+def test_outlet_every_direction(aq, d, bc, mode):
+    """The outlet drains along +x, -y, -x or +y: a walled duct with the inlet flow along the
+    same axis, the lumped meshwork (draining along the OUTLET cells' wall bits) or the
+    pressure outlet, 1000 steps, against the oracle to 1e-12, under the link-wise and the
+    paper's schemes."""
     m, bits = _duct_mask(d)
     ny, nx = m.shape
     ex, ey = [(1, 0), (0, 1), (-1, 0), (0, -1)][bits]
     U = 2e-3
     p = A.Params(nx=nx, ny=ny, tau_f=0.8, u_in_x=U * ex, u_in_y=U * ey, check_interval=50, bc_scheme=bc,
-                 outlet_mode=A.OUTLET_LUMPED, K_tm=0.05, h_tm=3.0, p_sc=1.0 / 3.0 - 2e-5, p_init=1.0 / 3.0 + 1e-4)
+                 outlet_mode=mode, K_tm=0.05, h_tm=3.0, p_sc=1.0 / 3.0 - 2e-5, p_init=1.0 / 3.0 + 1e-4,
+                 p_out=1.0 / 3.0 + 3e-5)
     s = aq.Solver(p, m, A.no_walls())
     s.step(1000)
     o = O.Oracle(p, m).step(1000)
     err = field_errors(s.fields(), o.fields(), m, p.T_ref)
-    announce(f"[lumped] duct draining along {bits} bc {bc}: {err}")
+    announce(f"[lumped] duct draining along {bits} bc {bc} outlet mode {mode}: {err}")
     assert all(v <= FIELD_TOL for v in err.values()), err
     gobs, oobs = s.observe(), o.observables()
     assert oobs["q_out"] > 0
