@@ -112,3 +112,35 @@ def test_full_box_conservation_8192(aq):
     assert abs(b["mass_thermal"] - a["mass_thermal"]) <= 1e-12 * abs(a["mass_thermal"])
     assert abs(b["mass_flow"] - a["mass_flow"]) <= 1e-8
     s.close()
+
+
+@pytest.mark.parametrize("storage,fused,tol", [(A.F32, False, 1e-4), (A.F32, True, 1e-4), (A.F16S, True, 1e-2)])
+def test_largest_lattice_far_corner(aq, storage, fused, tol):
+    """The largest lattice the single-precision storages accept (three padded population
+    planes within the 4 GiB that a 32-bit byte offset spans): 16384 columns and 21844 rows in
+    F32, 43690 in F16S.  The 192x96 eye sits in its far corner, where the offsets are
+    largest, with solid nodes everywhere else.  After 200 steps the corner holds what the
+    oracle computes for the eye alone: FP32 to 1e-4 of each field's largest value, single
+    and two-step launches, and F16S to 1e-2."""
+    p0, m0, w0, geo = A.config0()
+    elem = 4 if storage == A.F32 else 2
+    NX = 16384
+    NY = ((1 << 32) // elem - NX - 1 - 3 * 704) // (3 * NX)     # plane: NY * NX + 704 elements
+    ny, nx = m0.shape
+    y0, x0 = NY - ny, NX - nx
+    mask = np.full((NY, NX), A.encode(A.SOLID), np.uint8)
+    mask[y0:, x0:] = m0
+    walls = w0.copy()
+    walls["node"] = (w0["node"] // nx + y0) * NX + w0["node"] % nx + x0
+    p = A.Params(**{**p0.asdict(), "nx": NX, "ny": NY, "storage": storage})
+    announce(f"[edges] {NX}x{NY} storage={storage} fused={fused}: the eye in the far corner")
+    s = aq.Solver(p, mask, walls)
+    s.set_fusion(fused)
+    s.step(200)
+    g = [s.read_field(f)[y0:, x0:] for f in ("p", "ux", "uy", "T")]
+    s.close()
+    g[0] = g[0] - p.p_ref
+    o = O.Oracle(p0, m0, w0).step(200)
+    err = field_errors(g, o.fields(), m0, p0.T_ref)
+    announce(f"[edges] far corner errors {err}")
+    assert all(v <= tol for v in err.values()), err
