@@ -699,7 +699,9 @@ __device__ __forceinline__ void conserve_encode(const typename Traits<MODE>::R* 
         sum = i == 0 ? (Acc)d[0] : sum + (Acc)d[i];
     }
     const Acc r = target - sum;
-    if constexpr (N == 5) {
+    if constexpr (N == 5 && MODE == 2) {
+        // binary16: every link is encoded again with its share (one mixed-precision fma
+        // each, cheaper than selecting the links that take r)
         const L a0 = fabs(d[0]), a1 = fabs(d[1]), a2 = fabs(d[2]), a3 = fabs(d[3]), a4 = fabs(d[4]);
         const L mn = fmin(fmin(fmin(a0, a2), a4), fmin(a1, a3));
         const bool f0 = a0 == mn, f1 = a1 == mn, f2 = a2 == mn, f3 = a3 == mn, f4 = a4 == mn;
@@ -714,6 +716,27 @@ __device__ __forceinline__ void conserve_encode(const typename Traits<MODE>::R* 
         enc[2] = T::enc(fma(w2, r, (Acc)d[2]), sc);
         enc[3] = T::enc(fma(w3, r, (Acc)d[3]), sc);
         enc[4] = T::enc(fma(w4, r, (Acc)d[4]), sc);
+        return;
+    }
+    if constexpr (N == 5) {
+        // the storages with single-precision values and double sums encode again only the
+        // one or two links that take r (fewer registers live across the double arithmetic);
+        // a zero share would give every other link back its own encoding
+        const L a0 = fabs(d[0]), a1 = fabs(d[1]), a2 = fabs(d[2]), a3 = fabs(d[3]), a4 = fabs(d[4]);
+        const L mn = fmin(fmin(fmin(a0, a2), a4), fmin(a1, a3));
+        const bool f0 = a0 == mn, f1 = a1 == mn, f2 = a2 == mn, f3 = a3 == mn, f4 = a4 == mn;
+        const bool self = f0 || f2 || f4;
+        const bool s2 = !f0 && f2, s4 = !f0 && !f2 && f4;
+        Acc wa, wb;
+        pair_weights(!self && f1, !self && f3, in[1], in[3], wa, wb);
+        if (self) wa = Acc(1);
+        const L da = f0 ? d[0] : s2 ? d[2] : s4 ? d[4] : d[1];
+        const typename T::S ea = T::enc(fma(wa, r, (Acc)da), sc), eb = T::enc(fma(wb, r, (Acc)d[3]), sc);
+        enc[0] = f0 ? ea : enc[0];
+        enc[2] = s2 ? ea : enc[2];
+        enc[4] = s4 ? ea : enc[4];
+        enc[1] = self ? enc[1] : ea;
+        enc[3] = self ? enc[3] : eb;
         return;
     }
     if constexpr (MODE == 2) {
@@ -738,18 +761,20 @@ __device__ __forceinline__ void conserve_encode(const typename Traits<MODE>::R* 
 #pragma unroll
         for (int i = 0; i < 8; i++) enc[i] = T::enc(fma(w[i], r, (Acc)d[i]), sc);
     } else {
-        // the diagonals 5..8 (entries 4..7): the pair (5, 6) first, then (7, 8)
+        // the diagonals 5..8 (entries 4..7): the pair (5, 6) first, then (7, 8); only the
+        // pair that takes r is encoded again, as for the thermal links above
         const L a5 = fabs(d[4]), a6 = fabs(d[5]), a7 = fabs(d[6]), a8 = fabs(d[7]);
         const L mn = fmin(fmin(a5, a6), fmin(a7, a8));
         const bool f5 = a5 == mn, f6 = a6 == mn, f7 = a7 == mn, f8 = a8 == mn;
         const bool p56 = f5 || f6;
-        Acc w5, w6, w7, w8;
-        pair_weights(p56 && f5, p56 && f6, in[4], in[5], w5, w6);
-        pair_weights(!p56 && f7, !p56 && f8, in[6], in[7], w7, w8);
-        enc[4] = T::enc(fma(w5, r, (Acc)d[4]), sc);
-        enc[5] = T::enc(fma(w6, r, (Acc)d[5]), sc);
-        enc[6] = T::enc(fma(w7, r, (Acc)d[6]), sc);
-        enc[7] = T::enc(fma(w8, r, (Acc)d[7]), sc);
+        Acc wa, wb;
+        pair_weights(p56 ? f5 : f7, p56 ? f6 : f8, p56 ? in[4] : in[6], p56 ? in[5] : in[7], wa, wb);
+        const L da = p56 ? d[4] : d[6], db = p56 ? d[5] : d[7];
+        const typename T::S ea = T::enc(fma(wa, r, (Acc)da), sc), eb = T::enc(fma(wb, r, (Acc)db), sc);
+        enc[4] = p56 ? ea : enc[4];
+        enc[5] = p56 ? eb : enc[5];
+        enc[6] = p56 ? enc[6] : ea;
+        enc[7] = p56 ? enc[7] : eb;
     }
 }
 
