@@ -1391,7 +1391,9 @@ template <int MODE, bool NT, bool BC, int TY>
 __global__ __launch_bounds__((Fuse<MODE, TY>::THREADS), (Fuse<MODE, TY>::BLOCKS)) void step2_kernel(StepArgs a)
 {
     __shared__ typename Traits<MODE>::L lds[Fuse<MODE, TY>::WORDS];
-    process_tile2<MODE, NT, true, BC, TY>(a, a.tiles[tile_of_block(a)], lds);
+    // all of a thread's loads first, except in the paper-scheme variants of the single-
+    // precision storages, which would spill (as in batch_step2_kernel)
+    process_tile2<MODE, NT, !(MODE != 0 && BC), BC, TY>(a, a.tiles[tile_of_block(a)], lds);
 }
 
 // a.tile_y selects the tile rows: 4 (F32 and F16S) or 8
