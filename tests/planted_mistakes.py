@@ -134,6 +134,15 @@ M = [  # id, file, description, old, new
  ("umax_active", D, "maximum speed over all active nodes", "float(np.max(np.hypot(ux, uy)[fluid]))", "float(np.nanmax(np.where(_active(mask), np.hypot(ux, uy), np.nan)))"),
  ("argmax_last", D, "vortex centre at the last maximum", "imax = int(np.nanargmax(flat))      # first occurrence in y * nx + x order", "imax = int(len(flat) - 1 - np.nanargmax(flat[::-1]))"),
  ("psi_active", D, "stream function summed over inactive nodes too", "np.cumsum(np.where(act, ux, 0.0), axis=0)", "np.cumsum(np.nan_to_num(ux), axis=0)"),
+ ("bz_hi_idx", C, "interpolation for q >= 1/2 reads the outgoing population again",
+  "*back = hout / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * s->hs[(size_t)(ib - 1) * n + k];",
+  "*back = hout / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * s->hs[(size_t)(i - 1) * n + k];"),
+ ("mass_flow_half", C, "flow mass over half the links", "for (int i = 0; i < 8; i++) mf += h8[i];", "for (int i = 0; i < 4; i++) mf += h8[i];"),
+ ("wss_ids", C, "wall shear of cornea and iris merged", "        int id = s->wall_id[w];\n        if (id < 1 || id > 2) continue;", "        int id = 1;\n        if (id < 1 || id > 2) continue;"),
+ ("nonfinite", C, "non-finite count ignores the temperature", "if (!isfinite(m.dp) || !isfinite(m.ux) || !isfinite(m.uy) || !isfinite(m.T)) bad++;", "if (!isfinite(m.dp) || !isfinite(m.ux) || !isfinite(m.uy)) bad++;"),
+ ("ext_T_wall_u", C, "thermal extrapolation at walls with the inlet velocity", "double uxb = c == OR_INLET ? P->u_in_x : 0.0, uyb = c == OR_INLET ? P->u_in_y : 0.0;\n                    moments ms = post_moments(s, k);                        /* extrapolation */", "double uxb = P->u_in_x, uyb = P->u_in_y;\n                    moments ms = post_moments(s, k);                        /* extrapolation */"),
+ ("buoy_gbeta", C, "buoyancy without g beta on x", "double Bx = P->gbeta * (m.T - P->T0) * s->gx_hat;", "double Bx = (m.T - P->T0) * s->gx_hat;"),
+ ("thermal_rest_w", C, "thermal weights with the rest weight on the axis links", "static double w_heat(const or_params* P, int i) { return i == 0 ? P->w0 : (1.0 - P->w0) / 4.0; }", "static double w_heat(const or_params* P, int i) { return i == 0 ? (1.0 - P->w0) / 4.0 : P->w0; }"),
 ]
 
 

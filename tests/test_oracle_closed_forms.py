@@ -334,11 +334,12 @@ def test_thermal_walls_place_the_temperature(scheme, ends):
     """Conduction between Dirichlet walls (T = 1 below, 0 above): the extrapolation of the
     paper's scheme imposes the wall temperature on the solid rows themselves (T linear from
     y = 0 to y = ny - 1), the link-wise anti-bounce-back half a link inside them; both
-    profiles are exactly linear."""
+    profiles are exactly linear.  The walls are at rest whatever the inlet velocity (set
+    here although the channel has no inlet)."""
     nx, ny = 4, 12
     mask = A.channel_mask(nx, ny, bottom_wall=A.WALL_IRIS, top_wall=A.WALL_CORNEA)
     P = A.Params(nx=nx, ny=ny, tau_t=0.9, periodic_x=1, check_interval=1000, T_iris=1.0, T_cornea=0.0,
-                 bc_scheme=scheme)
+                 bc_scheme=scheme, u_in_x=0.01, u_in_y=0.02)
     o = O.Oracle(P, mask)
     o.step(40000)
     T = o.fields()[3][1:ny - 1, 1]

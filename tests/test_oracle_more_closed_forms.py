@@ -147,6 +147,20 @@ def test_max_speed_is_the_magnitude():
     assert o.observe_now()["u_max"] == pytest.approx(U, rel=1e-12)
 
 
+def test_non_finite_count_covers_every_field():
+    """The count of non-finite nodes reported at a check step covers the flow and the
+    thermal populations alike: one NaN in either makes that node count."""
+    n = 8
+    P = A.Params(nx=n, ny=n, periodic_x=1, periodic_y=1, check_interval=1000)
+    o = O.Oracle(P, np.full((n, n), A.encode(A.FLUID), np.uint8))
+    init_from_fields(o, P, P.p_ref, 0.0, 0.0, P.T_ref)
+    h, g = o.populations()
+    g[3, 2, 5] = np.nan
+    h[6, 4, 1] = np.inf
+    o.set_populations(h, g)
+    assert o.observe_now()["n_nonfinite"] == 2
+
+
 def test_paper_scheme_initial_wall_populations():
     """At t = 0 the paper's scheme gives the populations entering from Dirichlet walls the
     extrapolation of the initial equilibrium: a node at rest beside a wall at T_w receives
