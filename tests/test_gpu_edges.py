@@ -150,9 +150,8 @@ def test_largest_lattice_far_corner(aq, storage, fused, tol):
 def test_non_finite_nodes_counted_like_the_oracle(aq, storage):
     """A NaN planted in one thermal population and an infinity in one flow population, far
     apart, spread through the lattice step by step.  After one check interval of 10 steps
-    (387 of the 1,886 active nodes reached) the count of
-    non-finite nodes equals the oracle's (every node whose pressure, velocity or temperature
-    is not finite)."""
+    (387 of the 1,886 active nodes reached) the count of non-finite nodes equals the
+    oracle's (every node whose pressure, velocity or temperature is not finite)."""
     p0, mask, walls, geo = A.config0()
     p0.check_interval = 10
     p = A.Params(**{**p0.asdict(), "storage": storage})
