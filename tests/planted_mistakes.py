@@ -143,6 +143,10 @@ M = [  # id, file, description, old, new
  ("ext_T_wall_u", C, "thermal extrapolation at walls with the inlet velocity", "double uxb = c == OR_INLET ? P->u_in_x : 0.0, uyb = c == OR_INLET ? P->u_in_y : 0.0;\n                    moments ms = post_moments(s, k);                        /* extrapolation */", "double uxb = P->u_in_x, uyb = P->u_in_y;\n                    moments ms = post_moments(s, k);                        /* extrapolation */"),
  ("buoy_gbeta", C, "buoyancy without g beta on x", "double Bx = P->gbeta * (m.T - P->T0) * s->gx_hat;", "double Bx = (m.T - P->T0) * s->gx_hat;"),
  ("thermal_rest_w", C, "thermal weights with the rest weight on the axis links", "static double w_heat(const or_params* P, int i) { return i == 0 ? P->w0 : (1.0 - P->w0) / 4.0; }", "static double w_heat(const or_params* P, int i) { return i == 0 ? (1.0 - P->w0) / 4.0 : P->w0; }"),
+ ("uprev_stale", C, "velocity residual against a reference never updated", "        s->u_prev_x[k] = m.ux;\n        s->u_prev_y[k] = m.uy;\n        s->T_prev[k] = m.T;\n    }\n\n    /* wall shear", "        s->T_prev[k] = m.T;\n    }\n\n    /* wall shear"),
+ ("Tprev_stale", C, "thermal residual against a reference never updated", "        s->u_prev_y[k] = m.uy;\n        s->T_prev[k] = m.T;\n    }\n\n    /* wall shear", "        s->u_prev_y[k] = m.uy;\n    }\n\n    /* wall shear"),
+ ("ext_q_in", C, "inflow of the extrapolated inlet with the wrong sign", "if (c == OR_INLET) q_in += *back - hout;\n                    else q_out += hout - *back;", "if (c == OR_INLET) q_in += hout - *back;\n                    else q_out += hout - *back;"),
+ ("wss_normal_sign", C, "wall shear removes the normal part with the wrong sign", "double tn = tx * nx_ + ty * ny_;", "double tn = -(tx * nx_ + ty * ny_);"),
 ]
 
 
